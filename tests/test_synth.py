@@ -1,0 +1,87 @@
+"""Input generators: determinism, canonical ordering, tiling, leaf-count ranges."""
+import numpy as np
+
+from paper_2307_15333_amd import synth
+
+
+def _check_canonical(s):
+    # leaves tile the root cube
+    vol = ((s.bbox_size / 2.0 ** s.leaf_depth.astype(np.float64)) ** 3).sum()
+    assert abs(vol - s.bbox_size ** 3) < 1e-9
+    # leaves in Morton (DFS) order at the finest lattice
+    D = int(s.leaf_depth.max())
+    key = synth.morton3(s.leaf_ijk << (D - s.leaf_depth.astype(np.int64))[:, None])
+    assert np.all(np.diff(key.astype(np.float64)) > 0) or s.n_leaves == 1
+    # child array: every leaf referenced once, every non-root internal node once,
+    # children of internal nodes have larger indices (pre-order)
+    if s.n_internal:
+        c = s.child.reshape(-1)
+        leaves = -1 - c[c < 0]
+        assert np.array_equal(np.sort(leaves), np.arange(s.n_leaves))
+        ints = c[c >= 0]
+        assert np.array_equal(np.sort(ints), np.arange(1, s.n_internal))
+        parent = np.repeat(np.arange(s.n_internal), 8).reshape(-1, 8)
+        assert np.all(s.child[s.child >= 0] > parent[s.child >= 0])
+        # DFS leaf order: walking the tree in octant order visits leaves 0,1,2,...
+        order = []
+
+        def walk(n):
+            for oc in range(8):
+                e = int(s.child[n, oc])
+                if e >= 0:
+                    walk(e)
+                else:
+                    order.append(-1 - e)
+
+        import sys
+        sys.setrecursionlimit(10000)
+        walk(0)
+        assert order == list(range(s.n_leaves))
+
+
+def test_config1_scene_shape_and_determinism():
+    a = synth.config1_scene()
+    b = synth.config1_scene()
+    assert a.n_leaves == b.n_leaves and np.array_equal(a.child, b.child)
+    assert np.array_equal(a.sh32, b.sh32) and np.array_equal(a.sigma64, b.sigma64)
+    assert a.degree == 2 and a.sh32.shape == (a.n_leaves, 3, 9)
+    assert 6000 <= a.n_leaves <= 12000
+    assert a.leaf_depth.max() == 5
+    _check_canonical(a)
+    # value distributions
+    assert 0.0 <= a.sh32[:, :, 0].min() and a.sh32[:, :, 0].max() <= 1.0
+    assert abs(a.sh32[:, :, 1:].std() - 0.1) < 0.005
+    assert a.sigma64.max() <= 50.0 and a.sigma64.min() >= 0.0
+
+
+def test_random_and_uniform_trees_are_canonical():
+    for seed in range(4):
+        _check_canonical(synth.random_tree_scene(4, 1, seed))
+    _check_canonical(synth.uniform_scene(3, 0, 1.0))
+
+
+def test_tree_from_cells_matches_level_construction():
+    s = synth.config1_scene()
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(s.n_leaves)
+    child, order = synth.tree_from_cells(s.leaf_depth[perm], s.leaf_ijk[perm], 5)
+    assert np.array_equal(child, s.child)
+    assert np.array_equal(perm[order], np.arange(s.n_leaves))
+
+
+def test_cameras_look_at_origin():
+    cams = synth.config2_cameras()
+    assert cams.shape == (8,)
+    for c in cams:
+        M = c["c2w"].reshape(3, 4).astype(np.float64)
+        R, t = M[:, :3], M[:, 3]
+        assert abs(np.linalg.norm(t) - 4.0) < 1e-5
+        np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-6)
+        np.testing.assert_allclose(R[:, 2], -t / np.linalg.norm(t), atol=1e-6)
+
+
+def test_pixel_batch_is_a_sample_without_replacement():
+    cam, pix = synth.pixel_batch(100, 64, 64, 1 << 12, seed=3)
+    flat = cam.astype(np.int64) * 4096 + pix
+    assert np.unique(flat).shape[0] == flat.shape[0]
+    assert cam.max() < 100 and pix.max() < 4096
