@@ -178,15 +178,20 @@ static void seg_push(seglist *s, int32_t leaf, double delta) {
     s->n++;
 }
 
-/* Interval of t for which o + t d lies in the closed box [lo, lo+size]^3,
- * intersected with [ta, tb].  Returns 0 if empty (a >= b). */
-static int clip_box(const double lo[3], double size, const double o[3], const double d[3],
+/* Interval of t for which o + t d lies in the box [lo, lo+size]^3, intersected
+ * with [ta, tb].  Returns 0 if empty (a >= b).  Leaves tile the root, so every
+ * point belongs to exactly one cell: cells are half-open, [lo, lo+size) per
+ * axis, except that the root's upper faces belong to the last cell.  This
+ * matters only for a ray that lies in a cell plane (d[k] == 0); for any other
+ * ray the half-open and closed boxes give the same interval. */
+static int clip_box(const orc_tree *T, const double lo[3], double size, const double o[3], const double d[3],
                     double ta, double tb, double *a_out, double *b_out) {
     double a = ta, b = tb;
     for (int k = 0; k < 3; ++k) {
         double p0 = lo[k], p1 = lo[k] + size;
         if (d[k] == 0.0) {
-            if (o[k] < p0 || o[k] > p1) return 0;
+            int top = (p1 == T->bmin[k] + T->size);
+            if (o[k] < p0 || o[k] > p1 || (o[k] == p1 && !top)) return 0;
             continue;
         }
         double t0 = (p0 - o[k]) / d[k];
@@ -214,7 +219,7 @@ static void descend(const orc_tree *T, int32_t entry, const double lo[3], double
         double clo[3] = {lo[0] + ((oc & 1) ? half : 0.0), lo[1] + ((oc & 2) ? half : 0.0),
                          lo[2] + ((oc & 4) ? half : 0.0)};
         double a, b;
-        if (clip_box(clo, half, o, d, ta, tb, &a, &b)) {
+        if (clip_box(T, clo, half, o, d, ta, tb, &a, &b)) {
             ca[oc] = a;
             cb[oc] = b;
             /* insertion sort by entry t; equal entries keep octant order */
@@ -239,7 +244,7 @@ static void ray_segments(const orc_tree *T, const double o[3], const double d_in
     double d[3] = {d_in[0] / n, d_in[1] / n, d_in[2] / n};
     double a, b;
     out->n = 0;
-    if (!clip_box(T->bmin, T->size, o, d, 0.0, INFINITY, &a, &b)) return;
+    if (!clip_box(T, T->bmin, T->size, o, d, 0.0, INFINITY, &a, &b)) return;
     int32_t root = T->n_internal > 0 ? 0 : -1; /* a root that is a leaf is leaf 0 */
     descend(T, root, T->bmin, T->size, o, d, a, b, out);
 }

@@ -201,6 +201,29 @@ def test_traversal_matches_dense_grid_dda(depth):
         np.testing.assert_allclose(delta[keep], exp_len, atol=1e-12)
 
 
+def test_ray_in_a_cell_plane_belongs_to_the_upper_cell():
+    """Leaves tile the root: a ray lying in the plane between two cells crosses
+    one of them (half-open cells, the upper one), never both; a ray on the
+    root's upper face belongs to the last cell."""
+    U = synth.uniform_scene(1, 0, 1.0)
+    sig = np.arange(1.0, 9.0)           # distinct densities per octant
+    T = O.OracleTree(U.child, sig, U.sh64, 0)
+    d = np.array([1.0, 0.0, 0.0])
+    cases = [((-3.0, 0.0, 0.0), [6, 7]),      # y = z = 0: upper y, upper z octants (6, 7)
+             ((-3.0, -0.5, 0.0), [4, 5]),     # z = 0 only
+             ((-3.0, 1.0, -1.0), [2, 3]),     # y on the root's upper face, z on the lower face
+             ((-3.0, 1.0, 1.0), [6, 7])]      # the upper root edge
+    for o, want in cases:
+        leaf, delta = O.ray_segments(T, np.array(o), d)
+        assert list(leaf) == want, (o, leaf)
+        np.testing.assert_allclose(delta, [1.0, 1.0], atol=1e-15)
+    # a diagonal ray through cell corners: only positive-length segments, total = chord
+    o = np.array([-3.0, -3.0, -3.0])
+    dd = np.ones(3) / np.sqrt(3.0)
+    leaf, delta = O.ray_segments(O.OracleTree.from_scene(synth.uniform_scene(3, 0, 1.0)), o, dd)
+    assert len(leaf) == 8 and abs(delta.sum() - 2 * np.sqrt(3.0)) < 1e-12
+
+
 def test_segments_sum_to_chord_and_match_ray_marching():
     s = synth.random_tree_scene(5, 0, seed=4)
     T = O.OracleTree.from_scene(s)
