@@ -1,0 +1,273 @@
+/*
+ * dot.h -- C ABI of the MI355X (gfx950) octree volume renderer of the
+ * Dynamic PlenOctree method (DOT, arXiv 2307.15333).
+ *
+ * The library renders, differentiates and refines a sparse octree whose
+ * leaves hold a density sigma and real spherical-harmonic (SH) colour
+ * coefficients.  Every call is plain C: host or device pointers and sizes.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ *  - Return value: DOT_OK (0) or a negative DOT_E* code; the message of the
+ *    last failure on the calling thread is returned by dot_last_error().
+ *    No C++ exception crosses this interface.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  All
+ *    device work is enqueued asynchronously on it unless stated otherwise.
+ *  - Ownership: buffers passed in by the caller stay the caller's; the
+ *    library never frees them.  Tree planes are owned by the dot_tree_t
+ *    handle and released by dot_free.
+ *  - Device pointers passed in must be valid for the stated size; kernels do
+ *    not re-validate individual values (trees are validated at dot_build).
+ *
+ * Octree (canonical host form, accepted by dot_build)
+ * ---------------------------------------------------
+ *  Root cube [bbox_min, bbox_min + bbox_size]^3.  child is int32
+ *  [n_internal][8]; octant o = x | y<<1 | z<<2 (bit set = upper half of that
+ *  axis); an entry >= 0 is an internal node, an entry < 0 is leaf (-1-entry).
+ *  Node 0 is the root; a tree whose root is a leaf has n_internal = 0 and
+ *  n_leaves = 1.  Internal nodes are numbered in depth-first pre-order and
+ *  leaves in depth-first order (children visited in octant order), so leaves
+ *  are in Morton order.  Leaf depth <= DOT_MAX_DEPTH.
+ *  Leaf payload (Sec. 3, "Preliminaries"; Sec. 4.1 stores 16 SH coefficients
+ *  per channel plus a density): sigma[L] and sh[L][3][K] with
+ *  K = (sh_degree+1)^2, real orthonormal SH with the Condon-Shortley phase,
+ *  index k = l^2 + l + m.
+ */
+#ifndef DOT_H_
+#define DOT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DOT_OK = 0,
+    DOT_EINVAL = -1,       /* malformed argument or tree */
+    DOT_ENOMEM = -2,       /* allocation failed */
+    DOT_EHIP = -3,         /* HIP runtime error (message from hipGetErrorString) */
+    DOT_EUNSUPPORTED = -4  /* valid request this build does not implement */
+};
+
+/* leaf storage precision of the sigma and SH planes; arithmetic is FP32 */
+enum { DOT_F32 = 0, DOT_F16 = 1, DOT_BF16 = 2 };
+
+/* how rays are given */
+enum {
+    DOT_RAYS_CAMERAS = 0,  /* every pixel of n_cams cameras of width x height */
+    DOT_RAYS_PIXELS = 1,   /* an explicit list of (camera, pixel) pairs */
+    DOT_RAYS_EXPLICIT = 2  /* explicit origins and directions */
+};
+
+/* per-leaf training signal aggregate over rays (Sec. 3.1) */
+enum { DOT_SIGNAL_MAX = 0, DOT_SIGNAL_SUM = 1 };
+
+#define DOT_MAX_DEPTH 16
+
+typedef struct dot_tree *dot_tree_t;
+
+/* Device-memory allocator used for every allocation a tree makes (its planes,
+ * refinement scratch, upload staging).  NULL = hipMalloc/hipFree.  alloc
+ * returns NULL on failure (the call then fails with DOT_ENOMEM). */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} dot_allocator;
+
+typedef struct {
+    int64_t n_internal;
+    int64_t n_leaves;
+    int32_t sh_degree;      /* 0..3 */
+    int32_t reserved;
+    const int32_t *child;   /* host [n_internal][8] */
+    const float *sigma;     /* host [n_leaves] raw density (pre-activation) */
+    const float *sh;        /* host [n_leaves][3][K] */
+    float bbox_min[3];
+    float bbox_size;
+} dot_tree_desc;
+
+/* Pinhole camera: c2w is the row-major 3x4 [R | t] camera-to-world matrix
+ * (camera axes x right, y down, z forward).  The ray of pixel (u, v) has
+ * origin t and direction normalize(R ((u+0.5-cx)/fx, (v+0.5-cy)/fy, 1)). */
+typedef struct {
+    float c2w[12];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} dot_camera;
+
+/* Ray batch.  Ray order: CAMERAS = camera-major, then row-major pixels
+ * (ray id = cam * H * W + v * W + u); PIXELS / EXPLICIT = list order. */
+typedef struct {
+    int32_t kind;               /* DOT_RAYS_* */
+    int32_t n_cams;             /* CAMERAS, PIXELS */
+    const dot_camera *cams;     /* DEVICE [n_cams] (CAMERAS, PIXELS) */
+    int32_t width, height;      /* CAMERAS: image size shared by all cameras */
+    int64_t n_rays;             /* PIXELS, EXPLICIT */
+    const int32_t *cam_idx;     /* DEVICE [n_rays] (PIXELS) */
+    const int32_t *pix_idx;     /* DEVICE [n_rays] (PIXELS): v * width + u */
+    const float *origins;       /* DEVICE [n_rays][3] (EXPLICIT) */
+    const float *dirs;          /* DEVICE [n_rays][3] (EXPLICIT), normalised inside */
+} dot_rays;
+
+typedef struct {
+    float bg[3];            /* background colour added with the remaining transmittance */
+    float t_stop;           /* stop a ray once exp(-S) < t_stop; 0 disables */
+    int32_t signal_mode;    /* DOT_SIGNAL_MAX or DOT_SIGNAL_SUM */
+    int32_t reserved;
+} dot_render_opts;
+
+typedef struct {
+    int64_t n_internal, n_leaves;
+    int32_t sh_degree, storage;   /* storage: DOT_F32/F16/BF16 */
+    int32_t max_depth;            /* deepest leaf */
+    int32_t sh_stride;            /* elements per leaf row of the SH plane (>= 3K, padded) */
+    void *child;                  /* device int32 [n_internal][8] */
+    void *sigma;                  /* device [n_leaves] in the storage type */
+    void *sh;                     /* device [n_leaves][sh_stride]; row = [3][K] then padding */
+    void *leaf_depth;             /* device uint8 [n_leaves] */
+    float bbox_min[3], bbox_size;
+} dot_tree_info_t;
+
+/*
+ * dot_build -- validate a canonical host tree and upload it.
+ *  storage: DOT_F32 copies the planes; DOT_F16 / DOT_BF16 round each value to
+ *  nearest-even on the device.  The host arrays are read during the call only.
+ *  Errors: DOT_EINVAL for an out-of-range child entry, a node or leaf
+ *  referenced twice or never, a child numbered before its parent (cycle or
+ *  non pre-order), leaves not in DFS order, depth > DOT_MAX_DEPTH, a bad
+ *  degree, storage or box; DOT_ENOMEM / DOT_EHIP from the device.
+ *  The call synchronises `stream` before returning.
+ */
+int dot_build(const dot_tree_desc *desc, int32_t storage, const dot_allocator *alloc, void *stream,
+              dot_tree_t *out);
+
+/* dot_free -- release a tree and all device memory it owns (NULL is a no-op). */
+int dot_free(dot_tree_t tree);
+
+/* dot_tree_info -- sizes and device pointers of the tree's planes.  Pointers
+ * stay valid until the next dot_refine or dot_free on the tree. */
+int dot_tree_info(dot_tree_t tree, dot_tree_info_t *out);
+
+/*
+ * dot_render -- forward volume rendering (Sec. 3 "Preliminaries", Eq. 1-2).
+ *  For each ray: clip to the root cube, visit the leaves it crosses front to
+ *  back with exact segment lengths delta_i, and composite
+ *      C = sum_i T_i (1 - exp(-sigma^_i delta_i)) c_i + T_end bg,
+ *      T_i = exp(-sum_{j<i} sigma^_j delta_j),  sigma^ = max(sigma, 0),
+ *      c_i = sigmoid(sum_k sh_i[ch][k] Y_k(d))  per channel.
+ *  A ray stops after the segment that drives exp(-S) below t_stop.
+ *  rgb_out:   DEVICE float [n][3], required.
+ *  nseg_out:  DEVICE int32 [n] or NULL: segments visited (delta > 0), the
+ *             count dot_render_backward replays.
+ *  signal_inout: DEVICE float [n_leaves] or NULL: fused training signal
+ *             (Sec. 3.1, Alg. 1 "Q, pred <- render(rays)"): per leaf the max
+ *             (DOT_SIGNAL_MAX) or sum (DOT_SIGNAL_SUM) over rays of the ray
+ *             weight w_i = T_i (1 - exp(-sigma^_i delta_i)), accumulated into
+ *             the existing values (MAX expects non-negative initial values).
+ *  Errors: DOT_EINVAL on NULL tree/rays/rgb_out or an inconsistent ray batch.
+ */
+int dot_render(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts, float *rgb_out,
+               int32_t *nseg_out, float *signal_inout, void *stream);
+
+/*
+ * dot_accumulate_signal -- the signal pass alone (same traversal and weights as
+ * dot_render, no colour output): signal_inout DEVICE float [n_leaves], required.
+ */
+int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
+                          float *signal_inout, void *stream);
+
+/*
+ * dot_render_backward -- adjoint of dot_render for a loss L(C) (Sec. 3: the
+ *  renderer is fully differentiable and optimised under an MSE loss).  Each ray
+ *  is re-traversed for nseg[r] segments; with P_i = sum_{j<=i} w_j c_j,
+ *      dL/dsigma_i += [sigma_i > 0] delta_i sum_ch g_ch (T_{i+1} c_ch - (C_ch - P_i,ch))
+ *      dL/dsh_i[ch][k] += g_ch w_i c_ch (1 - c_ch) Y_k(d)
+ *  where g = grad_rgb[r] = dL/dC and C = rgb_fwd[r] (the forward output).
+ *  rgb_fwd, grad_rgb: DEVICE float [n][3]; nseg: DEVICE int32 [n] from dot_render
+ *  with the same tree, rays and opts.  grad_sigma: DEVICE float [n_leaves],
+ *  grad_sh: DEVICE float [n_leaves][3][K] (dense); both accumulated into (+=),
+ *  the caller zeroes them.  Accumulation uses FP32 atomics, so the last bits
+ *  depend on scheduling.
+ */
+int dot_render_backward(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
+                        const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,
+                        float *grad_sigma, float *grad_sh, void *stream);
+
+typedef struct {
+    float prune_tau;     /* prune selection: signal <= tau (prune_le) or < tau */
+    float sample_frac;   /* k = floor(sample_frac * n_leaves) leaves to subdivide */
+    int32_t prune_le;
+    int32_t max_depth;   /* only leaves shallower than this are subdivided */
+    int32_t recursive;   /* 1: repeat merging up the hierarchy (merged signal = max of children) */
+    int32_t reserved;
+} dot_refine_params;
+
+typedef struct {
+    int64_t leaves_before, leaves_after, internal_after;
+    int64_t merged;      /* internal nodes turned into leaves */
+    int64_t subdivided;  /* leaves turned into internal nodes */
+} dot_refine_stats;
+
+/*
+ * dot_refine -- one refinement of the tree from a per-leaf signal (Sec. 3.2,
+ *  Alg. 1: pruning then sampling from the same signal).
+ *   prune (Eq. 3): an internal node whose 8 children are all leaves and all
+ *     selected becomes a leaf holding the mean of the children's raw sigma and
+ *     SH, rounded once to the storage type;
+ *   sample (Eq. 4): among leaves not selected for pruning and shallower than
+ *     max_depth, the k with the largest signal (ties: lower leaf index first)
+ *     become internal nodes whose 8 children copy the parent's values.
+ *  The new tree is canonical (DFS numbering), so its topology is unique.
+ *  signal: DEVICE float [n_leaves] (not modified).  The tree's planes are
+ *  replaced; earlier dot_tree_info pointers become invalid.  stats may be NULL.
+ *  Synchronises `stream` once to size the new planes.
+ */
+int dot_refine(dot_tree_t tree, const float *signal, const dot_refine_params *params,
+               dot_refine_stats *stats, void *stream);
+
+typedef struct {
+    float lr_sigma, lr_sh;     /* learning rates (the paper's RMSProp uses 0.1 / 0.01) */
+    float beta1, beta2, eps;
+    int32_t step;              /* 1-based step number for bias correction */
+} dot_adam_params;
+
+/*
+ * dot_adam_step -- one Adam update of the tree's sigma and SH planes in place
+ *  (FP32 storage only).  grad_*: DEVICE float, dense layouts as in
+ *  dot_render_backward; m_* / v_*: DEVICE float moments of the same shapes,
+ *  zero-initialised by the caller before step 1.
+ *  Errors: DOT_EUNSUPPORTED for FP16/BF16 storage.
+ */
+int dot_adam_step(dot_tree_t tree, const float *grad_sigma, const float *grad_sh, float *m_sigma,
+                  float *v_sigma, float *m_sh, float *v_sh, const dot_adam_params *params,
+                  void *stream);
+
+/*
+ * dot_export -- copy the tree back to host memory in canonical form:
+ *  child [n_internal][8], sigma [L] and sh [L][3][K] decoded to FP32,
+ *  leaf_depth [L].  Any pointer may be NULL.  Synchronous.
+ */
+int dot_export(dot_tree_t tree, int32_t *child, float *sigma, float *sh, uint8_t *leaf_depth,
+               void *stream);
+
+/*
+ * dot_render_stats -- work counters of one forward pass over `rays` (no colour
+ *  output): counts[0] rays, [1] segments composited (delta > 0), [2] segments
+ *  whose SH coefficients were fetched (sigma^ delta > 0), [3] child-array
+ *  reads during traversal.  Synchronous.  Used to turn kernel time into
+ *  algorithmic bytes per second.
+ */
+int dot_render_stats(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
+                     int64_t counts[4], void *stream);
+
+/* dot_last_error -- message of the last failure on this thread ("" if none). */
+const char *dot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOT_H_ */

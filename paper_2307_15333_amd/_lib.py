@@ -1,0 +1,128 @@
+"""ctypes declarations of the libdot C ABI (include/dot.h).
+
+Loading fails loudly if the HIP library has not been built: there is no CPU
+fallback anywhere in this package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdot.so")
+
+DOT_OK, DOT_EINVAL, DOT_ENOMEM, DOT_EHIP, DOT_EUNSUPPORTED = 0, -1, -2, -3, -4
+DOT_F32, DOT_F16, DOT_BF16 = 0, 1, 2
+DOT_RAYS_CAMERAS, DOT_RAYS_PIXELS, DOT_RAYS_EXPLICIT = 0, 1, 2
+DOT_SIGNAL_MAX, DOT_SIGNAL_SUM = 0, 1
+DOT_MAX_DEPTH = 16
+
+STORAGE = {"f32": DOT_F32, "f16": DOT_F16, "bf16": DOT_BF16}
+STORAGE_NAME = {v: k for k, v in STORAGE.items()}
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class dot_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class dot_tree_desc(C.Structure):
+    _fields_ = [("n_internal", C.c_int64), ("n_leaves", C.c_int64), ("sh_degree", C.c_int32),
+                ("reserved", C.c_int32), ("child", C.c_void_p), ("sigma", C.c_void_p),
+                ("sh", C.c_void_p), ("bbox_min", C.c_float * 3), ("bbox_size", C.c_float)]
+
+
+class dot_camera(C.Structure):
+    _fields_ = [("c2w", C.c_float * 12), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
+                ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class dot_rays(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_cams", C.c_int32), ("cams", C.c_void_p),
+                ("width", C.c_int32), ("height", C.c_int32), ("n_rays", C.c_int64),
+                ("cam_idx", C.c_void_p), ("pix_idx", C.c_void_p), ("origins", C.c_void_p),
+                ("dirs", C.c_void_p)]
+
+
+class dot_render_opts(C.Structure):
+    _fields_ = [("bg", C.c_float * 3), ("t_stop", C.c_float), ("signal_mode", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class dot_tree_info_t(C.Structure):
+    _fields_ = [("n_internal", C.c_int64), ("n_leaves", C.c_int64), ("sh_degree", C.c_int32),
+                ("storage", C.c_int32), ("max_depth", C.c_int32), ("sh_stride", C.c_int32),
+                ("child", C.c_void_p), ("sigma", C.c_void_p), ("sh", C.c_void_p),
+                ("leaf_depth", C.c_void_p), ("bbox_min", C.c_float * 3), ("bbox_size", C.c_float)]
+
+
+class dot_refine_params(C.Structure):
+    _fields_ = [("prune_tau", C.c_float), ("sample_frac", C.c_float), ("prune_le", C.c_int32),
+                ("max_depth", C.c_int32), ("recursive", C.c_int32), ("reserved", C.c_int32)]
+
+
+class dot_refine_stats(C.Structure):
+    _fields_ = [("leaves_before", C.c_int64), ("leaves_after", C.c_int64),
+                ("internal_after", C.c_int64), ("merged", C.c_int64), ("subdivided", C.c_int64)]
+
+
+class dot_adam_params(C.Structure):
+    _fields_ = [("lr_sigma", C.c_float), ("lr_sh", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int32)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/dot.h
+SIGNATURES = {
+    "dot_build": (C.c_int, [C.POINTER(dot_tree_desc), C.c_int32, C.POINTER(dot_allocator), C.c_void_p,
+                            C.POINTER(C.c_void_p)]),
+    "dot_free": (C.c_int, [C.c_void_p]),
+    "dot_tree_info": (C.c_int, [C.c_void_p, C.POINTER(dot_tree_info_t)]),
+    "dot_render": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts), C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dot_accumulate_signal": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
+                                        C.c_void_p, C.c_void_p]),
+    "dot_render_backward": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
+    "dot_refine": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(dot_refine_params),
+                             C.POINTER(dot_refine_stats), C.c_void_p]),
+    "dot_adam_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.POINTER(dot_adam_params), C.c_void_p]),
+    "dot_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dot_render_stats": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
+                                   C.POINTER(C.c_int64), C.c_void_p]),
+    "dot_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class DotError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdot error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libdot.so (built in-tree by paper_2307_15333_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_15333_amd.build` "
+                              "(there is no CPU fallback)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(rc):
+    if rc != DOT_OK:
+        msg = load().dot_last_error().decode(errors="replace")
+        raise DotError(rc, msg)
+    return rc

@@ -1,0 +1,273 @@
+"""Python face of libdot: trees, ray batches and the autograd function.
+
+Argument marshalling only: every step of rendering, differentiation,
+refinement and optimisation runs in the HIP kernels behind the C ABI.  PyTorch
+provides device memory (through the allocator hook) and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_NP_CAMERA = np.dtype([("c2w", np.float32, (12,)), ("fx", np.float32), ("fy", np.float32),
+                       ("cx", np.float32), ("cy", np.float32), ("width", np.int32), ("height", np.int32)])
+assert _NP_CAMERA.itemsize == C.sizeof(L.dot_camera)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class TorchAllocator:
+    """Device allocations for the library served by torch's caching allocator."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.blocks = {}
+        self._cb_alloc = L.ALLOC_FN(self._alloc)
+        self._cb_free = L.FREE_FN(self._free)
+        self.struct = L.dot_allocator(self._cb_alloc, self._cb_free, None)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.blocks[p] = t
+        return p
+
+    def _free(self, p, ctx):
+        self.blocks.pop(p, None)
+
+    def tensor(self, ptr, nbytes):
+        base = self.blocks[ptr]
+        return base[:nbytes]
+
+
+class Rays:
+    """A ray batch: all pixels of cameras, a (camera, pixel) list, or explicit rays."""
+
+    def __init__(self, struct, keep, n_rays, shape=None):
+        self.struct = struct
+        self._keep = keep
+        self.n_rays = int(n_rays)
+        self.shape = shape
+
+    @staticmethod
+    def _cams_tensor(cams, device):
+        cams = np.ascontiguousarray(np.asarray(cams).astype(_NP_CAMERA, copy=False))
+        raw = torch.from_numpy(cams.view(np.uint8).copy()).to(device)
+        return cams, raw
+
+    @classmethod
+    def cameras(cls, cams, device="cuda"):
+        cams, raw = cls._cams_tensor(cams, device)
+        W, H = int(cams[0]["width"]), int(cams[0]["height"])
+        if not all(int(c["width"]) == W and int(c["height"]) == H for c in cams):
+            raise ValueError("all cameras of a CAMERAS batch must share width and height")
+        s = L.dot_rays(kind=L.DOT_RAYS_CAMERAS, n_cams=len(cams), cams=raw.data_ptr(), width=W, height=H)
+        return cls(s, [raw], len(cams) * W * H, (len(cams), H, W))
+
+    @classmethod
+    def pixels(cls, cams, cam_idx, pix_idx, device="cuda"):
+        cams, raw = cls._cams_tensor(cams, device)
+        ci = torch.as_tensor(np.asarray(cam_idx, np.int32)).to(device)
+        pi = torch.as_tensor(np.asarray(pix_idx, np.int32)).to(device)
+        n = ci.shape[0]
+        s = L.dot_rays(kind=L.DOT_RAYS_PIXELS, n_cams=len(cams), cams=raw.data_ptr(), n_rays=n,
+                       cam_idx=ci.data_ptr(), pix_idx=pi.data_ptr())
+        return cls(s, [raw, ci, pi], n)
+
+    @classmethod
+    def pixels_device(cls, cams_raw, n_cams, cam_idx, pix_idx):
+        """(camera, pixel) list from tensors already on the device."""
+        n = cam_idx.shape[0]
+        s = L.dot_rays(kind=L.DOT_RAYS_PIXELS, n_cams=n_cams, cams=cams_raw.data_ptr(), n_rays=n,
+                       cam_idx=cam_idx.data_ptr(), pix_idx=pix_idx.data_ptr())
+        return cls(s, [cams_raw, cam_idx, pix_idx], n)
+
+    @classmethod
+    def explicit(cls, origins, dirs, device="cuda"):
+        o = torch.as_tensor(np.asarray(origins, np.float32)).to(device).contiguous()
+        d = torch.as_tensor(np.asarray(dirs, np.float32)).to(device).contiguous()
+        n = o.shape[0]
+        s = L.dot_rays(kind=L.DOT_RAYS_EXPLICIT, n_rays=n, origins=o.data_ptr(), dirs=d.data_ptr())
+        return cls(s, [o, d], n)
+
+
+def render_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal_mode="max"):
+    bg = np.broadcast_to(np.asarray(bg, np.float32), (3,))
+    o = L.dot_render_opts()
+    for a in range(3):
+        o.bg[a] = float(bg[a])
+    o.t_stop = float(t_stop)
+    o.signal_mode = {"max": L.DOT_SIGNAL_MAX, "sum": L.DOT_SIGNAL_SUM}[signal_mode]
+    return o
+
+
+class Octree:
+    """A device-resident octree (handle of the C ABI)."""
+
+    def __init__(self, child, sigma, sh, degree, storage="f32", bbox_min=(-1.0, -1.0, -1.0),
+                 bbox_size=2.0, device="cuda"):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.alloc = TorchAllocator(self.device)
+        child = np.ascontiguousarray(child, np.int32).reshape(-1, 8)
+        sigma = np.ascontiguousarray(sigma, np.float32)
+        K = (degree + 1) ** 2
+        sh = np.ascontiguousarray(sh, np.float32).reshape(-1, 3, K)
+        desc = L.dot_tree_desc(n_internal=child.shape[0], n_leaves=sigma.shape[0], sh_degree=degree,
+                               child=child.ctypes.data, sigma=sigma.ctypes.data, sh=sh.ctypes.data,
+                               bbox_size=float(bbox_size))
+        for a in range(3):
+            desc.bbox_min[a] = float(bbox_min[a])
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dot_build(C.byref(desc), L.STORAGE[storage], C.byref(self.alloc.struct),
+                                       _stream(), C.byref(h)))
+        self.handle = h
+        self.degree = int(degree)
+        self.K = K
+
+    @classmethod
+    def from_scene(cls, scene, storage="f32", device="cuda"):
+        return cls(scene.child, scene.sigma, scene.sh, scene.degree, storage, scene.bbox_min,
+                   scene.bbox_size, device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.check(self.lib.dot_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- introspection ----
+    def info(self):
+        i = L.dot_tree_info_t()
+        L.check(self.lib.dot_tree_info(self.handle, C.byref(i)))
+        return i
+
+    @property
+    def n_leaves(self):
+        return int(self.info().n_leaves)
+
+    @property
+    def n_internal(self):
+        return int(self.info().n_internal)
+
+    @property
+    def storage(self):
+        return L.STORAGE_NAME[int(self.info().storage)]
+
+    def plane_views(self):
+        """(sigma [L], sh [L,3,K]) torch views aliasing the device planes."""
+        i = self.info()
+        Ln = int(i.n_leaves)
+        es = 4 if i.storage == L.DOT_F32 else 2
+        dt = {L.DOT_F32: torch.float32, L.DOT_F16: torch.float16, L.DOT_BF16: torch.bfloat16}[int(i.storage)]
+        sig = self.alloc.tensor(i.sigma, Ln * es).view(dt)
+        sh = self.alloc.tensor(i.sh, Ln * int(i.sh_stride) * es).view(dt).view(Ln, int(i.sh_stride))
+        sh = sh[:, :3 * self.K].unflatten(1, (3, self.K))
+        return sig, sh
+
+    # ---- the C ABI calls ----
+    def render(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, nseg=False, signal=None, signal_mode="max"):
+        rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device=self.device)
+        ns = torch.empty(rays.n_rays, dtype=torch.int32, device=self.device) if nseg else None
+        op = render_opts(bg, t_stop, signal_mode)
+        L.check(self.lib.dot_render(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb), _ptr(ns),
+                                    _ptr(signal), _stream()))
+        return (rgb, ns) if nseg else rgb
+
+    def accumulate_signal(self, rays, signal, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal_mode="max"):
+        op = render_opts(bg, t_stop, signal_mode)
+        L.check(self.lib.dot_accumulate_signal(self.handle, C.byref(rays.struct), C.byref(op), _ptr(signal),
+                                               _stream()))
+        return signal
+
+    def backward(self, rays, rgb, nseg, grad_rgb, grad_sigma, grad_sh, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
+        op = render_opts(bg, t_stop)
+        L.check(self.lib.dot_render_backward(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
+                                             _ptr(nseg), _ptr(grad_rgb), _ptr(grad_sigma), _ptr(grad_sh),
+                                             _stream()))
+
+    def render_stats(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
+        op = render_opts(bg, t_stop)
+        out = (C.c_int64 * 4)()
+        L.check(self.lib.dot_render_stats(self.handle, C.byref(rays.struct), C.byref(op), out, _stream()))
+        return dict(rays=out[0], segments=out[1], sh_fetches=out[2], child_reads=out[3])
+
+    def refine(self, signal, prune_tau=1e-3, sample_frac=0.05, max_depth=10, prune_le=True,
+               recursive=False):
+        p = L.dot_refine_params(prune_tau=float(prune_tau), sample_frac=float(sample_frac),
+                                prune_le=int(bool(prune_le)), max_depth=int(max_depth),
+                                recursive=int(bool(recursive)))
+        st = L.dot_refine_stats()
+        L.check(self.lib.dot_refine(self.handle, _ptr(signal), C.byref(p), C.byref(st), _stream()))
+        return dict(leaves_before=st.leaves_before, leaves_after=st.leaves_after,
+                    internal_after=st.internal_after, merged=st.merged, subdivided=st.subdivided)
+
+    def adam_step(self, grad_sigma, grad_sh, state, step, lr_sigma=0.1, lr_sh=0.01, beta1=0.9,
+                  beta2=0.999, eps=1e-8):
+        p = L.dot_adam_params(lr_sigma=lr_sigma, lr_sh=lr_sh, beta1=beta1, beta2=beta2, eps=eps, step=int(step))
+        L.check(self.lib.dot_adam_step(self.handle, _ptr(grad_sigma), _ptr(grad_sh), _ptr(state["m_sigma"]),
+                                       _ptr(state["v_sigma"]), _ptr(state["m_sh"]), _ptr(state["v_sh"]),
+                                       C.byref(p), _stream()))
+
+    def adam_state(self):
+        Ln = self.n_leaves
+        z = lambda *s: torch.zeros(s, dtype=torch.float32, device=self.device)
+        return dict(m_sigma=z(Ln), v_sigma=z(Ln), m_sh=z(Ln, 3, self.K), v_sh=z(Ln, 3, self.K))
+
+    def export(self):
+        i = self.info()
+        I, Ln = int(i.n_internal), int(i.n_leaves)
+        child = np.empty((I, 8), np.int32)
+        sigma = np.empty(Ln, np.float32)
+        sh = np.empty((Ln, 3, self.K), np.float32)
+        depth = np.empty(Ln, np.uint8)
+        L.check(self.lib.dot_export(self.handle, child.ctypes.data if I else None, sigma.ctypes.data,
+                                    sh.ctypes.data, depth.ctypes.data, _stream()))
+        return dict(child=child, sigma=sigma, sh=sh, depth=depth)
+
+
+class DotRender(torch.autograd.Function):
+    """C = render(sigma, sh; rays) with the hand-written adjoint as backward.
+
+    ``sigma``/``sh`` are the tree's plane views (see Octree.plane_views); the
+    gradients returned are dense FP32 [L] and [L,3,K]."""
+
+    @staticmethod
+    def forward(ctx, sigma, sh, tree, rays, bg, t_stop):
+        rgb, nseg = tree.render(rays, bg=bg, t_stop=t_stop, nseg=True)
+        ctx.save_for_backward(rgb, nseg)
+        ctx.tree, ctx.rays, ctx.bg, ctx.t_stop = tree, rays, bg, t_stop
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        rgb, nseg = ctx.saved_tensors
+        tree = ctx.tree
+        Ln = tree.n_leaves
+        gs = torch.zeros(Ln, dtype=torch.float32, device=rgb.device)
+        gh = torch.zeros((Ln, 3, tree.K), dtype=torch.float32, device=rgb.device)
+        tree.backward(ctx.rays, rgb, nseg, grad_rgb.contiguous().float(), gs, gh, bg=ctx.bg, t_stop=ctx.t_stop)
+        return gs, gh, None, None, None, None
+
+
+def render_autograd(tree, sigma, sh, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
+    return DotRender.apply(sigma, sh, tree, rays, bg, t_stop)

@@ -1,0 +1,450 @@
+// C ABI of libdot: argument validation, tree upload/export, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dot_internal.h"
+
+namespace dot {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return DOT_EHIP;
+}
+
+void* Alloc::get(size_t bytes) const {
+    if (bytes == 0) bytes = 16;
+    if (custom) return a.alloc(bytes, a.ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void Alloc::put(void* p) const {
+    if (!p) return;
+    if (custom)
+        a.free(p, a.ctx);
+    else
+        (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
+// host-side validation of the canonical tree; fills leaf depths
+// ---------------------------------------------------------------------------
+static int validate_tree(const dot_tree_desc& d, std::vector<uint8_t>& depth, int& max_depth) {
+    if (d.n_leaves < 1) return fail(DOT_EINVAL, "dot_build: n_leaves must be >= 1");
+    if (d.n_internal < 0) return fail(DOT_EINVAL, "dot_build: n_internal must be >= 0");
+    if (d.n_leaves > (int64_t)INT32_MAX || d.n_internal > (int64_t)INT32_MAX / 8)
+        return fail(DOT_EINVAL, "dot_build: tree too large for 32-bit node indices");
+    if (d.sh_degree < 0 || d.sh_degree > 3) return fail(DOT_EINVAL, "dot_build: sh_degree must be in 0..3");
+    if (!(d.bbox_size > 0.f) || !std::isfinite(d.bbox_size))
+        return fail(DOT_EINVAL, "dot_build: bbox_size must be positive and finite");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d.bbox_min[a])) return fail(DOT_EINVAL, "dot_build: bbox_min must be finite");
+    if (!d.sigma || !d.sh) return fail(DOT_EINVAL, "dot_build: sigma and sh are required");
+    depth.assign((size_t)d.n_leaves, 0);
+    max_depth = 0;
+    if (d.n_internal == 0) {
+        if (d.n_leaves != 1) return fail(DOT_EINVAL, "dot_build: a tree with no internal node has exactly one leaf");
+        return DOT_OK;
+    }
+    if (!d.child) return fail(DOT_EINVAL, "dot_build: child is required when n_internal > 0");
+    struct Frame {
+        int64_t node;
+        int depth, oct;
+    };
+    std::vector<Frame> st;
+    st.push_back({0, 0, 0});
+    int64_t next_int = 1, next_leaf = 0;
+    while (!st.empty()) {
+        Frame& f = st.back();
+        if (f.oct == 8) {
+            st.pop_back();
+            continue;
+        }
+        int64_t e = d.child[f.node * 8 + f.oct];
+        int oct = f.oct++;
+        int cd = f.depth + 1;
+        if (cd > DOT_MAX_DEPTH)
+            return fail(DOT_EINVAL, "dot_build: tree deeper than DOT_MAX_DEPTH (16)");
+        if (e >= 0) {
+            if (e >= d.n_internal)
+                return fail(DOT_EINVAL, "dot_build: child[" + std::to_string(f.node) + "][" + std::to_string(oct) +
+                                            "] = " + std::to_string(e) + " is out of range");
+            if (e != next_int)
+                return fail(DOT_EINVAL, "dot_build: internal node " + std::to_string(e) +
+                                            " is referenced twice or not in depth-first pre-order (expected " +
+                                            std::to_string(next_int) + ")");
+            ++next_int;
+            st.push_back({e, cd, 0});
+        } else {
+            int64_t l = -1 - e;
+            if (l >= d.n_leaves)
+                return fail(DOT_EINVAL, "dot_build: leaf id " + std::to_string(l) + " is out of range");
+            if (l != next_leaf)
+                return fail(DOT_EINVAL, "dot_build: leaf " + std::to_string(l) +
+                                            " is referenced twice or leaves are not in depth-first order (expected " +
+                                            std::to_string(next_leaf) + ")");
+            depth[(size_t)l] = (uint8_t)cd;
+            if (cd > max_depth) max_depth = cd;
+            ++next_leaf;
+        }
+    }
+    if (next_int != d.n_internal)
+        return fail(DOT_EINVAL, "dot_build: " + std::to_string(d.n_internal - next_int) +
+                                    " internal nodes are unreachable from the root");
+    if (next_leaf != d.n_leaves)
+        return fail(DOT_EINVAL, "dot_build: " + std::to_string(d.n_leaves - next_leaf) +
+                                    " leaves are unreachable from the root");
+    return DOT_OK;
+}
+
+// Copy a host FP32 matrix [rows][cols] into a device plane of the storage type
+// with row stride `stride`, through a bounded staging buffer.
+static int upload_plane(const Alloc& al, int storage, const float* host, void* dst, int64_t rows, int cols,
+                        int stride, hipStream_t s) {
+    const int64_t max_rows = std::max<int64_t>(1, (64ll << 20) / ((int64_t)cols * 4));
+    int64_t chunk = std::min(rows, max_rows);
+    float* stage = static_cast<float*>(al.get((size_t)chunk * cols * 4));
+    if (!stage) return fail(DOT_ENOMEM, "dot_build: staging allocation failed");
+    const int es = storage_bytes(storage);
+    int rc = DOT_OK;
+    for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+        int64_t n = std::min(chunk, rows - r0);
+        hipError_t e = hipMemcpyAsync(stage, host + r0 * cols, (size_t)n * cols * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_encode_planes(storage, stage, static_cast<char*>(dst) + (size_t)r0 * stride * es, n, cols,
+                                     stride, s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "dot_build: upload");
+            break;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (rc == DOT_OK && e != hipSuccess) rc = hip_fail(e, "dot_build: synchronise");
+    al.put(stage);
+    return rc;
+}
+
+static int download_plane(const Alloc& al, int storage, const void* src, float* host, int64_t rows, int cols,
+                          int stride, hipStream_t s) {
+    const int64_t max_rows = std::max<int64_t>(1, (64ll << 20) / ((int64_t)cols * 4));
+    int64_t chunk = std::min(rows, max_rows);
+    float* stage = static_cast<float*>(al.get((size_t)chunk * cols * 4));
+    if (!stage) return fail(DOT_ENOMEM, "dot_export: staging allocation failed");
+    const int es = storage_bytes(storage);
+    int rc = DOT_OK;
+    for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+        int64_t n = std::min(chunk, rows - r0);
+        hipError_t e = launch_decode_planes(storage, static_cast<const char*>(src) + (size_t)r0 * stride * es, stage,
+                                            n, cols, stride, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host + r0 * cols, stage, (size_t)n * cols * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "dot_export: download");
+            break;
+        }
+    }
+    al.put(stage);
+    return rc;
+}
+
+static void release(dot_tree* t) {
+    t->alloc.put(t->child);
+    t->alloc.put(t->sigma);
+    t->alloc.put(t->sh);
+    t->alloc.put(t->leaf_depth);
+    t->child = nullptr;
+    t->sigma = nullptr;
+    t->sh = nullptr;
+    t->leaf_depth = nullptr;
+}
+
+static int make_batch(const dot_rays* r, RayBatch& rb, const char* who) {
+    if (!r) return fail(DOT_EINVAL, std::string(who) + ": rays is NULL");
+    std::memset(&rb, 0, sizeof(rb));
+    rb.kind = r->kind;
+    rb.n_cams = r->n_cams;
+    rb.cams = r->cams;
+    rb.width = r->width;
+    rb.height = r->height;
+    rb.n_rays = r->n_rays;
+    rb.cam_idx = r->cam_idx;
+    rb.pix_idx = r->pix_idx;
+    rb.origins = r->origins;
+    rb.dirs = r->dirs;
+    if (r->kind == DOT_RAYS_CAMERAS) {
+        if (r->n_cams < 0) return fail(DOT_EINVAL, std::string(who) + ": n_cams < 0");
+        if (r->n_cams > 0 && (r->width <= 0 || r->height <= 0))
+            return fail(DOT_EINVAL, std::string(who) + ": width and height must be positive");
+        if (r->n_cams > 0 && !r->cams) return fail(DOT_EINVAL, std::string(who) + ": cams is NULL");
+        int64_t tiles = r->n_cams > 0 ? (int64_t)r->n_cams * ((r->width + 7) / 8) * ((r->height + 7) / 8) : 0;
+        rb.n_tiles = tiles;
+        rb.n_rays = r->n_cams > 0 ? (int64_t)r->n_cams * r->width * r->height : 0;
+    } else if (r->kind == DOT_RAYS_PIXELS || r->kind == DOT_RAYS_EXPLICIT) {
+        if (r->n_rays < 0) return fail(DOT_EINVAL, std::string(who) + ": n_rays < 0");
+        if (r->n_rays > 0) {
+            if (r->kind == DOT_RAYS_PIXELS && (!r->cams || !r->cam_idx || !r->pix_idx || r->n_cams <= 0))
+                return fail(DOT_EINVAL, std::string(who) + ": PIXELS rays need cams, cam_idx and pix_idx");
+            if (r->kind == DOT_RAYS_EXPLICIT && (!r->origins || !r->dirs))
+                return fail(DOT_EINVAL, std::string(who) + ": EXPLICIT rays need origins and dirs");
+        }
+        rb.n_tiles = (r->n_rays + 63) / 64;
+    } else {
+        return fail(DOT_EINVAL, std::string(who) + ": unknown ray kind " + std::to_string(r->kind));
+    }
+    if ((rb.n_tiles + 3) / 4 > (int64_t)INT32_MAX)
+        return fail(DOT_EINVAL, std::string(who) + ": too many rays for one launch");
+    return DOT_OK;
+}
+
+static int fill_opts(const dot_render_opts* o, float bg[3], float& thr, const char* who) {
+    if (!o) {
+        bg[0] = bg[1] = bg[2] = 1.f;
+        thr = -std::log(1e-4f);
+        return DOT_OK;
+    }
+    if (!(o->t_stop >= 0.f && o->t_stop < 1.f))
+        return fail(DOT_EINVAL, std::string(who) + ": t_stop must be in [0, 1)");
+    if (o->signal_mode != DOT_SIGNAL_MAX && o->signal_mode != DOT_SIGNAL_SUM)
+        return fail(DOT_EINVAL, std::string(who) + ": unknown signal_mode");
+    for (int a = 0; a < 3; ++a) bg[a] = o->bg[a];
+    thr = o->t_stop > 0.f ? -std::log(o->t_stop) : __builtin_huge_valf();
+    return DOT_OK;
+}
+
+}  // namespace dot
+
+using namespace dot;
+
+extern "C" {
+
+const char* dot_last_error(void) { return g_err.c_str(); }
+
+int dot_build(const dot_tree_desc* desc, int32_t storage, const dot_allocator* alloc, void* stream,
+              dot_tree_t* out) {
+    if (!out) return fail(DOT_EINVAL, "dot_build: out is NULL");
+    *out = nullptr;
+    if (!desc) return fail(DOT_EINVAL, "dot_build: desc is NULL");
+    if (storage != DOT_F32 && storage != DOT_F16 && storage != DOT_BF16)
+        return fail(DOT_EINVAL, "dot_build: unknown storage type " + std::to_string(storage));
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(DOT_EINVAL, "dot_build: allocator needs both alloc and free");
+    std::vector<uint8_t> depth;
+    int max_depth = 0;
+    int rc = validate_tree(*desc, depth, max_depth);
+    if (rc) return rc;
+
+    dot_tree* t = new (std::nothrow) dot_tree();
+    if (!t) return fail(DOT_ENOMEM, "dot_build: out of host memory");
+    if (alloc) {
+        t->alloc.a = *alloc;
+        t->alloc.custom = true;
+    }
+    t->n_internal = desc->n_internal;
+    t->n_leaves = desc->n_leaves;
+    t->degree = desc->sh_degree;
+    t->storage = storage;
+    t->max_depth = max_depth;
+    t->sh_stride = sh_stride_for(desc->sh_degree, storage);
+    for (int a = 0; a < 3; ++a) t->bmin[a] = desc->bbox_min[a];
+    t->size = desc->bbox_size;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int es = storage_bytes(storage);
+    const int nv = 3 * (t->degree + 1) * (t->degree + 1);
+    t->child = static_cast<int32_t*>(t->alloc.get((size_t)std::max<int64_t>(t->n_internal, 1) * 32));
+    t->sigma = t->alloc.get((size_t)t->n_leaves * es);
+    t->sh = t->alloc.get((size_t)t->n_leaves * t->sh_stride * es);
+    t->leaf_depth = static_cast<uint8_t*>(t->alloc.get((size_t)t->n_leaves));
+    if (!t->child || !t->sigma || !t->sh || !t->leaf_depth) {
+        release(t);
+        delete t;
+        return fail(DOT_ENOMEM, "dot_build: device allocation failed");
+    }
+    hipError_t e = hipSuccess;
+    if (t->n_internal > 0)
+        e = hipMemcpyAsync(t->child, desc->child, (size_t)t->n_internal * 32, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t->leaf_depth, depth.data(), (size_t)t->n_leaves, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "dot_build: upload");
+    } else {
+        rc = upload_plane(t->alloc, storage, desc->sigma, t->sigma, t->n_leaves, 1, 1, s);
+        if (!rc) rc = upload_plane(t->alloc, storage, desc->sh, t->sh, t->n_leaves, nv, t->sh_stride, s);
+    }
+    if (rc) {
+        release(t);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return DOT_OK;
+}
+
+int dot_free(dot_tree_t t) {
+    if (!t) return DOT_OK;
+    release(t);
+    delete t;
+    return DOT_OK;
+}
+
+int dot_tree_info(dot_tree_t t, dot_tree_info_t* out) {
+    if (!t || !out) return fail(DOT_EINVAL, "dot_tree_info: NULL argument");
+    out->n_internal = t->n_internal;
+    out->n_leaves = t->n_leaves;
+    out->sh_degree = t->degree;
+    out->storage = t->storage;
+    out->max_depth = t->max_depth;
+    out->sh_stride = t->sh_stride;
+    out->child = t->child;
+    out->sigma = t->sigma;
+    out->sh = t->sh;
+    out->leaf_depth = t->leaf_depth;
+    for (int a = 0; a < 3; ++a) out->bbox_min[a] = t->bmin[a];
+    out->bbox_size = t->size;
+    return DOT_OK;
+}
+
+int dot_render(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, float* rgb_out, int32_t* nseg_out,
+               float* signal_inout, void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_render: tree is NULL");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_render");
+    if (rc) return rc;
+    if (!rgb_out && rb.n_rays > 0) return fail(DOT_EINVAL, "dot_render: rgb_out is NULL");
+    FwdArgs a{};
+    rc = fill_opts(opts, a.bg, a.thr, "dot_render");
+    if (rc) return rc;
+    a.rgb = rgb_out;
+    a.nseg = nseg_out;
+    a.signal = signal_inout;
+    a.signal_mode = opts ? opts->signal_mode : DOT_SIGNAL_MAX;
+    hipError_t e = launch_render_fwd(*t, rb, a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_render: launch");
+    return DOT_OK;
+}
+
+int dot_accumulate_signal(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, float* signal_inout,
+                          void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_accumulate_signal: tree is NULL");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_accumulate_signal");
+    if (rc) return rc;
+    if (!signal_inout && t->n_leaves > 0) return fail(DOT_EINVAL, "dot_accumulate_signal: signal is NULL");
+    FwdArgs a{};
+    rc = fill_opts(opts, a.bg, a.thr, "dot_accumulate_signal");
+    if (rc) return rc;
+    a.signal = signal_inout;
+    a.signal_mode = opts ? opts->signal_mode : DOT_SIGNAL_MAX;
+    hipError_t e = launch_render_fwd(*t, rb, a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_accumulate_signal: launch");
+    return DOT_OK;
+}
+
+int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, const float* rgb_fwd,
+                        const int32_t* nseg, const float* grad_rgb, float* grad_sigma, float* grad_sh,
+                        void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_render_backward: tree is NULL");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_render_backward");
+    if (rc) return rc;
+    if (rb.n_rays > 0 && (!rgb_fwd || !nseg || !grad_rgb || !grad_sigma || !grad_sh))
+        return fail(DOT_EINVAL, "dot_render_backward: rgb_fwd, nseg, grad_rgb, grad_sigma and grad_sh are required");
+    BwdArgs a{};
+    float bg[3];
+    rc = fill_opts(opts, bg, a.thr, "dot_render_backward");
+    if (rc) return rc;
+    a.rgb_fwd = rgb_fwd;
+    a.nseg = nseg;
+    a.grad_rgb = grad_rgb;
+    a.grad_sigma = grad_sigma;
+    a.grad_sh = grad_sh;
+    hipError_t e = launch_render_bwd(*t, rb, a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_render_backward: launch");
+    return DOT_OK;
+}
+
+int dot_render_stats(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, int64_t counts[4],
+                     void* stream) {
+    if (!t || !counts) return fail(DOT_EINVAL, "dot_render_stats: NULL argument");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_render_stats");
+    if (rc) return rc;
+    FwdArgs a{};
+    rc = fill_opts(opts, a.bg, a.thr, "dot_render_stats");
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long* dev = static_cast<unsigned long long*>(t->alloc.get(4 * sizeof(unsigned long long)));
+    if (!dev) return fail(DOT_ENOMEM, "dot_render_stats: allocation failed");
+    unsigned long long host[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(dev, host, sizeof(host), hipMemcpyHostToDevice, s);
+    a.stats = dev;
+    if (e == hipSuccess) e = launch_render_fwd(*t, rb, a, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    t->alloc.put(dev);
+    if (e != hipSuccess) return hip_fail(e, "dot_render_stats");
+    for (int i = 0; i < 4; ++i) counts[i] = (int64_t)host[i];
+    return DOT_OK;
+}
+
+int dot_adam_step(dot_tree_t t, const float* grad_sigma, const float* grad_sh, float* m_sigma, float* v_sigma,
+                  float* m_sh, float* v_sh, const dot_adam_params* p, void* stream) {
+    if (!t || !p) return fail(DOT_EINVAL, "dot_adam_step: NULL argument");
+    if (t->storage != DOT_F32) return fail(DOT_EUNSUPPORTED, "dot_adam_step: only FP32 leaf storage is trainable");
+    if (!grad_sigma || !grad_sh || !m_sigma || !v_sigma || !m_sh || !v_sh)
+        return fail(DOT_EINVAL, "dot_adam_step: gradient and moment buffers are required");
+    if (p->step < 1) return fail(DOT_EINVAL, "dot_adam_step: step must be >= 1");
+    hipError_t e = launch_adam(*t, grad_sigma, grad_sh, m_sigma, v_sigma, m_sh, v_sh, *p,
+                               static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_adam_step: launch");
+    return DOT_OK;
+}
+
+int dot_export(dot_tree_t t, int32_t* child, float* sigma, float* sh, uint8_t* leaf_depth, void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_export: tree is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (child && t->n_internal > 0)
+        e = hipMemcpyAsync(child, t->child, (size_t)t->n_internal * 32, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && leaf_depth)
+        e = hipMemcpyAsync(leaf_depth, t->leaf_depth, (size_t)t->n_leaves, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "dot_export");
+    int nv = 3 * (t->degree + 1) * (t->degree + 1);
+    int rc = DOT_OK;
+    if (sigma) rc = download_plane(t->alloc, t->storage, t->sigma, sigma, t->n_leaves, 1, 1, s);
+    if (!rc && sh) rc = download_plane(t->alloc, t->storage, t->sh, sh, t->n_leaves, nv, t->sh_stride, s);
+    return rc;
+}
+
+int dot_refine(dot_tree_t t, const float* signal, const dot_refine_params* p, dot_refine_stats* stats,
+               void* stream) {
+    if (!t || !p) return fail(DOT_EINVAL, "dot_refine: NULL argument");
+    if (!signal) return fail(DOT_EINVAL, "dot_refine: signal is NULL");
+    if (!(p->sample_frac >= 0.f && p->sample_frac <= 1.f))
+        return fail(DOT_EINVAL, "dot_refine: sample_frac must be in [0, 1]");
+    if (p->max_depth < 0 || p->max_depth > DOT_MAX_DEPTH)
+        return fail(DOT_EINVAL, "dot_refine: max_depth must be in 0..DOT_MAX_DEPTH");
+    if (!std::isfinite(p->prune_tau)) return fail(DOT_EINVAL, "dot_refine: prune_tau must be finite");
+    return refine_tree(*t, signal, *p, stats, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// Internal declarations of libdot (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "dot.h"
+
+namespace dot {
+
+// Lattice used by the traversal: 2^LAT cells per axis at the finest level,
+// so a tree may be up to LAT levels deep (DOT_MAX_DEPTH).
+constexpr int LAT = 16;
+constexpr int LAT_N = 1 << LAT;
+static_assert(LAT == DOT_MAX_DEPTH, "lattice depth must match the ABI depth limit");
+
+// Elements per leaf row of the SH plane: 3K values padded to 16 bytes.
+inline int sh_stride_for(int degree, int storage) {
+    int nv = 3 * (degree + 1) * (degree + 1);
+    int per16 = storage == DOT_F32 ? 4 : 8;
+    return (nv + per16 - 1) / per16 * per16;
+}
+inline int storage_bytes(int storage) { return storage == DOT_F32 ? 4 : 2; }
+
+// Everything a kernel needs to read a tree (passed by value).
+struct TreeView {
+    const int32_t* child;
+    const void* sigma;
+    const void* sh;
+    int64_t n_internal;
+    int64_t n_leaves;
+    float bmin[3];
+    float scale;      // lattice cells per world unit = LAT_N / bbox_size
+    int max_steps;    // safety bound on traversal steps per ray
+    int sh_stride;
+};
+
+struct Alloc {
+    dot_allocator a{};
+    bool custom = false;
+    void* get(size_t bytes) const;
+    void put(void* p) const;
+};
+
+}  // namespace dot
+
+struct dot_tree {
+    dot::Alloc alloc;
+    int64_t n_internal = 0, n_leaves = 0;
+    int32_t degree = 0, storage = 0, max_depth = 0, sh_stride = 0;
+    float bmin[3] = {0, 0, 0};
+    float size = 1.f;
+    int32_t* child = nullptr;     // device
+    void* sigma = nullptr;        // device
+    void* sh = nullptr;           // device
+    uint8_t* leaf_depth = nullptr;  // device
+
+    dot::TreeView view() const {
+        dot::TreeView v;
+        v.child = child;
+        v.sigma = sigma;
+        v.sh = sh;
+        v.n_internal = n_internal;
+        v.n_leaves = n_leaves;
+        for (int a = 0; a < 3; ++a) v.bmin[a] = bmin[a];
+        v.scale = (float)dot::LAT_N / size;
+        int md = max_depth < 1 ? 1 : max_depth;
+        v.max_steps = 3 * (1 << md) + 64;
+        v.sh_stride = sh_stride;
+        return v;
+    }
+};
+
+namespace dot {
+
+// thread-local error message
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define DOT_HIP(call)                                    \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return ::dot::hip_fail(e_, #call); \
+    } while (0)
+
+// ---- launchers (defined next to their kernels) ----
+
+struct RayBatch {
+    int kind;
+    int n_cams;
+    const dot_camera* cams;
+    int width, height;
+    int64_t n_rays;
+    const int32_t* cam_idx;
+    const int32_t* pix_idx;
+    const float* origins;
+    const float* dirs;
+    int64_t n_tiles;   // 64-ray units
+};
+
+struct FwdArgs {
+    float* rgb;         // may be null
+    int32_t* nseg;      // may be null
+    float* signal;      // may be null
+    int signal_mode;
+    float bg[3];
+    float thr;          // -ln(t_stop), +inf when disabled
+    unsigned long long* stats;  // may be null
+};
+
+struct BwdArgs {
+    const float* rgb_fwd;
+    const int32_t* nseg;
+    const float* grad_rgb;
+    float* grad_sigma;
+    float* grad_sh;
+    float thr;
+};
+
+hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArgs& a, hipStream_t s);
+hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
+hipError_t launch_encode_planes(int storage, const float* src, void* dst, int64_t rows, int src_cols,
+                                int dst_stride, hipStream_t s);
+hipError_t launch_decode_planes(int storage, const void* src, float* dst, int64_t rows, int dst_cols,
+                                int src_stride, hipStream_t s);
+hipError_t launch_adam(const dot_tree& t, const float* gs, const float* gh, float* ms, float* vs,
+                       float* mh, float* vh, const dot_adam_params& p, hipStream_t s);
+int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st,
+                hipStream_t s);
+
+}  // namespace dot

@@ -1,0 +1,128 @@
+// Leaf-plane encoding (FP32 -> storage type, padded rows), decoding, and the
+// fused Adam update of the leaf parameters.
+#include <hip/hip_runtime.h>
+
+#include "dot_device.h"
+
+namespace dot {
+
+// dst[r][0..cols) = round(src[r][0..cols)), padding columns zeroed.
+template <int DT>
+__global__ void encode_kernel(const float* __restrict__ src, void* __restrict__ dst, int64_t rows, int cols,
+                              int stride) {
+    int64_t n = rows * stride;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i / stride;
+        int c = (int)(i - r * stride);
+        float v = c < cols ? src[r * cols + c] : 0.f;
+        if constexpr (DT == DOT_F32)
+            static_cast<float*>(dst)[i] = v;
+        else if constexpr (DT == DOT_F16)
+            static_cast<uint16_t*>(dst)[i] = f32_to_f16(v);
+        else
+            static_cast<uint16_t*>(dst)[i] = f32_to_bf16(v);
+    }
+}
+
+template <int DT>
+__global__ void decode_kernel(const void* __restrict__ src, float* __restrict__ dst, int64_t rows, int cols,
+                              int stride) {
+    int64_t n = rows * cols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i / cols;
+        int c = (int)(i - r * cols);
+        int64_t j = r * stride + c;
+        float v;
+        if constexpr (DT == DOT_F32)
+            v = static_cast<const float*>(src)[j];
+        else if constexpr (DT == DOT_F16)
+            v = f16_to_f32(static_cast<const uint16_t*>(src)[j]);
+        else
+            v = bf16_to_f32(static_cast<const uint16_t*>(src)[j]);
+        dst[i] = v;
+    }
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+hipError_t launch_encode_planes(int storage, const float* src, void* dst, int64_t rows, int cols, int stride,
+                                hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    dim3 g(grid_for(rows * stride));
+    if (storage == DOT_F32)
+        hipLaunchKernelGGL(encode_kernel<DOT_F32>, g, dim3(256), 0, s, src, dst, rows, cols, stride);
+    else if (storage == DOT_F16)
+        hipLaunchKernelGGL(encode_kernel<DOT_F16>, g, dim3(256), 0, s, src, dst, rows, cols, stride);
+    else
+        hipLaunchKernelGGL(encode_kernel<DOT_BF16>, g, dim3(256), 0, s, src, dst, rows, cols, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode_planes(int storage, const void* src, float* dst, int64_t rows, int cols, int stride,
+                                hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    dim3 g(grid_for(rows * cols));
+    if (storage == DOT_F32)
+        hipLaunchKernelGGL(decode_kernel<DOT_F32>, g, dim3(256), 0, s, src, dst, rows, cols, stride);
+    else if (storage == DOT_F16)
+        hipLaunchKernelGGL(decode_kernel<DOT_F16>, g, dim3(256), 0, s, src, dst, rows, cols, stride);
+    else
+        hipLaunchKernelGGL(decode_kernel<DOT_BF16>, g, dim3(256), 0, s, src, dst, rows, cols, stride);
+    return hipGetLastError();
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// theta -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
+// Parameter j < L is sigma[j]; j >= L is SH coefficient (j-L) of the dense
+// [L][3K] layout, stored at row stride `stride` in the plane.
+__global__ void adam_kernel(float* __restrict__ sigma, float* __restrict__ sh, const float* __restrict__ gs,
+                            const float* __restrict__ gh, float* __restrict__ ms, float* __restrict__ vs,
+                            float* __restrict__ mh, float* __restrict__ vh, int64_t L, int nv, int stride,
+                            dot_adam_params p, float bc1, float bc2) {
+    int64_t n = L * (1 + nv);
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        float g, m, v, lr;
+        float* theta;
+        float *mp, *vp;
+        if (j < L) {
+            g = gs[j];
+            mp = &ms[j];
+            vp = &vs[j];
+            theta = &sigma[j];
+            lr = p.lr_sigma;
+        } else {
+            int64_t q = j - L;
+            int64_t r = q / nv;
+            int c = (int)(q - r * nv);
+            g = gh[q];
+            mp = &mh[q];
+            vp = &vh[q];
+            theta = &sh[r * stride + c];
+            lr = p.lr_sh;
+        }
+        m = p.beta1 * *mp + (1.f - p.beta1) * g;
+        v = p.beta2 * *vp + (1.f - p.beta2) * g * g;
+        *mp = m;
+        *vp = v;
+        *theta -= lr * (m / bc1) / (sqrtf(v / bc2) + p.eps);
+    }
+}
+
+hipError_t launch_adam(const dot_tree& t, const float* gs, const float* gh, float* ms, float* vs, float* mh,
+                       float* vh, const dot_adam_params& p, hipStream_t s) {
+    int nv = 3 * (t.degree + 1) * (t.degree + 1);
+    int64_t n = t.n_leaves * (1 + nv);
+    float bc1 = 1.f - powf(p.beta1, (float)p.step);
+    float bc2 = 1.f - powf(p.beta2, (float)p.step);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, static_cast<float*>(t.sigma),
+                       static_cast<float*>(t.sh), gs, gh, ms, vs, mh, vh, t.n_leaves, nv, t.sh_stride, p, bc1,
+                       bc2);
+    return hipGetLastError();
+}
+
+}  // namespace dot

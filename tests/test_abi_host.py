@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/dot.h declares, and rejects malformed input before any
+device work with a specific message."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2307_15333_amd import _lib as L
+from paper_2307_15333_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "dot.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dot_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_match_binding():
+    assert _declared() == sorted(L.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.check_output(["nm", "-D", "--defined-only", L.LIB_PATH]).decode()
+    exported = set(re.findall(r" T (dot_[a-z_]+)$", out, flags=re.M))
+    assert set(_declared()) <= exported
+
+
+def _build(child, sigma, sh, degree=0, n_internal=None, n_leaves=None, storage=L.DOT_F32, bbox=2.0):
+    lib = L.load()
+    child = np.ascontiguousarray(child, np.int32)
+    sigma = np.ascontiguousarray(sigma, np.float32)
+    sh = np.ascontiguousarray(sh, np.float32)
+    d = L.dot_tree_desc(n_internal=child.shape[0] if n_internal is None else n_internal,
+                        n_leaves=sigma.shape[0] if n_leaves is None else n_leaves, sh_degree=degree,
+                        child=child.ctypes.data if child.size else None, sigma=sigma.ctypes.data,
+                        sh=sh.ctypes.data, bbox_size=bbox)
+    h = C.c_void_p()
+    rc = lib.dot_build(C.byref(d), storage, None, None, C.byref(h))
+    return rc, lib.dot_last_error().decode()
+
+
+def _tree():
+    s = synth.random_tree_scene(3, 0, seed=1)
+    return s.child.copy(), s.sigma.copy(), s.sh.copy()
+
+
+@pytest.mark.parametrize("mutate, msg", [
+    (lambda c: c.__setitem__((0, 3), 10 ** 6), "out of range"),
+    (lambda c: c.__setitem__((0, 3), c[0, 2]), "referenced twice"),
+    (lambda c: c.__setitem__((0, 0), -10 ** 6), "out of range"),
+])
+def test_build_rejects_malformed_child_arrays(mutate, msg):
+    child, sigma, sh = _tree()
+    mutate(child)
+    rc, err = _build(child, sigma, sh)
+    assert rc == L.DOT_EINVAL and msg in err, err
+
+
+def test_build_rejects_cycles_and_unreachable_nodes():
+    child, sigma, sh = _tree()
+    # an internal child pointing back at the root is a cycle
+    j = int(np.argwhere(child[1:] >= 0)[0][0]) + 1 if (child[1:] >= 0).any() else None
+    c2 = child.copy()
+    c2[1, 0] = 0
+    rc, err = _build(c2, sigma, sh)
+    assert rc == L.DOT_EINVAL
+    # declaring more leaves than the tree references
+    rc, err = _build(child, np.concatenate([sigma, [1.0]]), np.concatenate([sh, sh[:1]]))
+    assert rc == L.DOT_EINVAL and "unreachable" in err
+
+
+def test_build_rejects_leaves_out_of_dfs_order():
+    child, sigma, sh = _tree()
+    c2 = child.copy()
+    leaves = np.argwhere(c2 < 0)
+    a, b = leaves[0], leaves[1]
+    c2[tuple(a)], c2[tuple(b)] = c2[tuple(b)], c2[tuple(a)]
+    rc, err = _build(c2, sigma, sh)
+    assert rc == L.DOT_EINVAL and "depth-first" in err
+
+
+def test_build_rejects_depth_beyond_lattice():
+    # a chain of 17 internal nodes
+    n = 17
+    child = np.empty((n, 8), np.int32)
+    leaf = 0
+    for i in range(n):
+        for o in range(8):
+            if o == 0 and i + 1 < n:
+                child[i, o] = i + 1
+            else:
+                child[i, o] = -1 - leaf
+                leaf += 1
+    # leaves must be numbered in DFS order: renumber by a walk
+    order = []
+
+    def walk(i):
+        for o in range(8):
+            e = child[i, o]
+            if e >= 0:
+                walk(e)
+            else:
+                order.append(-1 - e)
+
+    walk(0)
+    remap = {old: new for new, old in enumerate(order)}
+    child = np.where(child < 0, -1 - np.vectorize(lambda e: remap[-1 - e])(np.minimum(child, -1)), child)
+    rc, err = _build(child, np.ones(leaf), np.zeros((leaf, 3, 1)))
+    assert rc == L.DOT_EINVAL and "DOT_MAX_DEPTH" in err
+
+
+def test_build_rejects_bad_arguments():
+    child, sigma, sh = _tree()
+    rc, err = _build(child, sigma, sh, degree=4)
+    assert rc == L.DOT_EINVAL and "sh_degree" in err
+    rc, err = _build(child, sigma, sh, storage=7)
+    assert rc == L.DOT_EINVAL and "storage" in err
+    rc, err = _build(child, sigma, sh, bbox=-1.0)
+    assert rc == L.DOT_EINVAL and "bbox_size" in err
+    rc, err = _build(np.zeros((0, 8)), np.ones(2), np.zeros((2, 3, 1)))
+    assert rc == L.DOT_EINVAL and "exactly one leaf" in err
+    lib = L.load()
+    h = C.c_void_p()
+    assert lib.dot_build(None, 0, None, None, C.byref(h)) == L.DOT_EINVAL
+    assert b"desc is NULL" in lib.dot_last_error()
+
+
+def test_calls_on_null_handles_fail_cleanly():
+    lib = L.load()
+    assert lib.dot_free(None) == L.DOT_OK
+    r = L.dot_rays()
+    assert lib.dot_render(None, C.byref(r), None, None, None, None, None) == L.DOT_EINVAL
+    assert b"tree is NULL" in lib.dot_last_error()
+    info = L.dot_tree_info_t()
+    assert lib.dot_tree_info(None, C.byref(info)) == L.DOT_EINVAL
+    p = L.dot_refine_params()
+    assert lib.dot_refine(None, None, C.byref(p), None, None) == L.DOT_EINVAL
