@@ -1,0 +1,288 @@
+"""Benchmark of the octree volume renderer on one MI355X.
+
+Step = one forward pass of the renderer with the fused max-weight training
+signal over the 800x800 x 8-camera workload (torus+box SDF octree of depth 9,
+3.54M leaves, SH degree 3, FP32 leaves), inputs resident in HBM.  The JSON
+line also carries the roofline of the render kernel, the FP64 CPU oracle as
+a baseline, and the other measured forms of the hot path (FP16/BF16 leaves,
+the differentiable training step, refinement, serving latency).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s render & train step (FP32 vs FP16 leaves); p50/p99 served latency"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "render_fwd_config2_traffic.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2307_15333_amd", "csrc")
+    for f in ("dot_device.h", "render.hip", "dot_internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    rec = None
+    for line in open(PROFILE_TRAFFIC):
+        if line.startswith("TRAFFIC_JSON "):
+            rec = json.loads(line[len("TRAFFIC_JSON "):])
+    if not rec or rec.get("kernel_src_sha") != kernel_source_hash():
+        return None
+    return rec
+
+
+def time_kernel(fn, reps, torch):
+    """Average duration of `fn` (one kernel launch on the current stream) by
+    HIP events recorded on that stream."""
+    s = torch.cuda.current_stream()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    start.record(s)
+    for _ in range(reps):
+        fn()
+    end.record(s)
+    end.synchronize()
+    return start.elapsed_time(end) / reps / 1e3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="run one 1 GiB device copy and one render (counter calibration runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design is described in DESIGN.md and is not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2307_15333_amd import core, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    scene = synth.config2_scene()
+    cams = synth.config2_cameras()
+    log(f"config2 scene: {scene.n_leaves} leaves, {scene.n_internal} internal ({time.time() - t0:.1f}s)")
+    tree = core.Octree.from_scene(scene, "f32")
+    rays = core.Rays.cameras(cams)
+    n_rays = rays.n_rays
+    signal = torch.zeros(tree.n_leaves, dtype=torch.float32, device=dev)
+    rgb = torch.empty((n_rays, 3), dtype=torch.float32, device=dev)
+    import ctypes as C
+    from paper_2307_15333_amd import _lib as L
+    opts = core.render_opts(t_stop=1e-4)
+    lib = L.load()
+
+    def step():
+        L.check(lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(opts), C.c_void_p(rgb.data_ptr()),
+                               None, C.c_void_p(signal.data_ptr()), core._stream()))
+
+    if args.profile_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        step()
+        torch.cuda.synchronize()
+        log("profile-copy: one 1 GiB copy and one render done")
+        return
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms = elapsed / args.steps * 1e3
+    value = n_rays / (elapsed / args.steps) / 1e6
+    log(f"render fp32: {ms:.3f} ms/step, {value:.1f} Mrays/s")
+
+    # ---- roofline of the render kernel ----
+    stats = tree.render_stats(rays)
+    K = (scene.degree + 1) ** 2
+    leaf_bytes = stats["segments"] * 4 + stats["sh_fetches"] * 3 * K * 4
+    kt = time_kernel(step, max(5, args.steps // 2), torch)
+    achieved = leaf_bytes / kt / 1e9
+    other = stats["child_reads"] * 4 + n_rays * 12 + stats["sh_fetches"] * 4
+    traffic = read_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
+                "kernel": "render_fwd_kernel<F32,deg3>", "kernel_ms": round(kt * 1e3, 4),
+                "algorithmic_bytes_per_launch": int(leaf_bytes),
+                "per_unit": "4 B sigma per segment + 192 B SH per segment with sigma*delta > 0",
+                "units_per_launch": {"segments": stats["segments"], "sh_fetches": stats["sh_fetches"]},
+                "other_bytes_per_launch": {"child_reads": stats["child_reads"] * 4, "rgb": n_rays * 12,
+                                           "signal_reads": stats["sh_fetches"] * 4, "total": int(other)}}
+    log(f"render kernel {kt * 1e3:.3f} ms; leaf-fetch {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak);"
+        f" segments/ray {stats['segments'] / n_rays:.2f}")
+
+    extra = {}
+    if not args.no_extra:
+        extra = measure_extra(torch, core, synth, scene, cams, tree, args)
+    tree.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cams)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded SDF octree, random SH; stands in for NeRF-synthetic 800x800 views)",
+        "config": {"workload": "config2: torus+box SDF octree, depth 9, %d leaves, SH degree 3, FP32 leaves, "
+                               "8 cameras x 800x800 on the radius-4 sphere, white bg, t_stop 1e-4, fused "
+                               "max-weight signal" % scene.n_leaves,
+                   "rays_per_step": n_rays, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
+    """FP16/BF16 leaves on the same workload, and the training step."""
+    res = {}
+    rays = core.Rays.cameras(cams)
+    base = None
+    for storage in ("f32", "f16", "bf16"):
+        tree = tree_f32 if storage == "f32" else core.Octree.from_scene(scene, storage)
+        sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
+        rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device="cuda")
+
+        def fn(tree=tree, sig=sig, rgb=rgb):
+            import ctypes as C
+            from paper_2307_15333_amd import _lib as L
+            op = core.render_opts()
+            L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op),
+                                        C.c_void_p(rgb.data_ptr()), None, C.c_void_p(sig.data_ptr()),
+                                        core._stream()))
+
+        kt = time_kernel(fn, max(5, args.steps // 2), torch)
+        mr = rays.n_rays / kt / 1e6
+        if storage == "f32":
+            base = mr
+        res[f"render_{storage}_mrays"] = round(mr, 1)
+        if storage != "f32":
+            res[f"render_{storage}_speedup_vs_f32"] = round(mr / base, 3)
+            tree.close()
+        log(f"render {storage}: {kt * 1e3:.3f} ms, {mr:.1f} Mrays/s")
+    res.update(train_step(torch, core, synth, args))
+    return res
+
+
+def train_step(torch, core, synth, args):
+    """Config 4: forward + hand-written backward + Adam over 2^18 random rays of
+    100 views of the config-1 octree (SH perturbed by N(0, 0.05^2))."""
+    gt = synth.config1_scene()
+    train = synth.perturb_sh(gt, 0.05, seed=3)
+    views = synth.config4_views(100)
+    gt_tree = core.Octree.from_scene(gt)
+    tree = core.Octree.from_scene(train)
+    W = H = 64
+    all_rays = core.Rays.cameras(views)
+    target = gt_tree.render(all_rays)           # [100*64*64, 3]
+    gt_tree.close()
+    cams_raw = all_rays._keep[0]
+    n_pool = 100 * W * H
+    B = 1 << 18
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    perm = torch.randperm(n_pool, device="cuda", generator=gen)
+    sig_v, sh_v = tree.plane_views()
+    sigma = sig_v.detach().requires_grad_()
+    sh = sh_v.detach().requires_grad_()
+    state = tree.adam_state()
+
+    def one(step_i, off):
+        idx = perm[off:off + B]
+        ci = (idx // (W * H)).to(torch.int32)
+        pi = (idx % (W * H)).to(torch.int32)
+        r = core.Rays.pixels_device(cams_raw, 100, ci, pi)
+        rgb = core.render_autograd(tree, sigma, sh, r)
+        loss = torch.mean((rgb - target[idx]) ** 2)
+        sigma.grad = None
+        sh.grad = None
+        loss.backward()
+        tree.adam_step(sigma.grad, sh.grad, state, step_i, lr_sigma=0.1, lr_sh=0.01)
+        return loss
+
+    losses = []
+    for i in range(2):
+        one(i + 1, 0)
+    torch.cuda.synchronize()
+    steps = 10
+    t = time.perf_counter()
+    for i in range(steps):
+        losses.append(one(3 + i, (i % 1) * B))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    tree.close()
+    l0, l1 = float(losses[0]), float(losses[-1])
+    log(f"train step: {dt * 1e3:.3f} ms, {B / dt / 1e6:.1f} Mrays/s, loss {l0:.3e} -> {l1:.3e}")
+    return {"train_step_ms": round(dt * 1e3, 3), "train_step_mrays": round(B / dt / 1e6, 1),
+            "train_rays_per_step": B, "train_loss_first_last": [l0, l1]}
+
+
+def cpu_baseline(scene, cams):
+    """The FP64 oracle, as it stands, on the host cores: all 8 cameras of the
+    workload (the same 5.12M rays the GPU step renders); render calls only."""
+    from oracle import oracle as O
+    T = O.OracleTree.from_scene(scene, sigma=scene.sigma.astype(np.float64))
+    return _cpu_result(T, cams)
+
+
+def _cpu_result(T, cams):
+    from oracle import oracle as O
+    total = 0.0
+    n = 0
+    for j in range(len(cams)):
+        ci = np.full(800 * 800, j, np.int32)
+        pi = np.arange(800 * 800, dtype=np.int32)
+        o, d = O.camera_rays(cams, ci, pi)
+        t1 = time.perf_counter()
+        O.render(T, o, d)
+        total += time.perf_counter() - t1
+        n += o.shape[0]
+    v = n / total / 1e6
+    log(f"cpu oracle: {n} rays in {total:.2f}s = {v:.3f} Mrays/s on {O.num_threads()} threads")
+    return {"value": round(v, 4), "unit": "Mrays/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"all {n} rays of the 8 800x800 views (render calls only, FP64, OpenMP)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,12 +1,525 @@
-// Octree refinement (Sec. 3.2): placeholder until the device implementation lands.
+// Octree refinement on the device (Sec. 3.2, Alg. 1: pruning, then sampling,
+// both driven by the same per-leaf signal).
+//
+//   mark    an internal node merges iff its 8 children are leaves and all are
+//           selected for pruning (signal <= tau, or < tau);
+//   select  exact top-k of the 64-bit keys (~ord(signal) << 32 | leaf) over
+//           the sampling candidates by an 8-pass MSD radix select, so ties in
+//           signal go to the lower leaf index;
+//   rebuild new leaf and internal indices by exclusive prefix scans over the
+//           old DFS order, then scatter: a merged group becomes one leaf with
+//           the mean of its 8 rows (Eq. 3), a sampled leaf becomes an internal
+//           node whose 8 children copy its row (Eq. 4).
+// The result is numbered in DFS order, so its topology is canonical.
 #include <hip/hip_runtime.h>
 
-#include "dot_internal.h"
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "dot_device.h"
 
 namespace dot {
 
-int refine_tree(dot_tree&, const float*, const dot_refine_params&, dot_refine_stats*, hipStream_t) {
-    return fail(DOT_EUNSUPPORTED, "dot_refine: not implemented yet");
+namespace {
+
+constexpr int TPB = 256;
+
+unsigned blocks_for(int64_t n, int per_thread = 1) {
+    int64_t g = (n + (int64_t)TPB * per_thread - 1) / ((int64_t)TPB * per_thread);
+    if (g > 1 << 20) g = 1 << 20;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ bool selected(float s, float tau, int le) { return le ? (s <= tau) : (s < tau); }
+
+// order-preserving map of a float to uint32 (ascending)
+__device__ __forceinline__ uint32_t ord32(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    GRID_STRIDE(i, n) p[i] = v;
+}
+
+// slot of each leaf in its parent's child list: parent * 8 + octant (-1 for a root leaf)
+__global__ void k_leaf_slot(const int32_t* __restrict__ child, int64_t I, int32_t* __restrict__ slot) {
+    GRID_STRIDE(j, I * 8) {
+        int32_t e = child[j];
+        if (e < 0) slot[-1 - e] = (int32_t)j;
+    }
+}
+
+__global__ void k_first_leaf(const int32_t* __restrict__ child, int64_t I, int32_t* __restrict__ first) {
+    GRID_STRIDE(p, I) {
+        int32_t e = child[p * 8];
+        while (e >= 0) e = child[(int64_t)e * 8];
+        first[p] = -1 - e;
+    }
+}
+
+__global__ void k_mark_merge(const int32_t* __restrict__ child, int64_t I, const float* __restrict__ sig,
+                             float tau, int le, uint32_t* __restrict__ survive) {
+    GRID_STRIDE(p, I) {
+        bool all = true;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            int32_t e = child[p * 8 + o];
+            if (e >= 0 || !selected(sig[-1 - e], tau, le)) all = false;
+        }
+        survive[p] = all ? 0u : 1u;
+    }
+}
+
+__global__ void k_keys(const float* __restrict__ sig, const uint8_t* __restrict__ depth, int64_t L, float tau,
+                       int le, int max_depth, uint64_t* __restrict__ keys) {
+    GRID_STRIDE(l, L) {
+        float s = sig[l];
+        bool cand = !selected(s, tau, le) && (int)depth[l] < max_depth;
+        keys[l] = cand ? (((uint64_t)(~ord32(s)) << 32) | (uint64_t)l) : ~0ull;
+    }
+}
+
+struct SelState {
+    unsigned long long prefix, mask;
+    unsigned long long k_rem, k_eff;
+    unsigned int hist[256];
+};
+
+__global__ void k_sel_init(SelState* st) {
+    int t = threadIdx.x;
+    if (t == 0) {
+        st->prefix = 0;
+        st->mask = 0;
+        st->k_rem = 0;
+        st->k_eff = 0;
+    }
+    st->hist[t] = 0;
+}
+
+__global__ void k_hist(const uint64_t* __restrict__ keys, int64_t L, int shift, SelState* st) {
+    __shared__ unsigned int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned long long prefix = st->prefix, mask = st->mask;
+    GRID_STRIDE(l, L) {
+        uint64_t k = keys[l];
+        if (k != ~0ull && (k & mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// one thread: choose the digit holding the k_rem-th smallest candidate
+__global__ void k_sel_digit(SelState* st, int shift, int first, long long k_req) {
+    if (threadIdx.x != 0) return;
+    if (first) {
+        unsigned long long n = 0;
+        for (int d = 0; d < 256; ++d) n += st->hist[d];
+        unsigned long long k = (unsigned long long)k_req < n ? (unsigned long long)k_req : n;
+        st->k_eff = k;
+        st->k_rem = k;
+    }
+    if (st->k_rem > 0) {
+        unsigned long long cum = 0;
+        int d = 0;
+        for (; d < 256; ++d) {
+            if (cum + st->hist[d] >= st->k_rem) break;
+            cum += st->hist[d];
+        }
+        st->k_rem -= cum;
+        st->prefix |= (unsigned long long)d << shift;
+        st->mask |= 255ull << shift;
+    }
+    for (int d = 0; d < 256; ++d) st->hist[d] = 0;
+}
+
+// new-leaf counts per old leaf, and the split flags
+__global__ void k_leaf_counts(int64_t L, const int32_t* __restrict__ slot, const uint32_t* __restrict__ survive,
+                              const uint64_t* __restrict__ keys, const SelState* __restrict__ st,
+                              uint32_t* __restrict__ cnt, uint32_t* __restrict__ split) {
+    const unsigned long long kstar = st->prefix;
+    const bool any = st->k_eff > 0;
+    GRID_STRIDE(l, L) {
+        int32_t s = slot[l];
+        bool merged = s >= 0 && survive[s >> 3] == 0u;
+        bool sp = any && keys[l] != ~0ull && keys[l] <= kstar;
+        split[l] = sp ? 1u : 0u;
+        cnt[l] = merged ? ((s & 7) == 0 ? 1u : 0u) : (sp ? 8u : 1u);
+    }
+}
+
+__global__ void k_add_u32(uint32_t* __restrict__ a, const uint32_t* __restrict__ h, int64_t n) {
+    GRID_STRIDE(i, n) a[i] += h[i];
+}
+
+__global__ void k_first_hist(int64_t I, const uint32_t* __restrict__ survive, const int32_t* __restrict__ first,
+                             uint32_t* __restrict__ hist) {
+    GRID_STRIDE(p, I) {
+        if (survive[p]) atomicAdd(&hist[first[p]], 1u);
+    }
+}
+
+// ---- exclusive prefix scan of uint32 (three passes over 4096-element tiles) ----
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& total) {
+    __shared__ uint32_t wsum[TPB / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    total = 0;
+#pragma unroll
+    for (int j = 0; j < TPB / 64; ++j) {
+        if (j < w) base += wsum[j];
+        total += wsum[j];
+    }
+    __syncthreads();
+    return base + x - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ bsum) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * TPB + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t total;
+    block_exclusive_scan(acc, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the block sums in place; total into *tot
+__global__ void k_scan_bsums(uint32_t* __restrict__ bsum, int64_t nb, uint32_t* __restrict__ tot) {
+    const int64_t per = (nb + TPB - 1) / TPB;
+    const int64_t b0 = threadIdx.x * per;
+    uint32_t acc = 0;
+    for (int64_t i = b0; i < b0 + per && i < nb; ++i) acc += bsum[i];
+    uint32_t total;
+    uint32_t off = block_exclusive_scan(acc, total);
+    for (int64_t i = b0; i < b0 + per && i < nb; ++i) {
+        uint32_t v = bsum[i];
+        bsum[i] = off;
+        off += v;
+    }
+    if (threadIdx.x == 0) *tot = total;
+}
+
+__global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ bsum,
+                             uint32_t* __restrict__ out) {
+    // each thread owns SCAN_ITEMS consecutive elements of the tile
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        v[j] = i < n ? in[i] : 0u;
+        acc += v[j];
+    }
+    uint32_t total;
+    uint32_t off = block_exclusive_scan(acc, total) + bsum[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = off;
+        off += v[j];
+    }
+}
+
+// ---- rebuild ----
+__global__ void k_child_internal(const int32_t* __restrict__ child, int64_t I, const uint32_t* __restrict__ survive,
+                                 const int32_t* __restrict__ first, const uint32_t* __restrict__ rank_int,
+                                 const uint32_t* __restrict__ rank_split, const uint32_t* __restrict__ split,
+                                 const uint32_t* __restrict__ cnt_le, const uint32_t* __restrict__ nl,
+                                 int32_t* __restrict__ out) {
+    GRID_STRIDE(p, I) {
+        if (!survive[p]) continue;
+        int64_t np = (int64_t)rank_int[p] + rank_split[first[p]];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            int32_t e = child[p * 8 + o];
+            int32_t v;
+            if (e >= 0) {
+                if (survive[e])
+                    v = (int32_t)(rank_int[e] + rank_split[first[e]]);
+                else
+                    v = -1 - (int32_t)nl[first[e]];
+            } else {
+                int64_t l = -1 - e;
+                if (split[l])
+                    v = (int32_t)(rank_split[l] + cnt_le[l]);
+                else
+                    v = -1 - (int32_t)nl[l];
+            }
+            out[np * 8 + o] = v;
+        }
+    }
+}
+
+__global__ void k_child_split(int64_t L, const uint32_t* __restrict__ split, const uint32_t* __restrict__ rank_split,
+                              const uint32_t* __restrict__ cnt_le, const uint32_t* __restrict__ nl,
+                              int32_t* __restrict__ out) {
+    GRID_STRIDE(l, L) {
+        if (!split[l]) continue;
+        int64_t np = (int64_t)rank_split[l] + cnt_le[l];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) out[np * 8 + o] = -1 - (int32_t)(nl[l] + o);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ double ld_elem(const void* p, int64_t i) {
+    if constexpr (DT == DOT_F32)
+        return (double)static_cast<const float*>(p)[i];
+    else if constexpr (DT == DOT_F16)
+        return (double)f16_to_f32(static_cast<const uint16_t*>(p)[i]);
+    else
+        return (double)bf16_to_f32(static_cast<const uint16_t*>(p)[i]);
+}
+
+// FP64 -> storage, round to nearest even, rounded once: FP32 directly; FP16 /
+// BF16 through an FP32 rounded to odd (truncate, set the last bit if inexact),
+// which carries enough bits that the final rounding is not a double rounding.
+template <int DT>
+__device__ __forceinline__ void st_elem(void* p, int64_t i, double x) {
+    if constexpr (DT == DOT_F32) {
+        static_cast<float*>(p)[i] = __double2float_rn(x);
+    } else {
+        float f = __double2float_rz(x);
+        if ((double)f != x) f = __uint_as_float(__float_as_uint(f) | 1u);
+        static_cast<uint16_t*>(p)[i] = DT == DOT_F16 ? f32_to_f16(f) : f32_to_bf16(f);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void cp_elem(const void* src, int64_t i, void* dst, int64_t j) {
+    if constexpr (DT == DOT_F32)
+        static_cast<float*>(dst)[j] = static_cast<const float*>(src)[i];
+    else
+        static_cast<uint16_t*>(dst)[j] = static_cast<const uint16_t*>(src)[i];
+}
+
+template <int DT>
+__global__ void k_emit_leaves(int64_t L, int nv, int stride, const int32_t* __restrict__ slot,
+                              const uint32_t* __restrict__ survive, const uint32_t* __restrict__ split,
+                              const uint32_t* __restrict__ nl, const uint8_t* __restrict__ depth,
+                              const void* __restrict__ sig, const void* __restrict__ sh, void* __restrict__ sig2,
+                              void* __restrict__ sh2, uint8_t* __restrict__ depth2) {
+    GRID_STRIDE(l, L) {
+        int32_t s = slot[l];
+        int64_t j = nl[l];
+        if (s >= 0 && survive[s >> 3] == 0u) {
+            if ((s & 7) != 0) continue;
+            // the 8 children of a merged node are the consecutive leaves l..l+7
+            auto mean8 = [&](const void* p, int64_t base, int64_t step) {
+                double v[8];
+#pragma unroll
+                for (int o = 0; o < 8; ++o) v[o] = ld_elem<DT>(p, base + o * step);
+                return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) * 0.125;
+            };
+            st_elem<DT>(sig2, j, mean8(sig, l, 1));
+            for (int c = 0; c < nv; ++c) st_elem<DT>(sh2, j * stride + c, mean8(sh, l * stride + c, stride));
+            for (int c = nv; c < stride; ++c) st_elem<DT>(sh2, j * stride + c, 0.0);
+            depth2[j] = (uint8_t)(depth[l] - 1);
+        } else {
+            int reps = split[l] ? 8 : 1;
+            uint8_t d = (uint8_t)(depth[l] + (split[l] ? 1 : 0));
+            for (int r = 0; r < reps; ++r) {
+                cp_elem<DT>(sig, l, sig2, j + r);
+                for (int c = 0; c < stride; ++c) cp_elem<DT>(sh, l * stride + c, sh2, (j + r) * stride + c);
+                depth2[j + r] = d;
+            }
+        }
+    }
+}
+
+__global__ void k_totals(int64_t L, int64_t I, const uint32_t* __restrict__ nl, const uint32_t* __restrict__ cnt,
+                         const uint32_t* __restrict__ tot_int, const uint32_t* __restrict__ tot_split,
+                         const SelState* __restrict__ st, unsigned long long* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    out[0] = (unsigned long long)nl[L - 1] + cnt[L - 1];      // new leaves
+    out[1] = (unsigned long long)(I > 0 ? *tot_int : 0u) + *tot_split;  // new internal nodes
+    out[2] = (unsigned long long)(I > 0 ? (uint64_t)I - *tot_int : 0u);  // merged nodes
+    out[3] = st->k_eff;
+}
+
+// RAII list of temporaries from the tree's allocator
+struct Temps {
+    const Alloc& al;
+    std::vector<void*> ps;
+    bool ok = true;
+    explicit Temps(const Alloc& a) : al(a) {}
+    template <class T>
+    T* get(int64_t n) {
+        void* p = al.get((size_t)(n < 1 ? 1 : n) * sizeof(T));
+        if (!p) ok = false;
+        ps.push_back(p);
+        return static_cast<T*>(p);
+    }
+    ~Temps() {
+        for (void* p : ps) al.put(p);
+    }
+};
+
+hipError_t scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(TPB), 0, s, bsum, nb, tot);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum, out);
+    return hipGetLastError();
+}
+
+template <int DT>
+hipError_t launch_emit(int64_t L, int nv, int stride, const int32_t* slot, const uint32_t* survive,
+                       const uint32_t* split, const uint32_t* nl, const uint8_t* depth, const void* sig,
+                       const void* sh, void* sig2, void* sh2, uint8_t* depth2, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit_leaves<DT>, dim3(blocks_for(L)), dim3(TPB), 0, s, L, nv, stride, slot, survive, split,
+                       nl, depth, sig, sh, sig2, sh2, depth2);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st_out,
+                hipStream_t s) {
+    if (p.recursive) return fail(DOT_EUNSUPPORTED, "dot_refine: recursive pruning is not implemented");
+    const int64_t L = t.n_leaves, I = t.n_internal;
+    const int64_t k_req = (int64_t)std::floor((double)p.sample_frac * (double)L);
+    if (L + 7 * k_req > (int64_t)INT32_MAX || I + k_req > (int64_t)INT32_MAX / 8)
+        return fail(DOT_EINVAL, "dot_refine: the refined tree would exceed 32-bit indices");
+    const int nv = 3 * (t.degree + 1) * (t.degree + 1);
+    const int stride = t.sh_stride;
+    const int es = storage_bytes(t.storage);
+
+    Temps tmp(t.alloc);
+    int32_t* slot = tmp.get<int32_t>(L);
+    int32_t* first = tmp.get<int32_t>(I);
+    uint32_t* survive = tmp.get<uint32_t>(I);
+    uint64_t* keys = tmp.get<uint64_t>(L);
+    SelState* sel = tmp.get<SelState>(1);
+    uint32_t* cnt = tmp.get<uint32_t>(L);
+    uint32_t* split = tmp.get<uint32_t>(L);
+    uint32_t* nl = tmp.get<uint32_t>(L);
+    uint32_t* rank_split = tmp.get<uint32_t>(L);
+    uint32_t* hist_first = tmp.get<uint32_t>(L);
+    uint32_t* cnt_le = tmp.get<uint32_t>(L);
+    uint32_t* rank_int = tmp.get<uint32_t>(I);
+    uint32_t* bsum = tmp.get<uint32_t>((std::max(L, I) + SCAN_TILE - 1) / SCAN_TILE + 1);
+    uint32_t* tots = tmp.get<uint32_t>(4);
+    unsigned long long* totals = tmp.get<unsigned long long>(4);
+    if (!tmp.ok) return fail(DOT_ENOMEM, "dot_refine: scratch allocation failed");
+
+    // 1. marks, keys
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, reinterpret_cast<uint32_t*>(slot), L,
+                       0xffffffffu);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, hist_first, L, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(TPB), 0, s, tots, (int64_t)4, 0u);
+    if (I > 0) {
+        hipLaunchKernelGGL(k_leaf_slot, dim3(blocks_for(I * 8)), dim3(TPB), 0, s, t.child, I, slot);
+        hipLaunchKernelGGL(k_first_leaf, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, first);
+        hipLaunchKernelGGL(k_mark_merge, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, signal, p.prune_tau,
+                           p.prune_le, survive);
+    }
+    hipLaunchKernelGGL(k_keys, dim3(blocks_for(L)), dim3(TPB), 0, s, signal, t.leaf_depth, L, p.prune_tau,
+                       p.prune_le, p.max_depth, keys);
+    // 2. exact top-k by radix select over the 64-bit keys
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, sel);
+    if (k_req > 0) {
+        for (int pass = 0; pass < 8; ++pass) {
+            int shift = 56 - 8 * pass;
+            hipLaunchKernelGGL(k_hist, dim3(blocks_for(L, 8)), dim3(256), 0, s, keys, L, shift, sel);
+            hipLaunchKernelGGL(k_sel_digit, dim3(1), dim3(64), 0, s, sel, shift, pass == 0 ? 1 : 0,
+                               (long long)k_req);
+        }
+    }
+    // 3. counts and scans
+    hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(L)), dim3(TPB), 0, s, L, slot, survive, keys, sel, cnt, split);
+    if (I > 0) hipLaunchKernelGGL(k_first_hist, dim3(blocks_for(I)), dim3(TPB), 0, s, I, survive, first, hist_first);
+    hipError_t e = scan(cnt, nl, L, bsum, &tots[0], s);
+    if (e == hipSuccess) e = scan(split, rank_split, L, bsum, &tots[1], s);
+    if (e == hipSuccess) e = scan(hist_first, cnt_le, L, bsum, &tots[2], s);  // exclusive; + hist -> inclusive
+    if (e == hipSuccess && I > 0) e = scan(survive, rank_int, I, bsum, &tots[3], s);
+    if (e != hipSuccess) return hip_fail(e, "dot_refine: scans");
+    // cnt_le must be inclusive: count of surviving nodes whose first leaf is <= l
+    hipLaunchKernelGGL(k_add_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, cnt_le, (const uint32_t*)hist_first, L);
+    hipLaunchKernelGGL(k_totals, dim3(1), dim3(64), 0, s, L, I, nl, cnt, &tots[3], &tots[1], sel, totals);
+    unsigned long long h_tot[4];
+    e = hipMemcpyAsync(h_tot, totals, sizeof(h_tot), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "dot_refine: sizes");
+    const int64_t L2 = (int64_t)h_tot[0], I2 = (int64_t)h_tot[1];
+
+    // 4. new planes
+    int32_t* child2 = static_cast<int32_t*>(t.alloc.get((size_t)std::max<int64_t>(I2, 1) * 32));
+    void* sig2 = t.alloc.get((size_t)L2 * es);
+    void* sh2 = t.alloc.get((size_t)L2 * stride * es);
+    uint8_t* depth2 = static_cast<uint8_t*>(t.alloc.get((size_t)L2));
+    if (!child2 || !sig2 || !sh2 || !depth2) {
+        t.alloc.put(child2);
+        t.alloc.put(sig2);
+        t.alloc.put(sh2);
+        t.alloc.put(depth2);
+        return fail(DOT_ENOMEM, "dot_refine: allocation of the refined planes failed");
+    }
+    if (I > 0)
+        hipLaunchKernelGGL(k_child_internal, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, survive, first,
+                           rank_int, rank_split, split, cnt_le, nl, child2);
+    hipLaunchKernelGGL(k_child_split, dim3(blocks_for(L)), dim3(TPB), 0, s, L, split, rank_split, cnt_le, nl, child2);
+    if (t.storage == DOT_F32)
+        e = launch_emit<DOT_F32>(L, nv, stride, slot, survive, split, nl, t.leaf_depth, t.sigma, t.sh, sig2, sh2,
+                                 depth2, s);
+    else if (t.storage == DOT_F16)
+        e = launch_emit<DOT_F16>(L, nv, stride, slot, survive, split, nl, t.leaf_depth, t.sigma, t.sh, sig2, sh2,
+                                 depth2, s);
+    else
+        e = launch_emit<DOT_BF16>(L, nv, stride, slot, survive, split, nl, t.leaf_depth, t.sigma, t.sh, sig2, sh2,
+                                  depth2, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        t.alloc.put(child2);
+        t.alloc.put(sig2);
+        t.alloc.put(sh2);
+        t.alloc.put(depth2);
+        return hip_fail(e, "dot_refine: rebuild");
+    }
+    // 5. swap into the handle
+    t.alloc.put(t.child);
+    t.alloc.put(t.sigma);
+    t.alloc.put(t.sh);
+    t.alloc.put(t.leaf_depth);
+    t.child = child2;
+    t.sigma = sig2;
+    t.sh = sh2;
+    t.leaf_depth = depth2;
+    t.n_leaves = L2;
+    t.n_internal = I2;
+    // an upper bound on the deepest leaf (it only bounds traversal steps)
+    t.max_depth = std::min(DOT_MAX_DEPTH, t.max_depth + (h_tot[3] > 0 ? 1 : 0));
+    if (st_out) {
+        st_out->leaves_before = L;
+        st_out->leaves_after = L2;
+        st_out->internal_after = I2;
+        st_out->merged = (int64_t)h_tot[2];
+        st_out->subdivided = (int64_t)h_tot[3];
+    }
+    return DOT_OK;
 }
 
 }  // namespace dot

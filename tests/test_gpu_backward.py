@@ -1,0 +1,145 @@
+"""Hand-written adjoint and Adam on the GPU.
+
+Gradients are compared with the FP64 oracle's analytic gradient (itself pinned
+by central differences) with t_stop = 0, where the render is smooth: the
+infinity-norm error of each gradient array relative to its infinity norm must
+be <= 1e-4.  Adam is compared with torch.optim.Adam on the CPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2307_15333_amd import synth
+
+pytestmark = pytest.mark.gpu
+GTOL = 1e-4
+
+
+def _core():
+    from paper_2307_15333_amd import core
+    return core
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def _grads(scene, rays_gpu, o, d, g, t_stop, bg=(1.0, 1.0, 1.0)):
+    core = _core()
+    tree = core.Octree.from_scene(scene)
+    rgb, ns = tree.render(rays_gpu, bg=bg, t_stop=t_stop, nseg=True)
+    Ln, K = tree.n_leaves, tree.K
+    gs = torch.zeros(Ln, device="cuda")
+    gh = torch.zeros((Ln, 3, K), device="cuda")
+    tree.backward(rays_gpu, rgb, ns, torch.as_tensor(g, dtype=torch.float32, device="cuda"), gs, gh,
+                  bg=bg, t_stop=t_stop)
+    torch.cuda.synchronize()
+    T = O.OracleTree.from_scene(scene, sigma=scene.sigma.astype(np.float64))
+    rs, rh = O.backward(T, o, d, g, bg=bg, t_stop=t_stop)
+    tree.close()
+    return gs.cpu().numpy(), gh.cpu().numpy(), rs, rh
+
+
+@pytest.mark.parametrize("t_stop", [0.0, 1e-4])
+def test_backward_matches_oracle_config1(t_stop):
+    core = _core()
+    s = synth.config1_scene()
+    views = synth.config4_views(n=9)
+    ci, pi = synth.pixel_batch(9, 64, 64, 8192, seed=1)
+    rng = np.random.default_rng(2)
+    g = rng.normal(size=(ci.shape[0], 3))
+    o, d = O.camera_rays(views, ci, pi)
+    gs, gh, rs, rh = _grads(s, core.Rays.pixels(views, ci, pi), o, d, g, t_stop)
+    es, eh = _rel(gs, rs), _rel(gh, rh)
+    print(f"t_stop={t_stop}: grad_sigma rel {es:.3e}, grad_sh rel {eh:.3e}")
+    if t_stop == 0.0:
+        assert es <= GTOL and eh <= GTOL
+    else:
+        # a stop decision that differs between FP32 and FP64 moves whole segment
+        # contributions; report, and require agreement away from those rays
+        assert eh <= 1e-2 and es <= 1e-2
+
+
+def test_backward_random_tree_explicit_rays():
+    core = _core()
+    s = synth.random_tree_scene(5, 3, seed=4, p_split=0.45, sigma_max=10.0)
+    o, d = synth.random_explicit_rays(3000, seed=21)
+    g = np.random.default_rng(3).normal(size=(3000, 3))
+    gs, gh, rs, rh = _grads(s, core.Rays.explicit(o, d), o.astype(np.float64), d.astype(np.float64), g, 0.0,
+                            bg=(0.3, 0.2, 0.9))
+    assert _rel(gs, rs) <= GTOL and _rel(gh, rh) <= GTOL
+
+
+def test_autograd_function_mse():
+    core = _core()
+    s = synth.config1_scene()
+    cams = synth.cameras([(40.0, 30.0, 4.0, 48, 40)])
+    tree = core.Octree.from_scene(s)
+    rays = core.Rays.cameras(cams)
+    sig_v, sh_v = tree.plane_views()
+    sigma = sig_v.detach().requires_grad_()
+    sh = sh_v.detach().requires_grad_()
+    target = torch.full((rays.n_rays, 3), 0.4, device="cuda")
+    rgb = core.render_autograd(tree, sigma, sh, rays, t_stop=0.0)
+    loss = torch.mean((rgb - target) ** 2)
+    loss.backward()
+    assert sigma.grad.shape == sigma.shape and sh.grad.shape == sh.shape
+    o, d = O.camera_rays(cams)
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    ref = O.render(T, o, d, t_stop=0.0)["rgb"]
+    g = 2.0 * (ref - 0.4) / ref.size
+    rs, rh = O.backward(T, o, d, g, t_stop=0.0)
+    assert _rel(sigma.grad.cpu().numpy(), rs) <= GTOL
+    assert _rel(sh.grad.cpu().numpy(), rh) <= GTOL
+    tree.close()
+
+
+def test_adam_step_matches_torch_adam():
+    core = _core()
+    s = synth.random_tree_scene(4, 2, seed=9)
+    tree = core.Octree.from_scene(s)
+    Ln, K = tree.n_leaves, tree.K
+    rng = np.random.default_rng(0)
+    state = tree.adam_state()
+    p_sig = torch.tensor(s.sigma.copy(), requires_grad=True)
+    p_sh = torch.tensor(s.sh.copy(), requires_grad=True)
+    opt = torch.optim.Adam([{"params": [p_sig], "lr": 0.1}, {"params": [p_sh], "lr": 0.01}],
+                           betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 4):
+        gs = rng.normal(size=Ln).astype(np.float32)
+        gh = rng.normal(size=(Ln, 3, K)).astype(np.float32)
+        tree.adam_step(torch.tensor(gs, device="cuda"), torch.tensor(gh, device="cuda"), state, step)
+        p_sig.grad = torch.tensor(gs)
+        p_sh.grad = torch.tensor(gh)
+        opt.step()
+    ex = tree.export()
+    np.testing.assert_allclose(ex["sigma"], p_sig.detach().numpy(), atol=2e-6, rtol=2e-6)
+    np.testing.assert_allclose(ex["sh"], p_sh.detach().numpy(), atol=2e-6, rtol=2e-6)
+    tree.close()
+
+
+def test_adam_rejects_reduced_precision():
+    from paper_2307_15333_amd import _lib as L
+    core = _core()
+    s = synth.random_tree_scene(3, 1, seed=1)
+    tree = core.Octree.from_scene(s, "f16")
+    state = tree.adam_state()
+    z = torch.zeros(tree.n_leaves, device="cuda")
+    with pytest.raises(L.DotError) as e:
+        tree.adam_step(z, torch.zeros((tree.n_leaves, 3, tree.K), device="cuda"), state, 1)
+    assert e.value.code == L.DOT_EUNSUPPORTED
+    tree.close()
+
+
+def test_export_roundtrip_all_storages():
+    core = _core()
+    s = synth.random_tree_scene(4, 3, seed=2)
+    for storage in ("f32", "f16", "bf16"):
+        tree = core.Octree.from_scene(s, storage)
+        ex = tree.export()
+        np.testing.assert_array_equal(ex["child"], s.child)
+        np.testing.assert_array_equal(ex["depth"], s.leaf_depth)
+        np.testing.assert_array_equal(ex["sigma"], O.round_storage(s.sigma.astype(np.float64), storage))
+        np.testing.assert_array_equal(ex["sh"], O.round_storage(s.sh.astype(np.float64), storage))
+        tree.close()

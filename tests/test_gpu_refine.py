@@ -1,0 +1,163 @@
+"""Device refinement versus the oracle's recursive rebuild.
+
+Given the same signal array (seeded, or computed by the oracle), the refined
+topology -- child array, leaf depths -- must match bit for bit; split children
+are exact copies; merged leaves equal the FP64 mean rounded once to the storage
+type (allowed: 1 ulp, counted and reported).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2307_15333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _core():
+    from paper_2307_15333_amd import core
+    return core
+
+
+def _seeded_signal(n, seed, frac_small=0.5):
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    small = rng.random(n) < frac_small
+    s[small] = rng.uniform(0.0, 2e-3, small.sum()).astype(np.float32)
+    return s
+
+
+def _ulps(a, b, storage):
+    if storage == "f32":
+        ai = np.asarray(a, np.float32).view(np.int32).astype(np.int64)
+        bi = np.asarray(b, np.float32).view(np.int32).astype(np.int64)
+    else:
+        dt = np.float16 if storage == "f16" else None
+        if dt is not None:
+            ai = np.asarray(a, np.float32).astype(np.float16).view(np.int16).astype(np.int64)
+            bi = np.asarray(b, np.float32).astype(np.float16).view(np.int16).astype(np.int64)
+        else:
+            ai = (np.asarray(a, np.float32).view(np.uint32) >> 16).astype(np.int64)
+            bi = (np.asarray(b, np.float32).view(np.uint32) >> 16).astype(np.int64)
+    return np.abs(ai - bi)
+
+
+def _compare(scene, signal, storage="f32", **kw):
+    core = _core()
+    tree = core.Octree.from_scene(scene, storage)
+    sig_d = torch.as_tensor(signal, device="cuda")
+    st = tree.refine(sig_d, **kw)
+    ex = tree.export()
+    tree.close()
+    if storage == "f32":
+        T = O.OracleTree.from_scene(scene, sigma=scene.sigma.astype(np.float64))
+    else:
+        T = O.OracleTree(scene.child, O.round_storage(scene.sigma.astype(np.float64), storage),
+                         O.round_storage(scene.sh.astype(np.float64), storage), scene.degree)
+    R = O.refine(T, signal, tau=kw.get("prune_tau", 1e-3), sample_frac=kw.get("sample_frac", 0.05),
+                 max_depth=kw.get("max_depth", 10), prune_le=kw.get("prune_le", True), storage=storage)
+    np.testing.assert_array_equal(ex["child"], R["child"])
+    np.testing.assert_array_equal(ex["depth"].astype(np.int32), R["depth"])
+    assert st["leaves_after"] == R["sigma"].shape[0]
+    assert st["merged"] == R["merged"] and st["subdivided"] == R["k"]
+    us = _ulps(ex["sigma"], R["sigma"], storage)
+    uh = _ulps(ex["sh"].reshape(-1), R["sh"].reshape(-1), storage)
+    assert us.max() <= 1 and uh.max() <= 1
+    return st, int((us > 0).sum() + (uh > 0).sum())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_refine_random_trees(seed):
+    s = synth.random_tree_scene(5, 2, seed=seed, p_split=0.5)
+    sig = _seeded_signal(s.n_leaves, seed)
+    st, n_ulp = _compare(s, sig, prune_tau=1e-3, sample_frac=0.07, max_depth=6)
+    print(f"seed {seed}: {st}, values off by 1 ulp: {n_ulp}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_refine_storage_types(storage):
+    s = synth.random_tree_scene(5, 3, seed=11, p_split=0.5)
+    sig = _seeded_signal(s.n_leaves, 12, 0.6)
+    st, n_ulp = _compare(s, sig, storage, prune_tau=1e-3, sample_frac=0.05, max_depth=7)
+    print(f"{storage}: {st}, values off by 1 ulp: {n_ulp}")
+
+
+def test_refine_ties_and_limits():
+    s = synth.uniform_scene(3, 1, 1.0, seed=4)
+    L = s.n_leaves
+    # every signal equal: top-k resolves by the lower leaf index
+    _compare(s, np.full(L, 0.5, np.float32), prune_tau=0.1, sample_frac=0.1, max_depth=4)
+    # exact tie at tau, both comparison senses
+    sig = np.full(L, 0.25, np.float32)
+    sig[::3] = 0.75
+    _compare(s, sig, prune_tau=0.25, sample_frac=0.02, max_depth=4, prune_le=True)
+    _compare(s, sig, prune_tau=0.25, sample_frac=0.02, max_depth=4, prune_le=False)
+    # k larger than the candidate set; max_depth excluding everything; k = 0
+    _compare(s, _seeded_signal(L, 3), prune_tau=0.5, sample_frac=1.0, max_depth=4)
+    _compare(s, _seeded_signal(L, 3), prune_tau=0.0, sample_frac=0.5, max_depth=3)
+    _compare(s, _seeded_signal(L, 3), prune_tau=1e-3, sample_frac=0.0, max_depth=4)
+
+
+def test_refine_degenerate_trees():
+    # everything prunes down to a root leaf
+    s = synth.uniform_scene(1, 2, 1.0, seed=5)
+    st, _ = _compare(s, np.zeros(8, np.float32), prune_tau=0.0, sample_frac=0.0, max_depth=3)
+    assert st["leaves_after"] == 1 and st["internal_after"] == 0
+    # a root leaf subdivides
+    r = synth.uniform_scene(0, 1, 2.0, seed=6)
+    st, _ = _compare(r, np.array([0.7], np.float32), prune_tau=0.1, sample_frac=1.0, max_depth=2)
+    assert st["leaves_after"] == 8
+
+
+def test_refine_then_render_matches_oracle():
+    """Refined trees stay renderable: subdivision leaves every pixel unchanged."""
+    core = _core()
+    s = synth.config1_scene()
+    tree = core.Octree.from_scene(s)
+    cams = synth.cameras([(30.0, 20.0, 4.0, 48, 48)])
+    rays = core.Rays.cameras(cams)
+    before = tree.render(rays, t_stop=0.0).cpu().numpy()
+    sig = torch.as_tensor(_seeded_signal(s.n_leaves, 9, 0.0) + 0.5, device="cuda")  # nothing prunes
+    st = tree.refine(sig, prune_tau=1e-3, sample_frac=0.2, max_depth=6)
+    assert st["subdivided"] > 0 and st["merged"] == 0
+    after = tree.render(rays, t_stop=0.0).cpu().numpy()
+    np.testing.assert_allclose(after, before, atol=1e-5)
+    tree.close()
+
+
+def test_refine_end_to_end_signal_from_oracle_render():
+    """GPU signal -> GPU refine versus oracle signal -> oracle refine; leaves whose
+    signal is within 1e-5 of tau or of the k-th key may differ (counted)."""
+    core = _core()
+    s = synth.config1_scene()
+    views = synth.config4_views(n=6)
+    tree = core.Octree.from_scene(s)
+    sig = torch.zeros(tree.n_leaves, device="cuda")
+    tree.accumulate_signal(core.Rays.cameras(views), sig)
+    g_sig = sig.cpu().numpy()
+    o, d = O.camera_rays(views)
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    ref = O.render(T, o, d, signal=True)
+    o_sig = ref["sig"].astype(np.float32)
+    tau, frac = 1e-3, 0.05
+    st = tree.refine(sig, prune_tau=tau, sample_frac=frac, max_depth=6)
+    ex = tree.export()
+    R = O.refine(T, o_sig, tau=tau, sample_frac=frac, max_depth=6)
+    # near-decision leaves: close to tau or to the k-th candidate signal
+    cand = np.sort(o_sig[o_sig > tau])[::-1]
+    k = int(np.floor(frac * s.n_leaves))
+    kth = cand[min(k, cand.shape[0]) - 1]
+    near = (np.abs(o_sig - tau) < 1e-5) | (np.abs(o_sig - kth) < 1e-5)
+    print(f"end-to-end: gpu {st}, oracle L'={R['sigma'].shape[0]}, near-decision leaves {near.sum()}")
+    if near.sum() == 0:
+        np.testing.assert_array_equal(ex["child"], R["child"])
+    tree.close()
+
+
+def test_refine_config2_full_size():
+    """The 3.54M-leaf octree with a seeded signal: top 5%, tau = 1e-3, max depth 10."""
+    s = synth.config2_scene()
+    sig = _seeded_signal(s.n_leaves, 21, 0.4)
+    st, n_ulp = _compare(s, sig, prune_tau=1e-3, sample_frac=0.05, max_depth=10)
+    print(f"config2 refine: {st}, values off by 1 ulp: {n_ulp}")
