@@ -201,7 +201,7 @@ typedef struct {
     float sample_frac;   /* k = floor(sample_frac * n_leaves) leaves to subdivide */
     int32_t prune_le;
     int32_t max_depth;   /* only leaves shallower than this are subdivided */
-    int32_t recursive;   /* 1: repeat merging up the hierarchy (merged signal = max of children) */
+    int32_t recursive;   /* 1: repeat merging up the hierarchy (the paper's "(R)" option) */
     int32_t reserved;
 } dot_refine_params;
 
@@ -217,6 +217,11 @@ typedef struct {
  *   prune (Eq. 3): an internal node whose 8 children are all leaves and all
  *     selected becomes a leaf holding the mean of the children's raw sigma and
  *     SH, rounded once to the storage type;
+ *   recursive pruning (Sec. 3.2, Alg. 1 with rec): merging repeats, a merged
+ *     node's signal being the max of its children's, until no group is
+ *     selected -- every node whose subtree leaves are all selected becomes a
+ *     leaf; its value is Eq. 3 applied level by level (mean of the 8
+ *     children's values, each rounded to the storage type when formed);
  *   sample (Eq. 4): among leaves not selected for pruning and shallower than
  *     max_depth, the k with the largest signal (ties: lower leaf index first)
  *     become internal nodes whose 8 children copy the parent's values.
@@ -262,6 +267,40 @@ int dot_export(dot_tree_t tree, int32_t *child, float *sigma, float *sh, uint8_t
  */
 int dot_render_stats(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                      int64_t counts[4], void *stream);
+
+/*
+ * Batched rendering for serving: many render requests, over several resident
+ * trees, in one launch.  A job renders the 8x8 pixel tiles
+ * [tile_begin, tile_begin + tile_count) of one request's image (tiles are
+ * numbered row-major over ceil(width/8) x ceil(height/8)); a large request can
+ * therefore be split over several launches and mixed with others.  The image
+ * of each pixel is exactly what dot_render computes for the same camera and
+ * options (Eq. 1-2), independent of the rest of the batch.
+ */
+typedef struct {
+    dot_tree_t tree;         /* resident tree */
+    const dot_camera *cam;   /* DEVICE pointer to one camera record */
+    float *rgb_out;          /* DEVICE float [height][width][3] */
+    int32_t width, height;
+    int64_t tile_begin, tile_count;
+    float bg[3];
+    float t_stop;
+} dot_render_job;
+
+/* dot_render_jobs_workspace -- bytes of device workspace a launch of n_jobs needs. */
+size_t dot_render_jobs_workspace(int32_t n_jobs);
+
+/*
+ * dot_render_jobs -- one persistent launch over all tiles of `jobs` (host
+ *  array, read during the call).  `workspace` is a DEVICE buffer of at least
+ *  dot_render_jobs_workspace(n_jobs) bytes owned by the caller; the call
+ *  writes the job table into it on `stream`, so it may be reused by the next
+ *  call on the same stream, but not concurrently on another stream.
+ *  Errors: DOT_EINVAL for a NULL tree/camera/output, a tile range outside the
+ *  image, or a small workspace.
+ */
+int dot_render_jobs(const dot_render_job *jobs, int32_t n_jobs, void *workspace, size_t workspace_bytes,
+                    void *stream);
 
 /* dot_last_error -- message of the last failure on this thread ("" if none). */
 const char *dot_last_error(void);

@@ -73,6 +73,12 @@ class dot_adam_params(C.Structure):
                 ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int32)]
 
 
+class dot_render_job(C.Structure):
+    _fields_ = [("tree", C.c_void_p), ("cam", C.c_void_p), ("rgb_out", C.c_void_p), ("width", C.c_int32),
+                ("height", C.c_int32), ("tile_begin", C.c_int64), ("tile_count", C.c_int64),
+                ("bg", C.c_float * 3), ("t_stop", C.c_float)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/dot.h
 SIGNATURES = {
     "dot_build": (C.c_int, [C.POINTER(dot_tree_desc), C.c_int32, C.POINTER(dot_allocator), C.c_void_p,
@@ -93,6 +99,8 @@ SIGNATURES = {
     "dot_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_render_stats": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                    C.POINTER(C.c_int64), C.c_void_p]),
+    "dot_render_jobs_workspace": (C.c_size_t, [C.c_int32]),
+    "dot_render_jobs": (C.c_int, [C.POINTER(dot_render_job), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dot_last_error": (C.c_char_p, []),
 }
 

@@ -447,4 +447,14 @@ int dot_refine(dot_tree_t t, const float* signal, const dot_refine_params* p, do
     return refine_tree(*t, signal, *p, stats, static_cast<hipStream_t>(stream));
 }
 
+size_t dot_render_jobs_workspace(int32_t n_jobs) { return jobs_workspace_bytes(n_jobs < 0 ? 0 : n_jobs); }
+
+int dot_render_jobs(const dot_render_job* jobs, int32_t n_jobs, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+    if (n_jobs < 0) return fail(DOT_EINVAL, "dot_render_jobs: n_jobs < 0");
+    if (n_jobs == 0) return DOT_OK;
+    if (!jobs || !workspace) return fail(DOT_EINVAL, "dot_render_jobs: jobs and workspace are required");
+    return launch_render_jobs(jobs, n_jobs, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -2,7 +2,11 @@
 // both driven by the same per-leaf signal).
 //
 //   mark    an internal node merges iff its 8 children are leaves and all are
-//           selected for pruning (signal <= tau, or < tau);
+//           selected for pruning (signal <= tau, or < tau); with recursive
+//           pruning (the paper's "(R)" option) merging repeats up the
+//           hierarchy, which ends with every node whose subtree leaves are all
+//           selected merged: the subtree's leaves are a contiguous DFS range,
+//           so one prefix count of unselected leaves decides every node;
 //   select  exact top-k of the 64-bit keys (~ord(signal) << 32 | leaf) over
 //           the sampling candidates by an 8-pass MSD radix select, so ties in
 //           signal go to the lower leaf index;
@@ -47,32 +51,70 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     GRID_STRIDE(i, n) p[i] = v;
 }
 
-// slot of each leaf in its parent's child list: parent * 8 + octant (-1 for a root leaf)
-__global__ void k_leaf_slot(const int32_t* __restrict__ child, int64_t I, int32_t* __restrict__ slot) {
+// first / last leaf of each internal node's subtree and the node's depth
+__global__ void k_node_meta(const int32_t* __restrict__ child, int64_t I, const uint8_t* __restrict__ leaf_depth,
+                            int32_t* __restrict__ first, int32_t* __restrict__ last, int32_t* __restrict__ ndepth) {
+    GRID_STRIDE(p, I) {
+        int steps = 1;
+        int32_t e = child[p * 8];
+        while (e >= 0) {
+            e = child[(int64_t)e * 8];
+            ++steps;
+        }
+        first[p] = -1 - e;
+        ndepth[p] = (int32_t)leaf_depth[-1 - e] - steps;
+        e = child[p * 8 + 7];
+        while (e >= 0) e = child[(int64_t)e * 8 + 7];
+        last[p] = -1 - e;
+    }
+}
+
+__global__ void k_node_parent(const int32_t* __restrict__ child, int64_t I, int32_t* __restrict__ parent) {
     GRID_STRIDE(j, I * 8) {
         int32_t e = child[j];
-        if (e < 0) slot[-1 - e] = (int32_t)j;
+        if (e >= 0) parent[e] = (int32_t)(j >> 3);
     }
 }
 
-__global__ void k_first_leaf(const int32_t* __restrict__ child, int64_t I, int32_t* __restrict__ first) {
-    GRID_STRIDE(p, I) {
-        int32_t e = child[p * 8];
-        while (e >= 0) e = child[(int64_t)e * 8];
-        first[p] = -1 - e;
-    }
+__global__ void k_unselected(const float* __restrict__ sig, int64_t L, float tau, int le, uint32_t* __restrict__ u) {
+    GRID_STRIDE(l, L) u[l] = selected(sig[l], tau, le) ? 0u : 1u;
 }
 
-__global__ void k_mark_merge(const int32_t* __restrict__ child, int64_t I, const float* __restrict__ sig,
-                             float tau, int le, uint32_t* __restrict__ survive) {
+// merge roots and survivors.  all_sel[p]: no unselected leaf in [first, last].
+__global__ void k_mark_merge(const int32_t* __restrict__ child, int64_t I, const int32_t* __restrict__ first,
+                             const int32_t* __restrict__ last, const int32_t* __restrict__ parent,
+                             const uint32_t* __restrict__ unsel, const uint32_t* __restrict__ pre_unsel,
+                             int recursive, uint32_t* __restrict__ survive, uint32_t* __restrict__ root,
+                             uint32_t* __restrict__ need) {
     GRID_STRIDE(p, I) {
-        bool all = true;
+        auto all_sel = [&](int64_t q) {
+            int32_t f = first[q], l = last[q];
+            return pre_unsel[l] + unsel[l] - pre_unsel[f] == 0u;
+        };
+        bool as = all_sel(p);
+        bool r;
+        if (recursive) {
+            r = as && (p == 0 || !all_sel(parent[p]));
+            survive[p] = as ? 0u : 1u;
+            need[p] = as ? 1u : 0u;
+        } else {
+            bool leaves = true;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            int32_t e = child[p * 8 + o];
-            if (e >= 0 || !selected(sig[-1 - e], tau, le)) all = false;
+            for (int o = 0; o < 8; ++o) leaves &= child[p * 8 + o] < 0;
+            r = as && leaves;
+            survive[p] = r ? 0u : 1u;
+            need[p] = r ? 1u : 0u;
         }
-        survive[p] = all ? 0u : 1u;
+        root[p] = r ? 1u : 0u;
+    }
+}
+
+// every leaf under a merge root records the root (roots' ranges are disjoint)
+__global__ void k_cover(int64_t I, const uint32_t* __restrict__ root, const int32_t* __restrict__ first,
+                        const int32_t* __restrict__ last, int32_t* __restrict__ cover) {
+    GRID_STRIDE(p, I) {
+        if (!root[p]) continue;
+        for (int32_t l = first[p]; l <= last[p]; ++l) cover[l] = (int32_t)p;
     }
 }
 
@@ -140,17 +182,16 @@ __global__ void k_sel_digit(SelState* st, int shift, int first, long long k_req)
 }
 
 // new-leaf counts per old leaf, and the split flags
-__global__ void k_leaf_counts(int64_t L, const int32_t* __restrict__ slot, const uint32_t* __restrict__ survive,
+__global__ void k_leaf_counts(int64_t L, const int32_t* __restrict__ cover, const int32_t* __restrict__ first,
                               const uint64_t* __restrict__ keys, const SelState* __restrict__ st,
                               uint32_t* __restrict__ cnt, uint32_t* __restrict__ split) {
     const unsigned long long kstar = st->prefix;
     const bool any = st->k_eff > 0;
     GRID_STRIDE(l, L) {
-        int32_t s = slot[l];
-        bool merged = s >= 0 && survive[s >> 3] == 0u;
+        int32_t c = cover[l];
         bool sp = any && keys[l] != ~0ull && keys[l] <= kstar;
         split[l] = sp ? 1u : 0u;
-        cnt[l] = merged ? ((s & 7) == 0 ? 1u : 0u) : (sp ? 8u : 1u);
+        cnt[l] = c >= 0 ? (first[c] == (int32_t)l ? 1u : 0u) : (sp ? 8u : 1u);
     }
 }
 
@@ -315,34 +356,61 @@ __device__ __forceinline__ void cp_elem(const void* src, int64_t i, void* dst, i
         static_cast<uint16_t*>(dst)[j] = static_cast<const uint16_t*>(src)[i];
 }
 
+// Values of merged nodes, one depth level per launch from the deepest up: the
+// mean of the 8 children's rows (leaf rows, or node rows formed by the previous
+// launch), summed pairwise in FP64 and rounded once to the storage type.
+// Row layout of nval: [sigma, sh[0..stride)] per node, in the storage type.
 template <int DT>
-__global__ void k_emit_leaves(int64_t L, int nv, int stride, const int32_t* __restrict__ slot,
-                              const uint32_t* __restrict__ survive, const uint32_t* __restrict__ split,
-                              const uint32_t* __restrict__ nl, const uint8_t* __restrict__ depth,
-                              const void* __restrict__ sig, const void* __restrict__ sh, void* __restrict__ sig2,
-                              void* __restrict__ sh2, uint8_t* __restrict__ depth2) {
-    GRID_STRIDE(l, L) {
-        int32_t s = slot[l];
-        int64_t j = nl[l];
-        if (s >= 0 && survive[s >> 3] == 0u) {
-            if ((s & 7) != 0) continue;
-            // the 8 children of a merged node are the consecutive leaves l..l+7
-            auto mean8 = [&](const void* p, int64_t base, int64_t step) {
-                double v[8];
+__global__ void k_node_values(const int32_t* __restrict__ child, int64_t I, int depth,
+                              const int32_t* __restrict__ ndepth, const uint32_t* __restrict__ need, int nv,
+                              int stride, const void* __restrict__ sig, const void* __restrict__ sh,
+                              void* __restrict__ nval) {
+    const int row = stride + 1;
+    GRID_STRIDE(p, I) {
+        if (!need[p] || ndepth[p] != depth) continue;
+        int32_t e[8];
 #pragma unroll
-                for (int o = 0; o < 8; ++o) v[o] = ld_elem<DT>(p, base + o * step);
-                return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) * 0.125;
-            };
-            st_elem<DT>(sig2, j, mean8(sig, l, 1));
-            for (int c = 0; c < nv; ++c) st_elem<DT>(sh2, j * stride + c, mean8(sh, l * stride + c, stride));
-            for (int c = nv; c < stride; ++c) st_elem<DT>(sh2, j * stride + c, 0.0);
-            depth2[j] = (uint8_t)(depth[l] - 1);
+        for (int o = 0; o < 8; ++o) e[o] = child[p * 8 + o];
+        for (int c = -1; c < nv; ++c) {
+            double v[8];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                if (e[o] < 0) {
+                    int64_t l = -1 - e[o];
+                    v[o] = c < 0 ? ld_elem<DT>(sig, l) : ld_elem<DT>(sh, l * stride + c);
+                } else {
+                    v[o] = ld_elem<DT>(nval, (int64_t)e[o] * row + 1 + c);
+                }
+            }
+            double m = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) * 0.125;
+            st_elem<DT>(nval, p * row + 1 + c, m);
+        }
+        for (int c = nv; c < stride; ++c) st_elem<DT>(nval, p * row + 1 + c, 0.0);
+    }
+}
+
+template <int DT>
+__global__ void k_emit_leaves(int64_t L, int stride, const int32_t* __restrict__ cover,
+                              const int32_t* __restrict__ first, const int32_t* __restrict__ ndepth,
+                              const uint32_t* __restrict__ split, const uint32_t* __restrict__ nl,
+                              const uint8_t* __restrict__ depth, const void* __restrict__ sig,
+                              const void* __restrict__ sh, const void* __restrict__ nval, void* __restrict__ sig2,
+                              void* __restrict__ sh2, uint8_t* __restrict__ depth2) {
+    const int row = stride + 1;
+    GRID_STRIDE(l, L) {
+        int32_t c = cover[l];
+        int64_t j = nl[l];
+        if (c >= 0) {
+            if (first[c] != (int32_t)l) continue;
+            cp_elem<DT>(nval, (int64_t)c * row, sig2, j);
+            for (int k = 0; k < stride; ++k) cp_elem<DT>(nval, (int64_t)c * row + 1 + k, sh2, j * stride + k);
+            depth2[j] = (uint8_t)ndepth[c];
         } else {
             int reps = split[l] ? 8 : 1;
             uint8_t d = (uint8_t)(depth[l] + (split[l] ? 1 : 0));
             for (int r = 0; r < reps; ++r) {
                 cp_elem<DT>(sig, l, sig2, j + r);
-                for (int c = 0; c < stride; ++c) cp_elem<DT>(sh, l * stride + c, sh2, (j + r) * stride + c);
+                for (int k = 0; k < stride; ++k) cp_elem<DT>(sh, l * stride + k, sh2, (j + r) * stride + k);
                 depth2[j + r] = d;
             }
         }
@@ -387,11 +455,16 @@ hipError_t scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, ui
 }
 
 template <int DT>
-hipError_t launch_emit(int64_t L, int nv, int stride, const int32_t* slot, const uint32_t* survive,
-                       const uint32_t* split, const uint32_t* nl, const uint8_t* depth, const void* sig,
-                       const void* sh, void* sig2, void* sh2, uint8_t* depth2, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit_leaves<DT>, dim3(blocks_for(L)), dim3(TPB), 0, s, L, nv, stride, slot, survive, split,
-                       nl, depth, sig, sh, sig2, sh2, depth2);
+hipError_t launch_values_emit(const dot_tree& t, int64_t L, int64_t I, int nv, int stride, const int32_t* cover,
+                              const int32_t* first, const int32_t* ndepth, const uint32_t* need,
+                              const uint32_t* split, const uint32_t* nl, void* nval, void* sig2, void* sh2,
+                              uint8_t* depth2, hipStream_t s) {
+    if (I > 0)
+        for (int d = DOT_MAX_DEPTH - 1; d >= 0; --d)
+            hipLaunchKernelGGL(k_node_values<DT>, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, d, ndepth, need,
+                               nv, stride, t.sigma, t.sh, nval);
+    hipLaunchKernelGGL(k_emit_leaves<DT>, dim3(blocks_for(L)), dim3(TPB), 0, s, L, stride, cover, first, ndepth, split,
+                       nl, t.leaf_depth, t.sigma, t.sh, nval, sig2, sh2, depth2);
     return hipGetLastError();
 }
 
@@ -399,7 +472,6 @@ hipError_t launch_emit(int64_t L, int nv, int stride, const int32_t* slot, const
 
 int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st_out,
                 hipStream_t s) {
-    if (p.recursive) return fail(DOT_EUNSUPPORTED, "dot_refine: recursive pruning is not implemented");
     const int64_t L = t.n_leaves, I = t.n_internal;
     const int64_t k_req = (int64_t)std::floor((double)p.sample_frac * (double)L);
     if (L + 7 * k_req > (int64_t)INT32_MAX || I + k_req > (int64_t)INT32_MAX / 8)
@@ -407,11 +479,21 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
     const int nv = 3 * (t.degree + 1) * (t.degree + 1);
     const int stride = t.sh_stride;
     const int es = storage_bytes(t.storage);
+    const int rec = p.recursive ? 1 : 0;
 
     Temps tmp(t.alloc);
-    int32_t* slot = tmp.get<int32_t>(L);
     int32_t* first = tmp.get<int32_t>(I);
+    int32_t* last = tmp.get<int32_t>(I);
+    int32_t* ndepth = tmp.get<int32_t>(I);
+    int32_t* parent = tmp.get<int32_t>(I);
     uint32_t* survive = tmp.get<uint32_t>(I);
+    uint32_t* root = tmp.get<uint32_t>(I);
+    uint32_t* need = tmp.get<uint32_t>(I);
+    uint32_t* rank_int = tmp.get<uint32_t>(I);
+    void* nval = tmp.get<unsigned char>(std::max<int64_t>(I, 1) * (stride + 1) * es);
+    uint32_t* unsel = tmp.get<uint32_t>(L);
+    uint32_t* pre_unsel = tmp.get<uint32_t>(L);
+    int32_t* cover = tmp.get<int32_t>(L);
     uint64_t* keys = tmp.get<uint64_t>(L);
     SelState* sel = tmp.get<SelState>(1);
     uint32_t* cnt = tmp.get<uint32_t>(L);
@@ -420,22 +502,28 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
     uint32_t* rank_split = tmp.get<uint32_t>(L);
     uint32_t* hist_first = tmp.get<uint32_t>(L);
     uint32_t* cnt_le = tmp.get<uint32_t>(L);
-    uint32_t* rank_int = tmp.get<uint32_t>(I);
     uint32_t* bsum = tmp.get<uint32_t>((std::max(L, I) + SCAN_TILE - 1) / SCAN_TILE + 1);
-    uint32_t* tots = tmp.get<uint32_t>(4);
+    uint32_t* tots = tmp.get<uint32_t>(8);
     unsigned long long* totals = tmp.get<unsigned long long>(4);
     if (!tmp.ok) return fail(DOT_ENOMEM, "dot_refine: scratch allocation failed");
 
-    // 1. marks, keys
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, reinterpret_cast<uint32_t*>(slot), L,
+    // 1. tree metadata, merge marks, candidate keys
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, reinterpret_cast<uint32_t*>(cover), L,
                        0xffffffffu);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, hist_first, L, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(TPB), 0, s, tots, (int64_t)4, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(TPB), 0, s, tots, (int64_t)8, 0u);
+    hipLaunchKernelGGL(k_unselected, dim3(blocks_for(L)), dim3(TPB), 0, s, signal, L, p.prune_tau, p.prune_le, unsel);
+    hipError_t e = scan(unsel, pre_unsel, L, bsum, &tots[4], s);
+    if (e != hipSuccess) return hip_fail(e, "dot_refine: scan");
     if (I > 0) {
-        hipLaunchKernelGGL(k_leaf_slot, dim3(blocks_for(I * 8)), dim3(TPB), 0, s, t.child, I, slot);
-        hipLaunchKernelGGL(k_first_leaf, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, first);
-        hipLaunchKernelGGL(k_mark_merge, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, signal, p.prune_tau,
-                           p.prune_le, survive);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(TPB), 0, s, reinterpret_cast<uint32_t*>(parent), (int64_t)1,
+                           0xffffffffu);
+        hipLaunchKernelGGL(k_node_parent, dim3(blocks_for(I * 8)), dim3(TPB), 0, s, t.child, I, parent);
+        hipLaunchKernelGGL(k_node_meta, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, t.leaf_depth, first, last,
+                           ndepth);
+        hipLaunchKernelGGL(k_mark_merge, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, first, last, parent, unsel,
+                           pre_unsel, rec, survive, root, need);
+        hipLaunchKernelGGL(k_cover, dim3(blocks_for(I)), dim3(TPB), 0, s, I, root, first, last, cover);
     }
     hipLaunchKernelGGL(k_keys, dim3(blocks_for(L)), dim3(TPB), 0, s, signal, t.leaf_depth, L, p.prune_tau,
                        p.prune_le, p.max_depth, keys);
@@ -450,14 +538,14 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
         }
     }
     // 3. counts and scans
-    hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(L)), dim3(TPB), 0, s, L, slot, survive, keys, sel, cnt, split);
+    hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(L)), dim3(TPB), 0, s, L, cover, first, keys, sel, cnt, split);
     if (I > 0) hipLaunchKernelGGL(k_first_hist, dim3(blocks_for(I)), dim3(TPB), 0, s, I, survive, first, hist_first);
-    hipError_t e = scan(cnt, nl, L, bsum, &tots[0], s);
+    e = scan(cnt, nl, L, bsum, &tots[0], s);
     if (e == hipSuccess) e = scan(split, rank_split, L, bsum, &tots[1], s);
-    if (e == hipSuccess) e = scan(hist_first, cnt_le, L, bsum, &tots[2], s);  // exclusive; + hist -> inclusive
+    if (e == hipSuccess) e = scan(hist_first, cnt_le, L, bsum, &tots[2], s);
     if (e == hipSuccess && I > 0) e = scan(survive, rank_int, I, bsum, &tots[3], s);
     if (e != hipSuccess) return hip_fail(e, "dot_refine: scans");
-    // cnt_le must be inclusive: count of surviving nodes whose first leaf is <= l
+    // cnt_le becomes inclusive: surviving nodes whose first leaf is <= l
     hipLaunchKernelGGL(k_add_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, cnt_le, (const uint32_t*)hist_first, L);
     hipLaunchKernelGGL(k_totals, dim3(1), dim3(64), 0, s, L, I, nl, cnt, &tots[3], &tots[1], sel, totals);
     unsigned long long h_tot[4];
@@ -471,11 +559,14 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
     void* sig2 = t.alloc.get((size_t)L2 * es);
     void* sh2 = t.alloc.get((size_t)L2 * stride * es);
     uint8_t* depth2 = static_cast<uint8_t*>(t.alloc.get((size_t)L2));
-    if (!child2 || !sig2 || !sh2 || !depth2) {
+    auto drop_new = [&]() {
         t.alloc.put(child2);
         t.alloc.put(sig2);
         t.alloc.put(sh2);
         t.alloc.put(depth2);
+    };
+    if (!child2 || !sig2 || !sh2 || !depth2) {
+        drop_new();
         return fail(DOT_ENOMEM, "dot_refine: allocation of the refined planes failed");
     }
     if (I > 0)
@@ -483,20 +574,17 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
                            rank_int, rank_split, split, cnt_le, nl, child2);
     hipLaunchKernelGGL(k_child_split, dim3(blocks_for(L)), dim3(TPB), 0, s, L, split, rank_split, cnt_le, nl, child2);
     if (t.storage == DOT_F32)
-        e = launch_emit<DOT_F32>(L, nv, stride, slot, survive, split, nl, t.leaf_depth, t.sigma, t.sh, sig2, sh2,
-                                 depth2, s);
+        e = launch_values_emit<DOT_F32>(t, L, I, nv, stride, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
+                                        depth2, s);
     else if (t.storage == DOT_F16)
-        e = launch_emit<DOT_F16>(L, nv, stride, slot, survive, split, nl, t.leaf_depth, t.sigma, t.sh, sig2, sh2,
-                                 depth2, s);
+        e = launch_values_emit<DOT_F16>(t, L, I, nv, stride, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
+                                        depth2, s);
     else
-        e = launch_emit<DOT_BF16>(L, nv, stride, slot, survive, split, nl, t.leaf_depth, t.sigma, t.sh, sig2, sh2,
-                                  depth2, s);
+        e = launch_values_emit<DOT_BF16>(t, L, I, nv, stride, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
+                                         depth2, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        t.alloc.put(child2);
-        t.alloc.put(sig2);
-        t.alloc.put(sh2);
-        t.alloc.put(depth2);
+        drop_new();
         return hip_fail(e, "dot_refine: rebuild");
     }
     // 5. swap into the handle

@@ -5,57 +5,6 @@
 
 namespace dot {
 
-// Per-ray compositing state for the forward pass.  S is the optical depth so
-// far (log of the transmittance, kept in FP32), T = exp(-S).  A segment's
-// weight is w = T_i - T_{i+1} = T_i (1 - exp(-tau_i)).
-template <int DT, int DEG>
-struct FwdSeg {
-    static constexpr int K = (DEG + 1) * (DEG + 1);
-    const TreeView& tv;
-    const FwdArgs& a;
-    float Y[K];
-    float S = 0.f, T = 1.f;
-    float C[3] = {0.f, 0.f, 0.f};
-    int n = 0;
-    int fetched = 0;
-
-    __device__ FwdSeg(const TreeView& tv_, const FwdArgs& a_) : tv(tv_), a(a_) {}
-
-    __device__ __forceinline__ bool operator()(int leaf, float delta) {
-        float sg = fmaxf(load_sigma<DT>(tv.sigma, leaf), 0.f);
-        float tau = sg * delta;
-        ++n;
-        if (tau > 0.f) {
-            float Sn = S + tau;
-            float Tn = __expf(-Sn);
-            float w = fmaxf(T - Tn, 0.f);
-            float row[3 * K];
-            load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
-            ++fetched;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float x = 0.f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) x = fmaf(row[ch * K + k], Y[k], x);
-                C[ch] = fmaf(w, sigmoidf_(x), C[ch]);
-            }
-            if (a.signal) {
-                if (a.signal_mode == DOT_SIGNAL_MAX) {
-                    // non-negative floats order like their bit patterns; skip the
-                    // atomic when the stored value already dominates
-                    float cur = a.signal[leaf];
-                    if (w > cur) atomicMax(reinterpret_cast<unsigned int*>(&a.signal[leaf]), __float_as_uint(w));
-                } else {
-                    unsafeAtomicAdd(&a.signal[leaf], w);
-                }
-            }
-            S = Sn;
-            T = Tn;
-        }
-        return !(S > a.thr);
-    }
-};
-
 template <int DT, int DEG, bool STATS>
 __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(TreeView tv, RayBatch rb, FwdArgs a) {
     __shared__ int stack_lds[LAT * BLOCK];

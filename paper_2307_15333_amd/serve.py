@@ -1,0 +1,222 @@
+"""Continuous-batching render server over octrees resident in HBM.
+
+Requests (tree, camera, resolution) arrive over time.  Each scheduling
+iteration the server
+
+  1. admits arrived requests in arrival order while the HBM budget for output
+     images and the slot limit allow (a request larger than the whole budget is
+     rejected),
+  2. packs the next tiles of the admitted requests, oldest first, into one
+     batch of at most `max_tiles` 8x8 tiles -- a large image is split over
+     several batches, so requests that arrive while others run join the next
+     batch instead of waiting for whole images --
+  3. launches the batch as ONE persistent kernel (`dot_render_jobs`) over all
+     resident trees, keeping up to `max_inflight` batches queued on the stream
+     so the device never idles while the host packs the next one,
+  4. retires launches whose completion event has fired; a request completes
+     with the launch that rendered its last tile, and frees its slot and budget.
+
+Latency = completion time - arrival time (host clock, event-polled).  The
+image a request receives is independent of the batch it was packed into: every
+pixel runs the same per-ray code on the same tree and camera.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import time
+from collections import deque
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import core
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    tree: int
+    cam: np.ndarray          # one camera record (synth.CAMERA_DTYPE)
+    width: int
+    height: int
+    arrival: float           # seconds from the start of the run
+    bg: tuple = (1.0, 1.0, 1.0)
+    t_stop: float = 1e-4
+    # runtime state
+    n_tiles: int = 0
+    next_tile: int = 0
+    out: torch.Tensor | None = None
+    cam_dev: torch.Tensor | None = None
+    admitted: float = -1.0
+    done: float = -1.0
+
+    @property
+    def rays(self):
+        return self.width * self.height
+
+    @property
+    def out_bytes(self):
+        return self.rays * 12
+
+
+class Server:
+    def __init__(self, trees, out_budget_bytes=2 << 30, max_active=64, max_tiles=8192, max_inflight=2,
+                 device="cuda"):
+        self.trees = trees
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.budget = int(out_budget_bytes)
+        self.max_active = int(max_active)
+        self.max_tiles = int(max_tiles)
+        self.max_inflight = int(max_inflight)
+        self.used = 0
+        self.max_used = 0
+        self.ws_bytes = 0
+        self.ws = None
+
+    def _workspace(self, n_jobs):
+        need = int(self.lib.dot_render_jobs_workspace(n_jobs))
+        if need > self.ws_bytes:
+            self.ws = torch.empty(need * 2, dtype=torch.uint8, device=self.device)
+            self.ws_bytes = need * 2
+        return self.ws
+
+    def _admit(self, req, now):
+        req.n_tiles = ((req.width + 7) // 8) * ((req.height + 7) // 8)
+        req.next_tile = 0
+        req.out = torch.empty((req.height, req.width, 3), dtype=torch.float32, device=self.device)
+        raw = np.ascontiguousarray(np.asarray(req.cam).reshape(1)).view(np.uint8)
+        # pinned source, so the upload is queued on the stream without a host wait
+        req.cam_dev = torch.from_numpy(raw.copy()).pin_memory().to(self.device, non_blocking=True)
+        req.admitted = now
+        self.used += req.out_bytes
+        self.max_used = max(self.max_used, self.used)
+
+    def launch(self, batch):
+        """batch: list of (request, tile_begin, tile_count) -> one persistent launch."""
+        n = len(batch)
+        jobs = (L.dot_render_job * n)()
+        for i, (r, b, c) in enumerate(batch):
+            j = jobs[i]
+            j.tree = self.trees[r.tree].handle
+            j.cam = r.cam_dev.data_ptr()
+            j.rgb_out = r.out.data_ptr()
+            j.width, j.height = r.width, r.height
+            j.tile_begin, j.tile_count = b, c
+            for a in range(3):
+                j.bg[a] = float(r.bg[a])
+            j.t_stop = float(r.t_stop)
+        ws = self._workspace(n)
+        L.check(self.lib.dot_render_jobs(jobs, n, C.c_void_p(ws.data_ptr()), C.c_size_t(self.ws_bytes),
+                                         core._stream()))
+
+    def run(self, requests, duration=None, warmup=0.0, keep_outputs=False, on_complete=None):
+        """Serve `requests` (sorted by arrival) in real time.  Returns stats over
+        the requests that arrived at or after `warmup` seconds."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting, active, inflight = deque(), [], deque()
+        completed, rejected = [], []
+        t0 = time.perf_counter()
+        launches = 0
+        tiles_launched = 0
+        while pending or waiting or active or inflight:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # 1. admission by slots and HBM budget, in arrival order
+            while waiting and len(active) < self.max_active:
+                r = waiting[0]
+                if r.out_bytes > self.budget:
+                    rejected.append(waiting.popleft())
+                    continue
+                if self.used + r.out_bytes > self.budget:
+                    break
+                self._admit(waiting.popleft(), now)
+                active.append(r)
+            # 2-3. pack the next batch and launch it
+            if len(inflight) < self.max_inflight:
+                batch, finishing, room = [], [], self.max_tiles
+                for r in active:
+                    if room == 0:
+                        break
+                    left = r.n_tiles - r.next_tile
+                    if left == 0:
+                        continue
+                    c = min(left, room)
+                    batch.append((r, r.next_tile, c))
+                    r.next_tile += c
+                    room -= c
+                    if r.next_tile == r.n_tiles:
+                        finishing.append(r)
+                if batch:
+                    self.launch(batch)
+                    ev = torch.cuda.Event()
+                    ev.record()
+                    inflight.append((ev, finishing))
+                    launches += 1
+                    tiles_launched += self.max_tiles - room
+                    continue
+            # 4. retire finished launches in order
+            progressed = False
+            while inflight and inflight[0][0].query():
+                _, fin = inflight.popleft()
+                t_done = time.perf_counter() - t0
+                for r in fin:
+                    r.done = t_done
+                    active.remove(r)
+                    self.used -= r.out_bytes
+                    if on_complete is not None:
+                        on_complete(r)
+                    if not keep_outputs:
+                        r.out = None
+                        r.cam_dev = None
+                    completed.append(r)
+                progressed = True
+            if not progressed:
+                if pending and not waiting and not active and not inflight:
+                    dt = pending[0].arrival - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(min(dt, 0.002))
+                else:
+                    time.sleep(0.00005)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        meas = [r for r in completed if r.arrival >= warmup]
+        lat = np.array([r.done - r.arrival for r in meas]) * 1e3
+        rays = sum(r.rays for r in meas)
+        span = (max(r.done for r in meas) - min(r.arrival for r in meas)) if meas else 0.0
+        return {
+            "requests": len(meas), "rejected": len(rejected), "launches": launches,
+            "p50_ms": float(np.percentile(lat, 50)) if meas else None,
+            "p99_ms": float(np.percentile(lat, 99)) if meas else None,
+            "mean_ms": float(lat.mean()) if meas else None,
+            "max_ms": float(lat.max()) if meas else None,
+            "mrays_per_s": rays / span / 1e6 if span > 0 else None,
+            "req_per_s": len(meas) / span if span > 0 else None,
+            "wall_s": wall, "mean_tiles_per_launch": tiles_launched / max(launches, 1),
+            "max_budget_used": self.max_used, "budget": self.budget,
+        }
+
+
+RESOLUTIONS = [(128, 128), (256, 256), (512, 512), (800, 800), (1920, 1080)]
+
+
+def poisson_requests(n_trees, rate, duration, seed, resolutions=RESOLUTIONS, radius=4.0):
+    """Poisson arrivals at `rate` req/s over `duration` s; resolution, tree and a
+    camera on the radius-4 sphere drawn uniformly (seeded)."""
+    from . import synth
+    rng = np.random.default_rng(seed)
+    t, out, i = 0.0, [], 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        w, h = resolutions[rng.integers(len(resolutions))]
+        v = rng.normal(size=3)
+        v *= radius / np.linalg.norm(v)
+        cam = synth._camera_at(v, w, h, 40.0)
+        out.append(Request(rid=i, tree=int(rng.integers(n_trees)), cam=cam, width=w, height=h, arrival=t))
+        i += 1
+    return out

@@ -68,7 +68,7 @@ def sdf_torus_box(major=0.55, minor=0.18, half=0.3):
     return f
 
 
-def sdf_terrain_ellipsoids(seed=2, n_ell=20, octaves=6, amp=0.15, base=-0.35):
+def sdf_terrain_ellipsoids(seed=2, n_ell=20, octaves=6, amp=0.12, base=-0.35, r_lo=0.04, r_hi=0.2):
     """Noisy height-field terrain (z below h(x,y) is solid) unioned with ellipsoids.
 
     The ellipsoid distance is the usual first-order estimate (|p/r| - 1) min r.
@@ -77,7 +77,7 @@ def sdf_terrain_ellipsoids(seed=2, n_ell=20, octaves=6, amp=0.15, base=-0.35):
     theta = rng.uniform(0, 2 * np.pi, octaves)
     phase = rng.uniform(0, 2 * np.pi, octaves)
     centres = rng.uniform(-0.8, 0.8, (n_ell, 3))
-    radii = rng.uniform(0.05, 0.3, (n_ell, 3))
+    radii = rng.uniform(r_lo, r_hi, (n_ell, 3))
 
     def height(x, y):
         h = np.full_like(x, base)
@@ -88,9 +88,7 @@ def sdf_terrain_ellipsoids(seed=2, n_ell=20, octaves=6, amp=0.15, base=-0.35):
         return h
 
     def f(p):
-        d = p[..., 2] - height(p[..., 0], p[..., 1])
-        # a height field is not an exact distance; scale by the slope bound
-        d = d / 1.6
+        d = p[..., 2] - height(p[..., 0], p[..., 1])   # vertical distance to the surface
         for e in range(n_ell):
             q = (p - centres[e]) / radii[e]
             de = (np.linalg.norm(q, axis=-1) - 1.0) * radii[e].min()

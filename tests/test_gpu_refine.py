@@ -56,7 +56,8 @@ def _compare(scene, signal, storage="f32", **kw):
         T = O.OracleTree(scene.child, O.round_storage(scene.sigma.astype(np.float64), storage),
                          O.round_storage(scene.sh.astype(np.float64), storage), scene.degree)
     R = O.refine(T, signal, tau=kw.get("prune_tau", 1e-3), sample_frac=kw.get("sample_frac", 0.05),
-                 max_depth=kw.get("max_depth", 10), prune_le=kw.get("prune_le", True), storage=storage)
+                 max_depth=kw.get("max_depth", 10), prune_le=kw.get("prune_le", True),
+                 recursive=kw.get("recursive", False), storage=storage)
     np.testing.assert_array_equal(ex["child"], R["child"])
     np.testing.assert_array_equal(ex["depth"].astype(np.int32), R["depth"])
     assert st["leaves_after"] == R["sigma"].shape[0]
@@ -108,6 +109,20 @@ def test_refine_degenerate_trees():
     r = synth.uniform_scene(0, 1, 2.0, seed=6)
     st, _ = _compare(r, np.array([0.7], np.float32), prune_tau=0.1, sample_frac=1.0, max_depth=2)
     assert st["leaves_after"] == 8
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_refine_recursive(seed):
+    s = synth.random_tree_scene(5, 2, seed=20 + seed, p_split=0.45)
+    sig = _seeded_signal(s.n_leaves, seed, 0.8)
+    for storage in ("f32", "bf16"):
+        st, n_ulp = _compare(s, sig, storage, prune_tau=1e-3, sample_frac=0.03, max_depth=6, recursive=True)
+        print(f"recursive seed {seed} {storage}: {st}, 1-ulp values {n_ulp}")
+    # everything selected: the tree collapses to a root leaf holding the mean of means
+    u = synth.uniform_scene(3, 1, 1.0, seed=seed)
+    st, _ = _compare(u, np.zeros(u.n_leaves, np.float32), prune_tau=0.0, sample_frac=0.0, max_depth=4,
+                     recursive=True)
+    assert st["leaves_after"] == 1 and st["merged"] == 73
 
 
 def test_refine_then_render_matches_oracle():
