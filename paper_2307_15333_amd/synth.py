@@ -32,8 +32,32 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
+
+_CHUNK = 1 << 20
+
+
+def _workers():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(fn, n, out):
+    """out[s:e] = fn(s, e) over chunks, on a thread pool (NumPy releases the GIL)."""
+    spans = [(a, min(a + _CHUNK, n)) for a in range(0, n, _CHUNK)]
+
+    def run(se):
+        out[se[0]:se[1]] = fn(*se)
+
+    if len(spans) <= 1:
+        for se in spans:
+            run(se)
+    else:
+        with ThreadPoolExecutor(_workers()) as ex:
+            list(ex.map(run, spans))
+    return out
 
 # ----------------------------------------------------------------------------
 # Signed distance functions (FP64, vectorised over points [..., 3])
@@ -307,26 +331,32 @@ def _sdf_split(sdf, bbox_min, size, factor=2.0):
     def split(d, ijk):
         h = size / 2.0 ** d
         out = np.empty(ijk.shape[0], bool)
-        chunk = 1 << 22
-        for s in range(0, ijk.shape[0], chunk):
-            centres = bmin + (ijk[s:s + chunk] + 0.5) * h
-            out[s:s + chunk] = np.abs(sdf(centres)) < factor * h
-        return out
+        return _chunked(lambda a, b: np.abs(sdf(bmin + (ijk[a:b] + 0.5) * h)) < factor * h, ijk.shape[0], out)
 
     return split
 
 
 def _random_sh(L, degree, rng, dc_lo=0.0, dc_hi=1.0, std=0.1):
     """SH coefficients drawn directly in FP32 (the generator values are exactly
-    these FP32 numbers, so FP32 storage is lossless for SH)."""
+    these FP32 numbers, so FP32 storage is lossless for SH).  Leaves are drawn
+    in chunks of 2^20 from independent streams spawned from `rng` (chunk order
+    fixed), DC first then the higher orders within each chunk."""
     K = (degree + 1) ** 2
     sh = np.empty((L, 3, K), np.float32)
-    sh[:, :, 0] = np.float32(dc_lo) + np.float32(dc_hi - dc_lo) * rng.random((L, 3), dtype=np.float32)
-    if K > 1:
-        hi = rng.standard_normal((L, 3, K - 1), dtype=np.float32)
-        hi *= np.float32(std)
-        sh[:, :, 1:] = hi
-    return sh
+    n_chunks = (L + _CHUNK - 1) // _CHUNK
+    seeds = rng.bit_generator.seed_seq.spawn(n_chunks) if n_chunks else []
+
+    def fill(a, b):
+        r = np.random.default_rng(seeds[a // _CHUNK])
+        blk = np.empty((b - a, 3, K), np.float32)
+        blk[:, :, 0] = np.float32(dc_lo) + np.float32(dc_hi - dc_lo) * r.random((b - a, 3), dtype=np.float32)
+        if K > 1:
+            hi = r.standard_normal((b - a, 3, K - 1), dtype=np.float32)
+            hi *= np.float32(std)
+            blk[:, :, 1:] = hi
+        return blk
+
+    return _chunked(fill, L, sh)
 
 
 def make_scene(sdf, max_depth, degree, seed, sigma_peak=50.0, shell=0.05,
@@ -336,12 +366,9 @@ def make_scene(sdf, max_depth, degree, seed, sigma_peak=50.0, shell=0.05,
     h = size / 2.0 ** ld
     L = ld.shape[0]
     sigma = np.empty(L, np.float64)
-    chunk = 1 << 22
     bmin = np.asarray(bbox_min, np.float64)
-    for s in range(0, L, chunk):
-        centres = bmin + (lijk[s:s + chunk] + 0.5) * h[s:s + chunk, None]
-        v = sdf(centres)
-        sigma[s:s + chunk] = sigma_peak * np.exp(-(v / shell) ** 2)
+    _chunked(lambda a, b: sigma_peak * np.exp(-(sdf(bmin + (lijk[a:b] + 0.5) * h[a:b, None]) / shell) ** 2),
+             L, sigma)
     rng = np.random.default_rng(seed)
     sh = _random_sh(L, degree, rng)
     return Scene(child=child, leaf_depth=ld.astype(np.int32), leaf_ijk=lijk,
