@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-config3", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
     args = ap.parse_args()
@@ -202,7 +204,97 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
             tree.close()
         log(f"render {storage}: {kt * 1e3:.3f} ms, {mr:.1f} Mrays/s")
     res.update(train_step(torch, core, synth, args))
+    res.update(refine_pass(torch, core, synth, scene))
+    res.update(serving(torch, core, synth, scene, args))
+    if not args.no_config3:
+        res.update(config3_precision(torch, core, synth, args))
     return res
+
+
+def refine_pass(torch, core, synth, scene):
+    """Config 2 refinement: max-weight signal over 100 random 800x800 views,
+    then top 5% subdivided (max depth 10) and signal <= 1e-3 pruned."""
+    tree = core.Octree.from_scene(scene, "f32")
+    views = synth.config2_refine_views(100)
+    sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
+    n_rays = 0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for j in range(0, 100, 10):
+        r = core.Rays.cameras(views[j:j + 10])
+        tree.accumulate_signal(r, sig)
+        n_rays += r.n_rays
+    torch.cuda.synchronize()
+    t_sig = time.perf_counter() - t
+    t = time.perf_counter()
+    st = tree.refine(sig, prune_tau=1e-3, sample_frac=0.05, max_depth=10)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t
+    tree.close()
+    log(f"refine: signal over {n_rays / 1e6:.0f}M rays {t_sig * 1e3:.1f} ms ({n_rays / t_sig / 1e6:.0f} Mrays/s); "
+        f"refine {t_ref * 1e3:.1f} ms {st}")
+    return {"signal_100views_ms": round(t_sig * 1e3, 2), "signal_mrays": round(n_rays / t_sig / 1e6, 1),
+            "refine_ms": round(t_ref * 1e3, 2), "refine_stats": st}
+
+
+def serving(torch, core, synth, c2_scene, args):
+    """Config 5: four resident FP16 trees (two config-1 size, two config-2 size),
+    Poisson arrivals at 200 req/s, resolutions uniform over {128^2, 256^2, 512^2,
+    800^2, 1920x1080}, continuous batching; latency percentiles after a warm-up."""
+    from paper_2307_15333_amd import serve
+    import dataclasses
+    s1a = synth.config1_scene()
+    s1b = synth.make_scene(synth.sdf_sphere(0.5), 5, 2, seed=40)
+    rng = np.random.default_rng(41)
+    sh_b = c2_scene.sh32.copy()
+    sh_b[:, :, 1:] = (rng.standard_normal(sh_b[:, :, 1:].shape, dtype=np.float32) * np.float32(0.1))
+    s2b = dataclasses.replace(c2_scene, sh32=sh_b)
+    trees = [core.Octree.from_scene(x, "f16") for x in (s1a, s1b, c2_scene, s2b)]
+    warm = 2.0
+    reqs = serve.poisson_requests(4, rate=200.0, duration=warm + args.serve_seconds, seed=4)
+    srv = serve.Server(trees, out_budget_bytes=2 << 30, max_tiles=16384)
+    st = srv.run(reqs, warmup=warm)
+    for t in trees:
+        t.close()
+    offered = sum(r.rays for r in reqs if r.arrival >= warm) / args.serve_seconds / 1e6
+    log(f"serving: {st['requests']} requests, p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
+        f"{st['mrays_per_s']:.0f} Mrays/s (offered {offered:.0f}), {st['launches']} launches")
+    return {"serve_p50_ms": round(st["p50_ms"], 3), "serve_p99_ms": round(st["p99_ms"], 3),
+            "serve_mean_ms": round(st["mean_ms"], 3), "serve_mrays": round(st["mrays_per_s"], 1),
+            "serve_offered_mrays": round(offered, 1), "serve_req_per_s": round(st["req_per_s"], 1),
+            "serve_requests": st["requests"], "serve_seconds": args.serve_seconds,
+            "serve_launches": st["launches"]}
+
+
+def config3_precision(torch, core, synth, args):
+    """Config 3: 19M-leaf terrain + ellipsoids octree, 4 views at 1920x1080,
+    leaves stored in FP32 / FP16 / BF16; throughput per dtype and error against
+    the FP64 oracle on the generator values (4096 sampled rays)."""
+    from oracle import oracle as O
+    t0 = time.time()
+    s = synth.config3_scene()
+    cams = synth.config3_cameras()
+    log(f"config3 scene: {s.n_leaves} leaves ({time.time() - t0:.0f}s)")
+    rays = core.Rays.cameras(cams)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(rays.n_rays, 4096, replace=False)
+    npx = 1920 * 1080
+    o, d = O.camera_rays(cams, (idx // npx).astype(np.int32), (idx % npx).astype(np.int32))
+    ref = O.render(O.OracleTree.from_scene(s), o, d)
+    out = {"config3_leaves": s.n_leaves}
+    for storage in ("f32", "f16", "bf16"):
+        tree = core.Octree.from_scene(s, storage)
+        rgb = tree.render(rays)
+        kt = time_kernel(lambda: tree.render(rays), 3, torch)
+        g = rgb.cpu().numpy()[idx].astype(np.float64)
+        e = np.minimum(np.abs(g - ref["rgb"]).max(1),
+                       np.minimum(np.abs(g - ref["rgb_early"]).max(1), np.abs(g - ref["rgb_late"]).max(1)))
+        out[f"config3_{storage}"] = {"mrays": round(rays.n_rays / kt / 1e6, 1), "err_max": float(e.max()),
+                                     "err_p99": float(np.quantile(e, 0.99)), "err_mean": float(e.mean())}
+        log(f"config3 {storage}: {rays.n_rays / kt / 1e6:.0f} Mrays/s, err max {e.max():.2e} "
+            f"p99 {np.quantile(e, 0.99):.2e} mean {e.mean():.2e}")
+        tree.close()
+    return out
 
 
 def train_step(torch, core, synth, args):
