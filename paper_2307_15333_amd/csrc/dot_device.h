@@ -329,16 +329,18 @@ struct FwdSeg {
     __device__ FwdSeg(const TreeView& tv_, const FwdArgs& a_) : tv(tv_), a(a_) {}
 
     __device__ __forceinline__ bool operator()(int leaf, float delta) {
+        // sigma and the SH row are requested together (one memory round trip);
+        // a leaf with sigma^ delta = 0 contributes w = 0
         float sg = fmaxf(load_sigma<DT>(tv.sigma, leaf), 0.f);
+        float row[3 * K];
+        load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
         float tau = sg * delta;
         ++n;
-        if (tau > 0.f) {
+        fetched += tau > 0.f;
+        {
             float Sn = S + tau;
             float Tn = __expf(-Sn);
             float w = fmaxf(T - Tn, 0.f);
-            float row[3 * K];
-            load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
-            ++fetched;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 float x = 0.f;
