@@ -332,8 +332,24 @@ struct FwdSeg {
         // sigma and the SH row are requested together (one memory round trip);
         // a leaf with sigma^ delta = 0 contributes w = 0
         float sg = fmaxf(load_sigma<DT>(tv.sigma, leaf), 0.f);
-        float row[3 * K];
-        load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
+        // BF16 rows stay packed in registers and each coefficient is widened in
+        // the dot product (FP16 rows stay packed through mixed-precision FMAs)
+        constexpr int NW = (3 * K + 1) / 2;
+        float row[DT == DOT_BF16 ? 1 : 3 * K];
+        uint32_t packed[DT == DOT_BF16 ? NW : 1];
+        if constexpr (DT == DOT_BF16) {
+            const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(tv.sh) + (int64_t)leaf * row_stride<DT>(3 * K));
+#pragma unroll
+            for (int c = 0; c < (NW + 3) / 4; ++c) {
+                uint4 v = p[c];
+                if (4 * c + 0 < NW) packed[4 * c + 0] = v.x;
+                if (4 * c + 1 < NW) packed[4 * c + 1] = v.y;
+                if (4 * c + 2 < NW) packed[4 * c + 2] = v.z;
+                if (4 * c + 3 < NW) packed[4 * c + 3] = v.w;
+            }
+        } else {
+            load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
+        }
         float tau = sg * delta;
         ++n;
         fetched += tau > 0.f;
@@ -345,7 +361,17 @@ struct FwdSeg {
             for (int ch = 0; ch < 3; ++ch) {
                 float x = 0.f;
 #pragma unroll
-                for (int k = 0; k < K; ++k) x = fmaf(row[ch * K + k], Y[k], x);
+                for (int k = 0; k < K; ++k) {
+                    float cf;
+                    if constexpr (DT == DOT_BF16) {
+                        int i = ch * K + k;
+                        uint32_t wv = packed[i >> 1];
+                        cf = __uint_as_float((i & 1) ? (wv & 0xffff0000u) : (wv << 16));
+                    } else {
+                        cf = row[ch * K + k];
+                    }
+                    x = fmaf(cf, Y[k], x);
+                }
                 C[ch] = fmaf(w, sigmoidf_(x), C[ch]);
             }
             if (a.signal) {
