@@ -189,8 +189,14 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  rgb_fwd, grad_rgb: DEVICE float [n][3]; nseg: DEVICE int32 [n] from dot_render
  *  with the same tree, rays and opts.  grad_sigma: DEVICE float [n_leaves],
  *  grad_sh: DEVICE float [n_leaves][3][K] (dense); both accumulated into (+=),
- *  the caller zeroes them.  Accumulation uses FP32 atomics, so the last bits
- *  depend on scheduling.
+ *  the caller zeroes them.  Contributions are grouped into per-leaf buckets
+ *  (a counting pass, a prefix scan, a pass that writes each segment's
+ *  gradient row into its leaf's bucket, then per-leaf column sums), which
+ *  needs device scratch of (1+3K) floats per contributing segment from the
+ *  tree's allocator and synchronises `stream` once to size it; beyond 8 GiB of
+ *  scratch, or if it cannot be allocated, the terms go straight to the
+ *  arrays with FP32 atomics.  Summation order, hence the last bits, depends
+ *  on scheduling.
  */
 int dot_render_backward(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                         const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,

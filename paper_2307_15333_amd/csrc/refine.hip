@@ -206,83 +206,6 @@ __global__ void k_first_hist(int64_t I, const uint32_t* __restrict__ survive, co
     }
 }
 
-// ---- exclusive prefix scan of uint32 (three passes over 4096-element tiles) ----
-constexpr int SCAN_ITEMS = 16;
-constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
-
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& total) {
-    __shared__ uint32_t wsum[TPB / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    uint32_t base = 0;
-    total = 0;
-#pragma unroll
-    for (int j = 0; j < TPB / 64; ++j) {
-        if (j < w) base += wsum[j];
-        total += wsum[j];
-    }
-    __syncthreads();
-    return base + x - v;
-}
-
-__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ bsum) {
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    uint32_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int64_t i = base + (int64_t)j * TPB + threadIdx.x;
-        if (i < n) acc += in[i];
-    }
-    uint32_t total;
-    block_exclusive_scan(acc, total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
-// single block: exclusive scan of the block sums in place; total into *tot
-__global__ void k_scan_bsums(uint32_t* __restrict__ bsum, int64_t nb, uint32_t* __restrict__ tot) {
-    const int64_t per = (nb + TPB - 1) / TPB;
-    const int64_t b0 = threadIdx.x * per;
-    uint32_t acc = 0;
-    for (int64_t i = b0; i < b0 + per && i < nb; ++i) acc += bsum[i];
-    uint32_t total;
-    uint32_t off = block_exclusive_scan(acc, total);
-    for (int64_t i = b0; i < b0 + per && i < nb; ++i) {
-        uint32_t v = bsum[i];
-        bsum[i] = off;
-        off += v;
-    }
-    if (threadIdx.x == 0) *tot = total;
-}
-
-__global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ bsum,
-                             uint32_t* __restrict__ out) {
-    // each thread owns SCAN_ITEMS consecutive elements of the tile
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    uint32_t v[SCAN_ITEMS];
-    uint32_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int64_t i = base + j;
-        v[j] = i < n ? in[i] : 0u;
-        acc += v[j];
-    }
-    uint32_t total;
-    uint32_t off = block_exclusive_scan(acc, total) + bsum[blockIdx.x];
-#pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int64_t i = base + j;
-        if (i < n) out[i] = off;
-        off += v[j];
-    }
-}
-
 // ---- rebuild ----
 __global__ void k_child_internal(const int32_t* __restrict__ child, int64_t I, const uint32_t* __restrict__ survive,
                                  const int32_t* __restrict__ first, const uint32_t* __restrict__ rank_int,
@@ -445,15 +368,6 @@ struct Temps {
     }
 };
 
-hipError_t scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum);
-    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(TPB), 0, s, bsum, nb, tot);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum, out);
-    return hipGetLastError();
-}
-
 template <int DT>
 hipError_t launch_values_emit(const dot_tree& t, int64_t L, int64_t I, int nv, int stride, const int32_t* cover,
                               const int32_t* first, const int32_t* ndepth, const uint32_t* need,
@@ -502,7 +416,7 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
     uint32_t* rank_split = tmp.get<uint32_t>(L);
     uint32_t* hist_first = tmp.get<uint32_t>(L);
     uint32_t* cnt_le = tmp.get<uint32_t>(L);
-    uint32_t* bsum = tmp.get<uint32_t>((std::max(L, I) + SCAN_TILE - 1) / SCAN_TILE + 1);
+    uint32_t* bsum = tmp.get<uint32_t>(scan_scratch_elems(std::max(L, I)));
     uint32_t* tots = tmp.get<uint32_t>(8);
     unsigned long long* totals = tmp.get<unsigned long long>(4);
     if (!tmp.ok) return fail(DOT_ENOMEM, "dot_refine: scratch allocation failed");
@@ -513,7 +427,7 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, hist_first, L, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(TPB), 0, s, tots, (int64_t)8, 0u);
     hipLaunchKernelGGL(k_unselected, dim3(blocks_for(L)), dim3(TPB), 0, s, signal, L, p.prune_tau, p.prune_le, unsel);
-    hipError_t e = scan(unsel, pre_unsel, L, bsum, &tots[4], s);
+    hipError_t e = scan_u32(unsel, pre_unsel, L, bsum, &tots[4], s);
     if (e != hipSuccess) return hip_fail(e, "dot_refine: scan");
     if (I > 0) {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(TPB), 0, s, reinterpret_cast<uint32_t*>(parent), (int64_t)1,
@@ -540,10 +454,10 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
     // 3. counts and scans
     hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(L)), dim3(TPB), 0, s, L, cover, first, keys, sel, cnt, split);
     if (I > 0) hipLaunchKernelGGL(k_first_hist, dim3(blocks_for(I)), dim3(TPB), 0, s, I, survive, first, hist_first);
-    e = scan(cnt, nl, L, bsum, &tots[0], s);
-    if (e == hipSuccess) e = scan(split, rank_split, L, bsum, &tots[1], s);
-    if (e == hipSuccess) e = scan(hist_first, cnt_le, L, bsum, &tots[2], s);
-    if (e == hipSuccess && I > 0) e = scan(survive, rank_int, I, bsum, &tots[3], s);
+    e = scan_u32(cnt, nl, L, bsum, &tots[0], s);
+    if (e == hipSuccess) e = scan_u32(split, rank_split, L, bsum, &tots[1], s);
+    if (e == hipSuccess) e = scan_u32(hist_first, cnt_le, L, bsum, &tots[2], s);
+    if (e == hipSuccess && I > 0) e = scan_u32(survive, rank_int, I, bsum, &tots[3], s);
     if (e != hipSuccess) return hip_fail(e, "dot_refine: scans");
     // cnt_le becomes inclusive: surviving nodes whose first leaf is <= l
     hipLaunchKernelGGL(k_add_u32, dim3(blocks_for(L)), dim3(TPB), 0, s, cnt_le, (const uint32_t*)hist_first, L);

@@ -1,6 +1,8 @@
 // Forward renderer (Eq. 1-2 with the fused training signal) and its adjoint.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dot_device.h"
 
 namespace dot {
@@ -117,6 +119,163 @@ __global__ __launch_bounds__(BLOCK) void render_bwd_kernel(TreeView tv, RayBatch
     traverse(tv, r, &stack_lds[tid], seg, desc);
 }
 
+// ---------------------------------------------------------------------------
+// Leaf-bucketed adjoint.  Many rays cross the same leaves, so pushing every
+// segment's 1 + 3K gradient terms with float atomics serialises on the hot
+// leaves.  Instead: (1) count the contributing segments of every leaf, (2)
+// scan the counts into bucket offsets, (3) write each segment's gradient row
+// into its leaf's bucket (one integer atomic per segment picks the slot), and
+// (4) sum every bucket column-wise into the gradient arrays.
+// ---------------------------------------------------------------------------
+template <int DT>
+struct BwdCount {
+    const TreeView& tv;
+    uint32_t* count;
+    int n = 0, limit = 0;
+    __device__ BwdCount(const TreeView& tv_, uint32_t* c) : tv(tv_), count(c) {}
+    __device__ __forceinline__ bool operator()(int leaf, float delta) {
+        ++n;
+        if (load_sigma<DT>(tv.sigma, leaf) > 0.f) atomicAdd(&count[leaf], 1u);
+        return n < limit;
+    }
+};
+
+template <int DT, int DEG>
+struct BwdEmit {
+    static constexpr int K = (DEG + 1) * (DEG + 1);
+    static constexpr int RS = (1 + 3 * K + 3) / 4 * 4;   // row stride (floats), 16-byte rows
+    const TreeView& tv;
+    const uint32_t* offset;
+    const uint32_t* count;
+    uint32_t* cursor;
+    float* rows;
+    float Y[K];
+    float S = 0.f, T = 1.f;
+    float C[3], g[3];
+    float P[3] = {0.f, 0.f, 0.f};
+    int n = 0, limit = 0;
+
+    __device__ BwdEmit(const TreeView& tv_, const uint32_t* o, const uint32_t* n_, uint32_t* c, float* r)
+        : tv(tv_), offset(o), count(n_), cursor(c), rows(r) {}
+
+    __device__ __forceinline__ bool operator()(int leaf, float delta) {
+        ++n;
+        float sraw = load_sigma<DT>(tv.sigma, leaf);
+        if (sraw > 0.f) {
+            float tau = sraw * delta;
+            float Sn = S + tau;
+            float Tn = __expf(-Sn);
+            float w = fmaxf(T - Tn, 0.f);
+            float row[3 * K];
+            load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
+            float c[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float x = 0.f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) x = fmaf(row[ch * K + k], Y[k], x);
+                c[ch] = sigmoidf_(x);
+            }
+            float out[RS];
+            float gs = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                P[ch] = fmaf(w, c[ch], P[ch]);
+                gs = fmaf(g[ch], Tn * c[ch] - (C[ch] - P[ch]), gs);
+            }
+            out[0] = gs * delta;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float f = g[ch] * w * c[ch] * (1.f - c[ch]);
+#pragma unroll
+                for (int k = 0; k < K; ++k) out[1 + ch * K + k] = f * Y[k];
+            }
+#pragma unroll
+            for (int j = 1 + 3 * K; j < RS; ++j) out[j] = 0.f;
+            // the bucket holds exactly the segments the counting pass found; a
+            // slot past it is never written (the reduction reads written rows only)
+            uint32_t k = atomicAdd(&cursor[leaf], 1u);
+            if (k < count[leaf]) {
+                float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)offset[leaf] + k) * RS);
+#pragma unroll
+                for (int j = 0; j < RS / 4; ++j)
+                    dst[j] = make_float4(out[4 * j], out[4 * j + 1], out[4 * j + 2], out[4 * j + 3]);
+            }
+            S = Sn;
+            T = Tn;
+        }
+        return n < limit;
+    }
+};
+
+template <int DT>
+__global__ __launch_bounds__(BLOCK) void bwd_count_kernel(TreeView tv, RayBatch rb, BwdArgs a, uint32_t* count) {
+    __shared__ int stack_lds[LAT * BLOCK];
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (tid >> 6);
+    if (tile >= rb.n_tiles) return;
+    Ray r;
+    int64_t rid;
+    if (!make_ray(rb, tile, lane, r, rid)) return;
+    BwdCount<DT> seg(tv, count);
+    seg.limit = a.nseg[rid];
+    if (seg.limit <= 0) return;
+    if (a.grad_rgb[3 * rid] == 0.f && a.grad_rgb[3 * rid + 1] == 0.f && a.grad_rgb[3 * rid + 2] == 0.f) return;
+    int desc = 0;
+    traverse(tv, r, &stack_lds[tid], seg, desc);
+}
+
+template <int DT, int DEG>
+__global__ __launch_bounds__(BLOCK) void bwd_emit_kernel(TreeView tv, RayBatch rb, BwdArgs a, const uint32_t* offset,
+                                                         const uint32_t* count, uint32_t* cursor, float* rows) {
+    __shared__ int stack_lds[LAT * BLOCK];
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (tid >> 6);
+    if (tile >= rb.n_tiles) return;
+    Ray r;
+    int64_t rid;
+    if (!make_ray(rb, tile, lane, r, rid)) return;
+    BwdEmit<DT, DEG> seg(tv, offset, count, cursor, rows);
+    seg.limit = a.nseg[rid];
+    if (seg.limit <= 0) return;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        seg.C[ch] = a.rgb_fwd[3 * rid + ch];
+        seg.g[ch] = a.grad_rgb[3 * rid + ch];
+    }
+    if (seg.g[0] == 0.f && seg.g[1] == 0.f && seg.g[2] == 0.f) return;
+    sh_basis<DEG>((float)r.dx, (float)r.dy, (float)r.dz, seg.Y);
+    int desc = 0;
+    traverse(tv, r, &stack_lds[tid], seg, desc);
+}
+
+// column sums of every leaf's bucket: thread (leaf, column), columns contiguous
+__global__ void bwd_reduce_kernel(int64_t L, int ncol, int rs, const uint32_t* __restrict__ offset,
+                                  const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor,
+                                  const float* __restrict__ rows, float* __restrict__ gsig, float* __restrict__ gsh) {
+    const int64_t n = L * ncol;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t l = i / ncol;
+        int c = (int)(i - l * ncol);
+        uint32_t m = min(count[l], cursor[l]);
+        if (m == 0) continue;
+        const float* p = rows + (int64_t)offset[l] * rs + c;
+        float acc = 0.f;
+        for (uint32_t r = 0; r < m; ++r) acc += p[(int64_t)r * rs];
+        if (c == 0)
+            gsig[l] += acc;
+        else
+            gsh[l * (ncol - 1) + (c - 1)] += acc;
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 template <int DT, int DEG>
 static hipError_t fwd_dispatch_stats(const TreeView& tv, const RayBatch& rb, const FwdArgs& a,
                                      dim3 grid, hipStream_t s) {
@@ -161,15 +320,87 @@ static hipError_t bwd_dispatch_deg(int deg, const TreeView& tv, const RayBatch& 
     return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s) {
-    if (rb.n_tiles == 0) return hipSuccess;
-    dim3 grid((unsigned)((rb.n_tiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
+static hipError_t bwd_atomic(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, dim3 grid, hipStream_t s) {
     TreeView tv = t.view();
     switch (t.storage) {
         case DOT_F32: return bwd_dispatch_deg<DOT_F32>(t.degree, tv, rb, a, grid, s);
         case DOT_F16: return bwd_dispatch_deg<DOT_F16>(t.degree, tv, rb, a, grid, s);
         default: return bwd_dispatch_deg<DOT_BF16>(t.degree, tv, rb, a, grid, s);
     }
+}
+
+template <int DT>
+static void launch_emit(int deg, const TreeView& tv, const RayBatch& rb, const BwdArgs& a, const uint32_t* off,
+                        const uint32_t* cnt, uint32_t* cur, float* rows, dim3 grid, hipStream_t s) {
+    switch (deg) {
+        case 0: hipLaunchKernelGGL((bwd_emit_kernel<DT, 0>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
+        case 1: hipLaunchKernelGGL((bwd_emit_kernel<DT, 1>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
+        case 2: hipLaunchKernelGGL((bwd_emit_kernel<DT, 2>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
+        default: hipLaunchKernelGGL((bwd_emit_kernel<DT, 3>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
+    }
+}
+
+// bucket scratch beyond this many bytes falls back to the atomic adjoint
+static constexpr double kBucketBytesMax = 8.0 * (1ull << 30);
+
+hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s) {
+    if (rb.n_tiles == 0) return hipSuccess;
+    dim3 grid((unsigned)((rb.n_tiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
+    const int64_t L = t.n_leaves;
+    const int K = (t.degree + 1) * (t.degree + 1);
+    const int ncol = 1 + 3 * K;
+    const int rs = (ncol + 3) / 4 * 4;
+    TreeView tv = t.view();
+    uint32_t* count = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
+    uint32_t* offset = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
+    uint32_t* cursor = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
+    uint32_t* bsum = static_cast<uint32_t*>(t.alloc.get((size_t)scan_scratch_elems(L) * 4));
+    uint32_t* tot = static_cast<uint32_t*>(t.alloc.get(16));
+    auto drop = [&]() {
+        t.alloc.put(count);
+        t.alloc.put(offset);
+        t.alloc.put(cursor);
+        t.alloc.put(bsum);
+        t.alloc.put(tot);
+    };
+    if (!count || !offset || !cursor || !bsum || !tot) {
+        drop();
+        return bwd_atomic(t, rb, a, grid, s);
+    }
+    unsigned fg = (unsigned)std::min<int64_t>((L + 255) / 256, 65536);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count, L);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L);
+    switch (t.storage) {
+        case DOT_F32: hipLaunchKernelGGL(bwd_count_kernel<DOT_F32>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+        case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+        default: hipLaunchKernelGGL(bwd_count_kernel<DOT_BF16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+    }
+    hipError_t e = scan_u32(count, offset, L, bsum, tot, s);
+    uint32_t m = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&m, tot, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        drop();
+        return e;
+    }
+    float* rows = nullptr;
+    if ((double)m * rs * 4 <= kBucketBytesMax) rows = static_cast<float*>(t.alloc.get((size_t)std::max<uint32_t>(m, 1) * rs * 4));
+    if (!rows) {
+        drop();
+        return bwd_atomic(t, rb, a, grid, s);
+    }
+    switch (t.storage) {
+        case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
+        case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
+        default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
+    }
+    unsigned rg = (unsigned)std::min<int64_t>((L * ncol + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(bwd_reduce_kernel, dim3(rg), dim3(256), 0, s, L, ncol, rs, offset, count, cursor, rows,
+                       a.grad_sigma, a.grad_sh);
+    e = hipGetLastError();
+    t.alloc.put(rows);
+    drop();
+    return e;
 }
 
 }  // namespace dot

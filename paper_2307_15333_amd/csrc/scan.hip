@@ -1,0 +1,100 @@
+// Exclusive prefix scan of uint32 arrays: per-tile sums, a single-workgroup
+// scan of the tile sums, then a per-tile rescan with the tile's offset.
+#include <hip/hip_runtime.h>
+
+#include "dot_internal.h"
+
+namespace dot {
+
+namespace {
+constexpr int TPB = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& total) {
+    __shared__ uint32_t wsum[TPB / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    total = 0;
+#pragma unroll
+    for (int j = 0; j < TPB / 64; ++j) {
+        if (j < w) base += wsum[j];
+        total += wsum[j];
+    }
+    __syncthreads();
+    return base + x - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ bsum) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * TPB + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t total;
+    block_exclusive_scan(acc, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the block sums in place; total into *tot
+__global__ void k_scan_bsums(uint32_t* __restrict__ bsum, int64_t nb, uint32_t* __restrict__ tot) {
+    const int64_t per = (nb + TPB - 1) / TPB;
+    const int64_t b0 = threadIdx.x * per;
+    uint32_t acc = 0;
+    for (int64_t i = b0; i < b0 + per && i < nb; ++i) acc += bsum[i];
+    uint32_t total;
+    uint32_t off = block_exclusive_scan(acc, total);
+    for (int64_t i = b0; i < b0 + per && i < nb; ++i) {
+        uint32_t v = bsum[i];
+        bsum[i] = off;
+        off += v;
+    }
+    if (threadIdx.x == 0) *tot = total;
+}
+
+__global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ bsum,
+                             uint32_t* __restrict__ out) {
+    // each thread owns SCAN_ITEMS consecutive elements of the tile
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        v[j] = i < n ? in[i] : 0u;
+        acc += v[j];
+    }
+    uint32_t total;
+    uint32_t off = block_exclusive_scan(acc, total) + bsum[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = off;
+        off += v[j];
+    }
+}
+
+}  // namespace
+
+int64_t scan_scratch_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(TPB), 0, s, bsum, nb, tot);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum, out);
+    return hipGetLastError();
+}
+
+}  // namespace dot
