@@ -10,7 +10,7 @@
 namespace dot {
 
 constexpr int WAVE = 64;
-constexpr int BLOCK = 256;            // 4 waves, one 8x8 ray tile each
+constexpr int BLOCK = 128;            // 2 waves, one 8x8 ray tile each
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 
 // ---------------------------------------------------------------------------
@@ -332,6 +332,9 @@ struct FwdSeg {
         // sigma and the SH row are requested together (one memory round trip);
         // a leaf with sigma^ delta = 0 contributes w = 0
         float sg = fmaxf(load_sigma<DT>(tv.sigma, leaf), 0.f);
+        // the stored signal, read for the max filter below, is requested with the
+        // leaf data so it does not add a dependent load after compositing
+        const float cur = a.signal ? a.signal[leaf] : 0.f;
         // BF16 rows stay packed in registers and each coefficient is widened in
         // the dot product (FP16 rows stay packed through mixed-precision FMAs)
         constexpr int NW = (3 * K + 1) / 2;
@@ -378,7 +381,6 @@ struct FwdSeg {
                 if (a.signal_mode == DOT_SIGNAL_MAX) {
                     // non-negative floats order like their bit patterns; skip the
                     // atomic when the stored value already dominates
-                    float cur = a.signal[leaf];
                     if (w > cur) atomicMax(reinterpret_cast<unsigned int*>(&a.signal[leaf]), __float_as_uint(w));
                 } else {
                     unsafeAtomicAdd(&a.signal[leaf], w);
