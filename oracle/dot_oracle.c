@@ -557,6 +557,8 @@ typedef struct {
     int32_t max_depth;
     int32_t recursive;
     int32_t storage;
+    int32_t reinit;    /* 1: new leaves start from zero instead of the fused values */
+    int32_t pad_;
 } orc_refine_params;
 
 typedef struct {
@@ -626,14 +628,19 @@ static int64_t rf_merge_pass(rf_ctx *c, int first_pass) {
     return added;
 }
 
-static void rf_push_leaf(rf_ctx *c, int32_t depth, uint64_t morton, const double *sig, const double *sh) {
+/* `fresh` marks a leaf created by this refinement (a merged node or a child of
+ * a subdivided leaf); with reinit such leaves start from zero -- the paper's
+ * ablation that disables feature fusion (App. B.1) -- instead of Eq. 3 / Eq. 4 */
+static void rf_push_leaf(rf_ctx *c, int32_t depth, uint64_t morton, const double *sig, const double *sh,
+                         int fresh) {
     orc_refined *o = c->out;
     int64_t l = o->n_leaves++;
     int K = c->K;
+    int zero = fresh && c->P->reinit;
     o->depth[l] = depth;
     o->morton[l] = morton;
-    o->sigma[l] = orc_round_storage(c->P->storage, sig[0]);
-    for (int j = 0; j < 3 * K; ++j) o->sh[l * 3 * K + j] = (float)orc_round_storage(c->P->storage, sh[j]);
+    o->sigma[l] = zero ? 0.0 : orc_round_storage(c->P->storage, sig[0]);
+    for (int j = 0; j < 3 * K; ++j) o->sh[l * 3 * K + j] = zero ? 0.0f : (float)orc_round_storage(c->P->storage, sh[j]);
 }
 
 /* mean of the stored values of all leaves under `node` when the subtree is
@@ -678,7 +685,7 @@ static int32_t rf_build(rf_ctx *c, int32_t entry, int32_t depth, uint64_t morton
     if (entry >= 0) { /* merged node -> one leaf */
         rf_subtree_value(c, entry, &sig, sh);
         int64_t l = o->n_leaves;
-        rf_push_leaf(c, depth, morton, &sig, sh);
+        rf_push_leaf(c, depth, morton, &sig, sh, 1);
         return (int32_t)(-1 - l);
     }
     int64_t old = -1 - entry;
@@ -688,13 +695,13 @@ static int32_t rf_build(rf_ctx *c, int32_t entry, int32_t depth, uint64_t morton
         int64_t me = o->n_internal++;
         for (int oc = 0; oc < 8; ++oc) {
             int64_t l = o->n_leaves;
-            rf_push_leaf(c, depth + 1, rf_child_morton(morton, oc), &sig, sh);
+            rf_push_leaf(c, depth + 1, rf_child_morton(morton, oc), &sig, sh, 1);
             o->child[8 * me + oc] = (int32_t)(-1 - l);
         }
         return (int32_t)me;
     }
     int64_t l = o->n_leaves;
-    rf_push_leaf(c, depth, morton, &sig, sh);
+    rf_push_leaf(c, depth, morton, &sig, sh, 0);
     return (int32_t)(-1 - l);
 }
 

@@ -528,6 +528,32 @@ def test_refine_recursive_climbs_hierarchy():
     assert R["sigma"].shape[0] == 1 and R["child"].shape[0] == 0
 
 
+def test_refine_reinit_zeroes_only_new_leaves():
+    """The fusion-disabled ablation: the same topology; merged leaves and the
+    children of split leaves start at zero, untouched leaves keep their values."""
+    s = synth.random_tree_scene(3, 1, seed=31, p_split=0.5)
+    rng = np.random.default_rng(5)
+    signal = rng.uniform(0.5, 1.0, s.n_leaves).astype(np.float32)
+    groups = {}
+    for i in range(s.n_leaves):
+        groups.setdefault((s.leaf_depth[i] - 1, tuple(s.leaf_ijk[i] >> 1)), []).append(i)
+    grp = [m for m in groups.values() if len(m) == 8][0]
+    signal[grp] = 0.0
+    T = O.OracleTree.from_scene(s)
+    A = O.refine(T, signal, tau=0.0, sample_frac=0.05, max_depth=5)
+    B = O.refine(T, signal, tau=0.0, sample_frac=0.05, max_depth=5, reinit=True)
+    np.testing.assert_array_equal(A["child"], B["child"])
+    np.testing.assert_array_equal(A["depth"], B["depth"])
+    fresh = np.zeros(A["sigma"].shape[0], bool)
+    old_key = {(int(d), int(m)) for d, m in zip(s.leaf_depth, synth.morton3(s.leaf_ijk))}
+    for j, (d, m) in enumerate(zip(A["depth"], A["morton"])):
+        fresh[j] = (int(d), int(m)) not in old_key
+    assert fresh.sum() == 1 + 8 * A["k"]
+    assert not B["sigma"][fresh].any() and not B["sh"][fresh].any()
+    np.testing.assert_array_equal(B["sigma"][~fresh], A["sigma"][~fresh])
+    np.testing.assert_array_equal(B["sh"][~fresh], A["sh"][~fresh])
+
+
 def test_refine_root_leaf():
     T = _root_leaf_tree(1.0, 0.5, degree=1)
     R = O.refine(T, np.array([0.9], np.float32), tau=0.1, sample_frac=1.0, max_depth=2)
