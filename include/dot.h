@@ -208,7 +208,8 @@ typedef struct {
     int32_t prune_le;
     int32_t max_depth;   /* only leaves shallower than this are subdivided */
     int32_t recursive;   /* 1: repeat merging up the hierarchy (the paper's "(R)" option) */
-    int32_t reserved;
+    int32_t reinit;      /* 1: new leaves start at sigma = 0, SH = 0 instead of the fused values
+                            (the paper's ablation without feature fusion, App. C.1) */
 } dot_refine_params;
 
 typedef struct {
@@ -255,6 +256,29 @@ typedef struct {
 int dot_adam_step(dot_tree_t tree, const float *grad_sigma, const float *grad_sh, float *m_sigma,
                   float *v_sigma, float *m_sh, float *v_sh, const dot_adam_params *params,
                   void *stream);
+
+typedef struct {
+    float lr_sigma, lr_sh;     /* learning rates (the paper: 0.1 for sigma, 0.01 for SH, Sec. 4.1) */
+    float alpha, eps;          /* square-average decay and denominator term */
+} dot_rmsprop_params;
+
+/*
+ * dot_rmsprop_step -- one RMSProp update of the sigma and SH planes in place
+ *  (the optimiser of Sec. 3.3): v = alpha v + (1 - alpha) g^2,
+ *  theta -= lr g / (sqrt(v) + eps).  grad_*: DEVICE float, dense layouts as in
+ *  dot_render_backward; v_*: DEVICE float square averages of the same shapes,
+ *  zero-initialised by the caller.  FP32 storage only (DOT_EUNSUPPORTED
+ *  otherwise).
+ */
+int dot_rmsprop_step(dot_tree_t tree, const float *grad_sigma, const float *grad_sh, float *v_sigma,
+                     float *v_sh, const dot_rmsprop_params *params, void *stream);
+
+/*
+ * dot_sigma_signal -- the density as the training signal (the paper's Pr_sigma
+ *  ablation, Sec. 3.1 and Tab. 3): signal_out[l] = max(sigma_l, 0) decoded to
+ *  FP32.  signal_out: DEVICE float [n_leaves].
+ */
+int dot_sigma_signal(dot_tree_t tree, float *signal_out, void *stream);
 
 /*
  * dot_export -- copy the tree back to host memory in canonical form:

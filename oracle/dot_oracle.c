@@ -630,7 +630,7 @@ static int64_t rf_merge_pass(rf_ctx *c, int first_pass) {
 
 /* `fresh` marks a leaf created by this refinement (a merged node or a child of
  * a subdivided leaf); with reinit such leaves start from zero -- the paper's
- * ablation that disables feature fusion (App. B.1) -- instead of Eq. 3 / Eq. 4 */
+ * ablation that disables feature fusion (App. C.1) -- instead of Eq. 3 / Eq. 4 */
 static void rf_push_leaf(rf_ctx *c, int32_t depth, uint64_t morton, const double *sig, const double *sh,
                          int fresh) {
     orc_refined *o = c->out;

@@ -60,7 +60,7 @@ class dot_tree_info_t(C.Structure):
 
 class dot_refine_params(C.Structure):
     _fields_ = [("prune_tau", C.c_float), ("sample_frac", C.c_float), ("prune_le", C.c_int32),
-                ("max_depth", C.c_int32), ("recursive", C.c_int32), ("reserved", C.c_int32)]
+                ("max_depth", C.c_int32), ("recursive", C.c_int32), ("reinit", C.c_int32)]
 
 
 class dot_refine_stats(C.Structure):
@@ -71,6 +71,10 @@ class dot_refine_stats(C.Structure):
 class dot_adam_params(C.Structure):
     _fields_ = [("lr_sigma", C.c_float), ("lr_sh", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int32)]
+
+
+class dot_rmsprop_params(C.Structure):
+    _fields_ = [("lr_sigma", C.c_float), ("lr_sh", C.c_float), ("alpha", C.c_float), ("eps", C.c_float)]
 
 
 class dot_render_job(C.Structure):
@@ -96,6 +100,9 @@ SIGNATURES = {
                              C.POINTER(dot_refine_stats), C.c_void_p]),
     "dot_adam_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.POINTER(dot_adam_params), C.c_void_p]),
+    "dot_rmsprop_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.POINTER(dot_rmsprop_params), C.c_void_p]),
+    "dot_sigma_signal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_render_stats": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                    C.POINTER(C.c_int64), C.c_void_p]),

@@ -418,6 +418,25 @@ int dot_adam_step(dot_tree_t t, const float* grad_sigma, const float* grad_sh, f
     return DOT_OK;
 }
 
+int dot_rmsprop_step(dot_tree_t t, const float* grad_sigma, const float* grad_sh, float* v_sigma, float* v_sh,
+                     const dot_rmsprop_params* p, void* stream) {
+    if (!t || !p) return fail(DOT_EINVAL, "dot_rmsprop_step: NULL argument");
+    if (t->storage != DOT_F32) return fail(DOT_EUNSUPPORTED, "dot_rmsprop_step: only FP32 leaf storage is trainable");
+    if (!grad_sigma || !grad_sh || !v_sigma || !v_sh)
+        return fail(DOT_EINVAL, "dot_rmsprop_step: gradient and square-average buffers are required");
+    if (!(p->alpha >= 0.f && p->alpha < 1.f)) return fail(DOT_EINVAL, "dot_rmsprop_step: alpha must be in [0, 1)");
+    hipError_t e = launch_rmsprop(*t, grad_sigma, grad_sh, v_sigma, v_sh, *p, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_rmsprop_step: launch");
+    return DOT_OK;
+}
+
+int dot_sigma_signal(dot_tree_t t, float* signal_out, void* stream) {
+    if (!t || !signal_out) return fail(DOT_EINVAL, "dot_sigma_signal: NULL argument");
+    hipError_t e = launch_sigma_signal(*t, signal_out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_sigma_signal: launch");
+    return DOT_OK;
+}
+
 int dot_export(dot_tree_t t, int32_t* child, float* sigma, float* sh, uint8_t* leaf_depth, void* stream) {
     if (!t) return fail(DOT_EINVAL, "dot_export: tree is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -132,6 +132,9 @@ hipError_t launch_adam(const dot_tree& t, const float* gs, const float* gh, floa
 // needs scan_scratch_elems(n) elements
 int64_t scan_scratch_elems(int64_t n);
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s);
+hipError_t launch_rmsprop(const dot_tree& t, const float* gs, const float* gh, float* vs, float* vh,
+                          const dot_rmsprop_params& p, hipStream_t s);
+hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s);
 size_t jobs_workspace_bytes(int n_jobs);
 int launch_render_jobs(const dot_render_job* jobs, int n_jobs, void* ws, size_t ws_bytes, hipStream_t s);
 int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st,

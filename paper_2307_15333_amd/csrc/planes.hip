@@ -125,4 +125,58 @@ hipError_t launch_adam(const dot_tree& t, const float* gs, const float* gh, floa
     return hipGetLastError();
 }
 
+// RMSProp: v = alpha v + (1-alpha) g^2; theta -= lr * g / (sqrt(v) + eps).
+__global__ void rmsprop_kernel(float* __restrict__ sigma, float* __restrict__ sh, const float* __restrict__ gs,
+                               const float* __restrict__ gh, float* __restrict__ vs, float* __restrict__ vh, int64_t L,
+                               int nv, int stride, dot_rmsprop_params p) {
+    int64_t n = L * (1 + nv);
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        float g, lr;
+        float *theta, *vp;
+        if (j < L) {
+            g = gs[j];
+            vp = &vs[j];
+            theta = &sigma[j];
+            lr = p.lr_sigma;
+        } else {
+            int64_t q = j - L;
+            int64_t r = q / nv;
+            int c = (int)(q - r * nv);
+            g = gh[q];
+            vp = &vh[q];
+            theta = &sh[r * stride + c];
+            lr = p.lr_sh;
+        }
+        float v = p.alpha * *vp + (1.f - p.alpha) * g * g;
+        *vp = v;
+        *theta -= lr * g / (sqrtf(v) + p.eps);
+    }
+}
+
+hipError_t launch_rmsprop(const dot_tree& t, const float* gs, const float* gh, float* vs, float* vh,
+                          const dot_rmsprop_params& p, hipStream_t s) {
+    int nv = 3 * (t.degree + 1) * (t.degree + 1);
+    int64_t n = t.n_leaves * (1 + nv);
+    hipLaunchKernelGGL(rmsprop_kernel, dim3(grid_for(n)), dim3(256), 0, s, static_cast<float*>(t.sigma),
+                       static_cast<float*>(t.sh), gs, gh, vs, vh, t.n_leaves, nv, t.sh_stride, p);
+    return hipGetLastError();
+}
+
+template <int DT>
+__global__ void sigma_signal_kernel(const void* __restrict__ sig, int64_t L, float* __restrict__ out) {
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L; l += (int64_t)gridDim.x * blockDim.x)
+        out[l] = fmaxf(load_sigma<DT>(sig, l), 0.f);
+}
+
+hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s) {
+    dim3 g(grid_for(t.n_leaves));
+    if (t.storage == DOT_F32)
+        hipLaunchKernelGGL(sigma_signal_kernel<DOT_F32>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);
+    else if (t.storage == DOT_F16)
+        hipLaunchKernelGGL(sigma_signal_kernel<DOT_F16>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);
+    else
+        hipLaunchKernelGGL(sigma_signal_kernel<DOT_BF16>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);
+    return hipGetLastError();
+}
+
 }  // namespace dot

@@ -313,7 +313,7 @@ __global__ void k_node_values(const int32_t* __restrict__ child, int64_t I, int 
 }
 
 template <int DT>
-__global__ void k_emit_leaves(int64_t L, int stride, const int32_t* __restrict__ cover,
+__global__ void k_emit_leaves(int64_t L, int stride, int reinit, const int32_t* __restrict__ cover,
                               const int32_t* __restrict__ first, const int32_t* __restrict__ ndepth,
                               const uint32_t* __restrict__ split, const uint32_t* __restrict__ nl,
                               const uint8_t* __restrict__ depth, const void* __restrict__ sig,
@@ -325,15 +325,25 @@ __global__ void k_emit_leaves(int64_t L, int stride, const int32_t* __restrict__
         int64_t j = nl[l];
         if (c >= 0) {
             if (first[c] != (int32_t)l) continue;
-            cp_elem<DT>(nval, (int64_t)c * row, sig2, j);
-            for (int k = 0; k < stride; ++k) cp_elem<DT>(nval, (int64_t)c * row + 1 + k, sh2, j * stride + k);
+            if (reinit) {
+                st_elem<DT>(sig2, j, 0.0);
+                for (int k = 0; k < stride; ++k) st_elem<DT>(sh2, j * stride + k, 0.0);
+            } else {
+                cp_elem<DT>(nval, (int64_t)c * row, sig2, j);
+                for (int k = 0; k < stride; ++k) cp_elem<DT>(nval, (int64_t)c * row + 1 + k, sh2, j * stride + k);
+            }
             depth2[j] = (uint8_t)ndepth[c];
         } else {
             int reps = split[l] ? 8 : 1;
             uint8_t d = (uint8_t)(depth[l] + (split[l] ? 1 : 0));
             for (int r = 0; r < reps; ++r) {
-                cp_elem<DT>(sig, l, sig2, j + r);
-                for (int k = 0; k < stride; ++k) cp_elem<DT>(sh, l * stride + k, sh2, (j + r) * stride + k);
+                if (reinit && split[l]) {
+                    st_elem<DT>(sig2, j + r, 0.0);
+                    for (int k = 0; k < stride; ++k) st_elem<DT>(sh2, (j + r) * stride + k, 0.0);
+                } else {
+                    cp_elem<DT>(sig, l, sig2, j + r);
+                    for (int k = 0; k < stride; ++k) cp_elem<DT>(sh, l * stride + k, sh2, (j + r) * stride + k);
+                }
                 depth2[j + r] = d;
             }
         }
@@ -369,7 +379,8 @@ struct Temps {
 };
 
 template <int DT>
-hipError_t launch_values_emit(const dot_tree& t, int64_t L, int64_t I, int nv, int stride, const int32_t* cover,
+hipError_t launch_values_emit(const dot_tree& t, int64_t L, int64_t I, int nv, int stride, int reinit,
+                              const int32_t* cover,
                               const int32_t* first, const int32_t* ndepth, const uint32_t* need,
                               const uint32_t* split, const uint32_t* nl, void* nval, void* sig2, void* sh2,
                               uint8_t* depth2, hipStream_t s) {
@@ -377,7 +388,8 @@ hipError_t launch_values_emit(const dot_tree& t, int64_t L, int64_t I, int nv, i
         for (int d = DOT_MAX_DEPTH - 1; d >= 0; --d)
             hipLaunchKernelGGL(k_node_values<DT>, dim3(blocks_for(I)), dim3(TPB), 0, s, t.child, I, d, ndepth, need,
                                nv, stride, t.sigma, t.sh, nval);
-    hipLaunchKernelGGL(k_emit_leaves<DT>, dim3(blocks_for(L)), dim3(TPB), 0, s, L, stride, cover, first, ndepth, split,
+    hipLaunchKernelGGL(k_emit_leaves<DT>, dim3(blocks_for(L)), dim3(TPB), 0, s, L, stride, reinit, cover, first, ndepth,
+                       split,
                        nl, t.leaf_depth, t.sigma, t.sh, nval, sig2, sh2, depth2);
     return hipGetLastError();
 }
@@ -488,13 +500,13 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
                            rank_int, rank_split, split, cnt_le, nl, child2);
     hipLaunchKernelGGL(k_child_split, dim3(blocks_for(L)), dim3(TPB), 0, s, L, split, rank_split, cnt_le, nl, child2);
     if (t.storage == DOT_F32)
-        e = launch_values_emit<DOT_F32>(t, L, I, nv, stride, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
+        e = launch_values_emit<DOT_F32>(t, L, I, nv, stride, p.reinit, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
                                         depth2, s);
     else if (t.storage == DOT_F16)
-        e = launch_values_emit<DOT_F16>(t, L, I, nv, stride, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
+        e = launch_values_emit<DOT_F16>(t, L, I, nv, stride, p.reinit, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
                                         depth2, s);
     else
-        e = launch_values_emit<DOT_BF16>(t, L, I, nv, stride, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
+        e = launch_values_emit<DOT_BF16>(t, L, I, nv, stride, p.reinit, cover, first, ndepth, need, split, nl, nval, sig2, sh2,
                                          depth2, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
