@@ -281,6 +281,23 @@ int dot_rmsprop_step(dot_tree_t tree, const float *grad_sigma, const float *grad
 int dot_sigma_signal(dot_tree_t tree, float *signal_out, void *stream);
 
 /*
+ * dot_mse_loss -- the photometric loss of a training step (Sec. 3 and Alg. 1:
+ *  the prediction of a permuted ray batch against its ground-truth pixels)
+ *  and its gradient with respect to the prediction:
+ *      loss        = 1/(3n) sum_r sum_ch (pred[r][ch] - target[idx_r][ch])^2
+ *      grad_rgb[r] = 2 (pred[r] - target[idx_r]) / (3n)
+ *  pred: DEVICE float [n][3]; target: DEVICE float [*][3]; target_idx: DEVICE
+ *  int64 [n] (row of `target` that ray r is compared with, which the caller
+ *  guarantees to be in range) or NULL (row r); grad_rgb_out: DEVICE float
+ *  [n][3] or NULL; loss_out: DEVICE double [1] or NULL, overwritten.  Residuals
+ *  and the sum are formed in FP64 (the gradient is rounded once to FP32; the
+ *  summation order depends on scheduling).  n_rays = 0 writes a zero loss.
+ *  Errors: DOT_EINVAL on n_rays < 0 or a NULL pred/target with n_rays > 0.
+ */
+int dot_mse_loss(const float *pred, const float *target, const int64_t *target_idx, int64_t n_rays,
+                 float *grad_rgb_out, double *loss_out, void *stream);
+
+/*
  * dot_export -- copy the tree back to host memory in canonical form:
  *  child [n_internal][8], sigma [L] and sh [L][3][K] decoded to FP32,
  *  leaf_depth [L].  Any pointer may be NULL.  Synchronous.

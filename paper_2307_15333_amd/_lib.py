@@ -103,6 +103,8 @@ SIGNATURES = {
     "dot_rmsprop_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(dot_rmsprop_params), C.c_void_p]),
     "dot_sigma_signal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dot_mse_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
     "dot_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_render_stats": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                    C.POINTER(C.c_int64), C.c_void_p]),

@@ -212,10 +212,10 @@ class Octree:
         return dict(rays=out[0], segments=out[1], sh_fetches=out[2], child_reads=out[3])
 
     def refine(self, signal, prune_tau=1e-3, sample_frac=0.05, max_depth=10, prune_le=True,
-               recursive=False):
+               recursive=False, reinit=False):
         p = L.dot_refine_params(prune_tau=float(prune_tau), sample_frac=float(sample_frac),
                                 prune_le=int(bool(prune_le)), max_depth=int(max_depth),
-                                recursive=int(bool(recursive)))
+                                recursive=int(bool(recursive)), reinit=int(bool(reinit)))
         st = L.dot_refine_stats()
         L.check(self.lib.dot_refine(self.handle, _ptr(signal), C.byref(p), C.byref(st), _stream()))
         return dict(leaves_before=st.leaves_before, leaves_after=st.leaves_after,
@@ -233,6 +233,23 @@ class Octree:
         z = lambda *s: torch.zeros(s, dtype=torch.float32, device=self.device)
         return dict(m_sigma=z(Ln), v_sigma=z(Ln), m_sh=z(Ln, 3, self.K), v_sh=z(Ln, 3, self.K))
 
+    def rmsprop_step(self, grad_sigma, grad_sh, state, lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8):
+        p = L.dot_rmsprop_params(lr_sigma=lr_sigma, lr_sh=lr_sh, alpha=alpha, eps=eps)
+        L.check(self.lib.dot_rmsprop_step(self.handle, _ptr(grad_sigma), _ptr(grad_sh), _ptr(state["v_sigma"]),
+                                          _ptr(state["v_sh"]), C.byref(p), _stream()))
+
+    def rmsprop_state(self):
+        Ln = self.n_leaves
+        z = lambda *s: torch.zeros(s, dtype=torch.float32, device=self.device)
+        return dict(v_sigma=z(Ln), v_sh=z(Ln, 3, self.K))
+
+    def sigma_signal(self, out=None):
+        """The density signal max(sigma, 0) per leaf (FP32 [L])."""
+        if out is None:
+            out = torch.empty(self.n_leaves, dtype=torch.float32, device=self.device)
+        L.check(self.lib.dot_sigma_signal(self.handle, _ptr(out), _stream()))
+        return out
+
     def export(self):
         i = self.info()
         I, Ln = int(i.n_internal), int(i.n_leaves)
@@ -245,15 +262,29 @@ class Octree:
         return dict(child=child, sigma=sigma, sh=sh, depth=depth)
 
 
+def mse_loss(pred, target, target_idx=None, grad=True, loss=True):
+    """(loss, grad_rgb) of pred [n,3] against target rows (target_idx: int64 [n]
+    or None); either may be skipped.  loss is a device float64 scalar."""
+    n = pred.shape[0]
+    g = torch.empty_like(pred) if grad else None
+    lo = torch.empty((), dtype=torch.float64, device=pred.device) if loss else None
+    if target_idx is not None:
+        assert target_idx.dtype == torch.int64 and target_idx.shape[0] == n
+    L.check(L.load().dot_mse_loss(_ptr(pred), _ptr(target), _ptr(target_idx), C.c_int64(n), _ptr(g), _ptr(lo),
+                                  _stream()))
+    return lo, g
+
+
 class DotRender(torch.autograd.Function):
     """C = render(sigma, sh; rays) with the hand-written adjoint as backward.
 
     ``sigma``/``sh`` are the tree's plane views (see Octree.plane_views); the
-    gradients returned are dense FP32 [L] and [L,3,K]."""
+    gradients returned are dense FP32 [L] and [L,3,K].  A ``signal`` buffer, if
+    given, receives the fused training signal of the forward pass."""
 
     @staticmethod
-    def forward(ctx, sigma, sh, tree, rays, bg, t_stop):
-        rgb, nseg = tree.render(rays, bg=bg, t_stop=t_stop, nseg=True)
+    def forward(ctx, sigma, sh, tree, rays, bg, t_stop, signal=None, signal_mode="max"):
+        rgb, nseg = tree.render(rays, bg=bg, t_stop=t_stop, nseg=True, signal=signal, signal_mode=signal_mode)
         ctx.save_for_backward(rgb, nseg)
         ctx.tree, ctx.rays, ctx.bg, ctx.t_stop = tree, rays, bg, t_stop
         return rgb
@@ -266,8 +297,8 @@ class DotRender(torch.autograd.Function):
         gs = torch.zeros(Ln, dtype=torch.float32, device=rgb.device)
         gh = torch.zeros((Ln, 3, tree.K), dtype=torch.float32, device=rgb.device)
         tree.backward(ctx.rays, rgb, nseg, grad_rgb.contiguous().float(), gs, gh, bg=ctx.bg, t_stop=ctx.t_stop)
-        return gs, gh, None, None, None, None
+        return gs, gh, None, None, None, None, None, None
 
 
-def render_autograd(tree, sigma, sh, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
-    return DotRender.apply(sigma, sh, tree, rays, bg, t_stop)
+def render_autograd(tree, sigma, sh, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max"):
+    return DotRender.apply(sigma, sh, tree, rays, bg, t_stop, signal, signal_mode)

@@ -437,6 +437,16 @@ int dot_sigma_signal(dot_tree_t t, float* signal_out, void* stream) {
     return DOT_OK;
 }
 
+int dot_mse_loss(const float* pred, const float* target, const int64_t* target_idx, int64_t n_rays,
+                 float* grad_rgb_out, double* loss_out, void* stream) {
+    if (n_rays < 0) return fail(DOT_EINVAL, "dot_mse_loss: n_rays < 0");
+    if (n_rays > 0 && (!pred || !target)) return fail(DOT_EINVAL, "dot_mse_loss: NULL prediction or target");
+    hipError_t e = launch_mse(pred, target, target_idx, n_rays, grad_rgb_out, loss_out,
+                              static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_mse_loss: launch");
+    return DOT_OK;
+}
+
 int dot_export(dot_tree_t t, int32_t* child, float* sigma, float* sh, uint8_t* leaf_depth, void* stream) {
     if (!t) return fail(DOT_EINVAL, "dot_export: tree is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);

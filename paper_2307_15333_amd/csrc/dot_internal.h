@@ -135,6 +135,8 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum
 hipError_t launch_rmsprop(const dot_tree& t, const float* gs, const float* gh, float* vs, float* vh,
                           const dot_rmsprop_params& p, hipStream_t s);
 hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s);
+hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx, int64_t n, float* grad,
+                      double* loss, hipStream_t s);
 size_t jobs_workspace_bytes(int n_jobs);
 int launch_render_jobs(const dot_render_job* jobs, int n_jobs, void* ws, size_t ws_bytes, hipStream_t s);
 int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st,

@@ -1,5 +1,6 @@
-// Leaf-plane encoding (FP32 -> storage type, padded rows), decoding, and the
-// fused Adam update of the leaf parameters.
+// Leaf-plane encoding (FP32 -> storage type, padded rows), decoding, the
+// photometric loss of a training batch, the optimiser updates of the leaf
+// parameters (Adam, RMSProp) and the density signal.
 #include <hip/hip_runtime.h>
 
 #include "dot_device.h"
@@ -176,6 +177,52 @@ hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s) {
         hipLaunchKernelGGL(sigma_signal_kernel<DOT_F16>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);
     else
         hipLaunchKernelGGL(sigma_signal_kernel<DOT_BF16>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);
+    return hipGetLastError();
+}
+
+// Squared error of a ray batch and its gradient.  One block partial per
+// workgroup, combined with a double atomic into *loss (zeroed by the first
+// kernel of the same stream).
+__global__ void zero_f64_kernel(double* p) { *p = 0.0; }
+
+__global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
+                                                  const int64_t* __restrict__ idx, int64_t n, double gscale,
+                                                  float* __restrict__ grad, double* __restrict__ loss, double lscale) {
+    __shared__ double part[256 / WAVE];
+    double acc = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = idx ? idx[r] : r;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double e = (double)pred[3 * r + c] - (double)target[3 * t + c];   // exact
+            if (grad) grad[3 * r + c] = (float)(gscale * e);
+            acc += e * e;
+        }
+    }
+    if (!loss) return;
+    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = 0.0;
+        for (int w = 0; w < 256 / WAVE; ++w) b += part[w];
+        atomicAdd(loss, b * lscale);
+    }
+}
+
+hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx, int64_t n, float* grad,
+                      double* loss, hipStream_t s) {
+    if (loss) {
+        hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(1), 0, s, loss);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    const double gscale = 2.0 / (3.0 * (double)n);
+    hipLaunchKernelGGL(mse_kernel, dim3((unsigned)g), dim3(256), 0, s, pred, target, idx, n, gscale, grad, loss,
+                       1.0 / (3.0 * (double)n));
     return hipGetLastError();
 }
 

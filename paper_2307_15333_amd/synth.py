@@ -529,6 +529,13 @@ def perturb_sh(scene, std=0.05, seed=3):
     return dataclasses.replace(scene, sh32=scene.sh32 + noise)
 
 
+def ray_permutations(n_rays, epochs, seed):
+    """One random order of the training rays per epoch (the permutation step of
+    the training loop), drawn from a seeded generator."""
+    rng = np.random.default_rng(seed)
+    return [rng.permutation(n_rays).astype(np.int64) for _ in range(epochs)]
+
+
 def pixel_batch(n_views, width, height, batch, seed):
     """Random (view, pixel) pairs without replacement from the view pool."""
     rng = np.random.default_rng(seed)

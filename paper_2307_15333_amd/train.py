@@ -1,0 +1,154 @@
+"""The refinement-training loop of DOT (Alg. 1) over a device-resident octree.
+
+One epoch permutes the training rays, then for every batch of the permuted
+order renders the batch (fusing the training signal Q into the forward pass
+when this epoch ends with a refinement), takes the MSE against the ground-truth
+pixels, runs the hand-written adjoint and one optimiser step (RMSProp as in
+Sec. 3.3, or Adam).  Every `interval` epochs (the structure is frozen for T
+epochs in between, Sec. 3.3) the octree is refined from the epoch's signal:
+recursive or one-level pruning of groups whose signal is at most tau, then
+subdivision of the top gamma fraction of leaves (Sec. 3.2), with fused
+features or, for the ablation without fusion, fresh zero-valued leaves.  The
+optimiser state restarts from zero after a refinement, since the leaf set
+changed.
+
+Everything per ray and per leaf runs in libdot's kernels; this module
+only sequences the calls and slices the permuted ray order into batches.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import core
+
+
+@dataclasses.dataclass
+class TrainConfig:
+    epochs: int = 100
+    interval: int = 20              # T: epochs between refinements (Sec. 4.1)
+    batch_rays: int = 1 << 18
+    optimizer: str = "rmsprop"      # "rmsprop" (Sec. 3.3) or "adam"
+    lr_sigma: float = 0.1           # Sec. 4.1
+    lr_sh: float = 0.01
+    alpha: float = 0.99             # RMSProp square-average decay
+    beta1: float = 0.9              # Adam
+    beta2: float = 0.999
+    eps: float = 1e-8
+    signal: str = "max"             # "max" / "sum" of ray weights (Q), or "sigma" (the Pr_sigma ablation)
+    tau: float = 1e-3               # prune groups whose signal is <= tau (Sec. 3.2)
+    gamma: float = 0.01             # subdivide the top gamma fraction of leaves
+    prune_le: bool = True
+    max_depth: int = 10
+    recursive: bool = False
+    reinit: bool = False            # ablation: new leaves start at zero instead of fused values
+    refine: bool = True
+    bg: tuple = (1.0, 1.0, 1.0)
+    t_stop: float = 1e-4
+    seed: int = 0
+
+
+class Trainer:
+    """Alg. 1 on `tree` (FP32 storage) against multi-view targets.
+
+    cams: camera records (all of one size W x H); targets: float32 [n_cams, H, W, 3]
+    (host or device)."""
+
+    def __init__(self, tree, cams, targets, cfg: TrainConfig):
+        if tree.storage != "f32":
+            raise ValueError("training needs FP32 leaf storage")
+        if cfg.signal not in ("max", "sum", "sigma"):
+            raise ValueError(f"unknown signal {cfg.signal!r}")
+        if cfg.optimizer not in ("rmsprop", "adam"):
+            raise ValueError(f"unknown optimizer {cfg.optimizer!r}")
+        self.tree = tree
+        self.cfg = cfg
+        self.device = tree.device
+        cams = np.asarray(cams)
+        self.n_cams = len(cams)
+        self.W, self.H = int(cams[0]["width"]), int(cams[0]["height"])
+        _, self.cams_raw = core.Rays._cams_tensor(cams, self.device)
+        self.targets = torch.as_tensor(targets, dtype=torch.float32).to(self.device).reshape(-1, 3).contiguous()
+        self.n_rays = self.n_cams * self.W * self.H
+        if self.targets.shape[0] != self.n_rays:
+            raise ValueError("targets must hold one RGB value per pixel of every camera")
+        self.gen = torch.Generator(device=self.device)
+        self.gen.manual_seed(int(cfg.seed))
+        self.epoch = 0
+        self.opt_step = 0
+        self._reset_optimizer()
+
+    def _reset_optimizer(self):
+        t = self.tree
+        self.state = t.rmsprop_state() if self.cfg.optimizer == "rmsprop" else t.adam_state()
+        self.gs = torch.zeros(t.n_leaves, dtype=torch.float32, device=self.device)
+        self.gh = torch.zeros((t.n_leaves, 3, t.K), dtype=torch.float32, device=self.device)
+        self.opt_step = 0
+
+    def permutation(self):
+        return torch.randperm(self.n_rays, generator=self.gen, device=self.device)
+
+    def step(self, idx, signal=None):
+        """One optimisation step on the rays idx (int64 device tensor of pixel
+        indices into the flattened [n_cams, H, W] images).  Returns the batch
+        loss as a device float64 scalar."""
+        c = self.cfg
+        hw = self.W * self.H
+        rays = core.Rays.pixels_device(self.cams_raw, self.n_cams, (idx // hw).to(torch.int32),
+                                       (idx % hw).to(torch.int32))
+        mode = "sum" if c.signal == "sum" else "max"
+        rgb, nseg = self.tree.render(rays, bg=c.bg, t_stop=c.t_stop, nseg=True, signal=signal, signal_mode=mode)
+        loss, grad = core.mse_loss(rgb, self.targets, idx)
+        self.gs.zero_()
+        self.gh.zero_()
+        self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop)
+        self.opt_step += 1
+        if c.optimizer == "rmsprop":
+            self.tree.rmsprop_step(self.gs, self.gh, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
+                                   alpha=c.alpha, eps=c.eps)
+        else:
+            self.tree.adam_step(self.gs, self.gh, self.state, self.opt_step, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
+                                beta1=c.beta1, beta2=c.beta2, eps=c.eps)
+        return loss
+
+    def run_epoch(self, perm=None):
+        """One epoch of Alg. 1 (1-based epoch number i = self.epoch after the
+        call); refines when i is a multiple of the interval.  Returns a dict
+        with the batch losses (host) and, after a refinement, its statistics."""
+        c = self.cfg
+        self.epoch += 1
+        refine_now = c.refine and c.interval > 0 and self.epoch % c.interval == 0
+        if perm is None:
+            perm = self.permutation()
+        else:
+            perm = torch.as_tensor(perm, dtype=torch.int64).to(self.device)
+            if perm.shape[0] != self.n_rays:
+                raise ValueError("a permutation must cover every training ray")
+        signal = None
+        if refine_now and c.signal != "sigma":
+            signal = torch.zeros(self.tree.n_leaves, dtype=torch.float32, device=self.device)
+        losses = []
+        for b in range(0, self.n_rays, c.batch_rays):
+            losses.append(self.step(perm[b:b + c.batch_rays], signal))
+        out = dict(epoch=self.epoch, losses=torch.stack(losses).cpu().numpy() if losses else np.zeros(0))
+        if refine_now:
+            if c.signal == "sigma":
+                signal = self.tree.sigma_signal()
+            out["signal"] = signal
+            out["refine"] = self.tree.refine(signal, prune_tau=c.tau, sample_frac=c.gamma, max_depth=c.max_depth,
+                                             prune_le=c.prune_le, recursive=c.recursive, reinit=c.reinit)
+            self._reset_optimizer()
+        out["leaves"] = self.tree.n_leaves
+        return out
+
+    def train(self, epochs=None, callback=None):
+        hist = []
+        for _ in range(self.cfg.epochs if epochs is None else epochs):
+            r = self.run_epoch()
+            r.pop("signal", None)
+            hist.append(r)
+            if callback is not None:
+                callback(r)
+        return hist

@@ -57,7 +57,7 @@ def _compare(scene, signal, storage="f32", **kw):
                          O.round_storage(scene.sh.astype(np.float64), storage), scene.degree)
     R = O.refine(T, signal, tau=kw.get("prune_tau", 1e-3), sample_frac=kw.get("sample_frac", 0.05),
                  max_depth=kw.get("max_depth", 10), prune_le=kw.get("prune_le", True),
-                 recursive=kw.get("recursive", False), storage=storage)
+                 recursive=kw.get("recursive", False), storage=storage, reinit=kw.get("reinit", False))
     np.testing.assert_array_equal(ex["child"], R["child"])
     np.testing.assert_array_equal(ex["depth"].astype(np.int32), R["depth"])
     assert st["leaves_after"] == R["sigma"].shape[0]
@@ -123,6 +123,18 @@ def test_refine_recursive(seed):
     st, _ = _compare(u, np.zeros(u.n_leaves, np.float32), prune_tau=0.0, sample_frac=0.0, max_depth=4,
                      recursive=True)
     assert st["leaves_after"] == 1 and st["merged"] == 73
+
+
+@pytest.mark.parametrize("recursive", [False, True])
+def test_refine_reinit(recursive):
+    # the ablation without fusion: same topology, new leaves exactly zero
+    s = synth.random_tree_scene(5, 2, seed=31, p_split=0.5)
+    sig = _seeded_signal(s.n_leaves, 32, 0.9)
+    for storage in ("f32", "f16"):
+        st, n_ulp = _compare(s, sig, storage, prune_tau=2e-3, sample_frac=0.05, max_depth=6, recursive=recursive,
+                             reinit=True)
+        assert st["merged"] > 0 and st["subdivided"] > 0
+        assert n_ulp == 0
 
 
 def test_refine_then_render_matches_oracle():
