@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-config3", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--alg1-epochs", type=int, default=4, help="epochs of the end-to-end training loop (0: skip)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
     args = ap.parse_args()
@@ -204,6 +205,8 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
             tree.close()
         log(f"render {storage}: {kt * 1e3:.3f} ms, {mr:.1f} Mrays/s")
     res.update(train_step(torch, core, synth, args))
+    if args.alg1_epochs > 0:
+        res.update(alg1_loop(torch, core, synth, scene, args))
     res.update(refine_pass(torch, core, synth, scene))
     res.update(serving(torch, core, synth, scene, args))
     if not args.no_config3:
@@ -298,49 +301,29 @@ def config3_precision(torch, core, synth, args):
 
 
 def train_step(torch, core, synth, args):
-    """Config 4: forward + hand-written backward + Adam over 2^18 random rays of
-    100 views of the config-1 octree (SH perturbed by N(0, 0.05^2))."""
+    """Config 4: one optimisation step -- forward, MSE, hand-written backward,
+    Adam -- over 2^18 random rays of 100 views of the config-1 octree (SH
+    perturbed by N(0, 0.05^2)), through the training driver."""
+    from paper_2307_15333_amd import train as TR
     gt = synth.config1_scene()
-    train = synth.perturb_sh(gt, 0.05, seed=3)
+    start = synth.perturb_sh(gt, 0.05, seed=3)
     views = synth.config4_views(100)
     gt_tree = core.Octree.from_scene(gt)
-    tree = core.Octree.from_scene(train)
-    W = H = 64
-    all_rays = core.Rays.cameras(views)
-    target = gt_tree.render(all_rays)           # [100*64*64, 3]
+    target = gt_tree.render(core.Rays.cameras(views))           # [100*64*64, 3]
     gt_tree.close()
-    cams_raw = all_rays._keep[0]
-    n_pool = 100 * W * H
+    tree = core.Octree.from_scene(start)
     B = 1 << 18
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(3)
-    perm = torch.randperm(n_pool, device="cuda", generator=gen)
-    sig_v, sh_v = tree.plane_views()
-    sigma = sig_v.detach().requires_grad_()
-    sh = sh_v.detach().requires_grad_()
-    state = tree.adam_state()
-
-    def one(step_i, off):
-        idx = perm[off:off + B]
-        ci = (idx // (W * H)).to(torch.int32)
-        pi = (idx % (W * H)).to(torch.int32)
-        r = core.Rays.pixels_device(cams_raw, 100, ci, pi)
-        rgb = core.render_autograd(tree, sigma, sh, r)
-        loss = torch.mean((rgb - target[idx]) ** 2)
-        sigma.grad = None
-        sh.grad = None
-        loss.backward()
-        tree.adam_step(sigma.grad, sh.grad, state, step_i, lr_sigma=0.1, lr_sh=0.01)
-        return loss
-
-    losses = []
-    for i in range(2):
-        one(i + 1, 0)
+    tr = TR.Trainer(tree, views, target, TR.TrainConfig(optimizer="adam", batch_rays=B, refine=False, seed=3))
+    perm = tr.permutation()
+    idx = perm[:B]
+    for _ in range(2):
+        tr.step(idx)
     torch.cuda.synchronize()
     steps = 10
+    losses = []
     t = time.perf_counter()
-    for i in range(steps):
-        losses.append(one(3 + i, (i % 1) * B))
+    for _ in range(steps):
+        losses.append(tr.step(idx))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / steps
     tree.close()
@@ -348,6 +331,44 @@ def train_step(torch, core, synth, args):
     log(f"train step: {dt * 1e3:.3f} ms, {B / dt / 1e6:.1f} Mrays/s, loss {l0:.3e} -> {l1:.3e}")
     return {"train_step_ms": round(dt * 1e3, 3), "train_step_mrays": round(B / dt / 1e6, 1),
             "train_rays_per_step": B, "train_loss_first_last": [l0, l1]}
+
+
+def alg1_loop(torch, core, synth, scene, args):
+    """Alg. 1 end to end on the config-2 octree: 100 random 800x800 views of
+    the generator scene as targets (64M rays per epoch), training copy with SH
+    perturbed by N(0, 0.05^2); epochs of 2^20-ray batches, RMSProp (lr 0.1 /
+    0.01), refinement every 2nd epoch from the fused max-weight signal (prune
+    <= 1e-3, top 1% subdivided up to depth 10)."""
+    from paper_2307_15333_amd import train as TR
+    views = synth.config2_refine_views(100)
+    gt = core.Octree.from_scene(scene)
+    W, H = int(views[0]["width"]), int(views[0]["height"])
+    target = torch.empty((len(views) * W * H, 3), dtype=torch.float32, device="cuda")
+    for j in range(0, len(views), 10):
+        target[j * W * H:(j + 10) * W * H] = gt.render(core.Rays.cameras(views[j:j + 10]))
+    gt.close()
+    tree = core.Octree.from_scene(synth.perturb_sh(scene, 0.05, seed=3))
+    cfg = TR.TrainConfig(interval=2, batch_rays=1 << 20, tau=1e-3, gamma=0.01, max_depth=10, seed=1)
+    tr = TR.Trainer(tree, views, target, cfg)
+    epochs = []
+    for e in range(args.alg1_epochs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = tr.run_epoch()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        rec = {"epoch": r["epoch"], "ms": round(dt * 1e3, 1), "mrays": round(tr.n_rays / dt / 1e6, 1),
+               "loss_mean": float(r["losses"].mean()), "leaves": r["leaves"]}
+        if "refine" in r:
+            rec["refine"] = r["refine"]
+        epochs.append(rec)
+        log(f"alg1 epoch {rec['epoch']}: {rec['ms']:.0f} ms ({rec['mrays']:.0f} Mrays/s), loss {rec['loss_mean']:.3e},"
+            f" leaves {rec['leaves']}{' refined' if 'refine' in r else ''}")
+    tree.close()
+    plain = [x["ms"] for x in epochs if "refine" not in x]
+    return {"alg1_rays_per_epoch": tr.n_rays, "alg1_batch": cfg.batch_rays, "alg1_epochs": epochs,
+            "alg1_epoch_ms": min(plain) if plain else None,
+            "alg1_train_mrays": round(tr.n_rays / (min(plain) / 1e3) / 1e6, 1) if plain else None}
 
 
 def cpu_baseline(scene, cams):

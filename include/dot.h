@@ -191,9 +191,11 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  grad_sh: DEVICE float [n_leaves][3][K] (dense); both accumulated into (+=),
  *  the caller zeroes them.  Contributions are grouped into per-leaf buckets
  *  (a counting pass, a prefix scan, a pass that writes each segment's
- *  gradient row into its leaf's bucket, then per-leaf column sums), which
- *  needs device scratch of (1+3K) floats per contributing segment from the
- *  tree's allocator and synchronises `stream` once to size it; beyond 8 GiB of
+ *  compact gradient row -- dsigma, g_ch w c_ch (1 - c_ch) and the ray
+ *  direction -- into its leaf's bucket, then per-leaf sums that expand the SH
+ *  outer product), which needs device scratch of 32 B (16 B at degree 0) per
+ *  contributing segment from the tree's allocator and synchronises `stream`
+ *  once to size it; beyond 8 GiB of
  *  scratch, or if it cannot be allocated, the terms go straight to the
  *  arrays with FP32 atomics.  Summation order, hence the last bits, depends
  *  on scheduling.
@@ -274,11 +276,49 @@ int dot_rmsprop_step(dot_tree_t tree, const float *grad_sigma, const float *grad
                      float *v_sh, const dot_rmsprop_params *params, void *stream);
 
 /*
+ * dot_render_backward_rmsprop -- dot_render_backward followed by one
+ *  dot_rmsprop_step, fused: each leaf's bucket sums (its gradient) feed the
+ *  update directly, so the dense gradient arrays are neither zeroed, written
+ *  nor read back.  Same arithmetic as dot_render_backward into zeroed arrays
+ *  followed by dot_rmsprop_step; every leaf is updated (a leaf no ray reached
+ *  has g = 0: its square average decays, its values stay).  Arguments as in
+ *  those two calls.  When the bucket scratch cannot be used the call falls
+ *  back to dense gradients from the tree's allocator (DOT_ENOMEM if that
+ *  fails too).  FP32 storage only (DOT_EUNSUPPORTED otherwise).
+ */
+int dot_render_backward_rmsprop(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
+                                const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb, float *v_sigma,
+                                float *v_sh, const dot_rmsprop_params *params, void *stream);
+
+/*
  * dot_sigma_signal -- the density as the training signal (the paper's Pr_sigma
  *  ablation, Sec. 3.1 and Tab. 3): signal_out[l] = max(sigma_l, 0) decoded to
  *  FP32.  signal_out: DEVICE float [n_leaves].
  */
 int dot_sigma_signal(dot_tree_t tree, float *signal_out, void *stream);
+
+/*
+ * dot_pixel_batch -- a batch of training rays for one optimisation step
+ *  (Alg. 1: the rays are permuted each epoch and consumed batch by batch).
+ *  ray_ids: DEVICE int64 [n] flat pixel ids cam * H * W + v * W + u over
+ *  n_cams cameras of width x height (a slice of the epoch's permutation).
+ *  Writes the same rays as a DOT_RAYS_PIXELS list, cam_idx_out / pix_idx_out
+ *  (DEVICE int32 [n]), grouped by screen tile -- square tiles sized to hold
+ *  about 64 of the batch's rays, in camera-then-row-major tile order; order
+ *  inside a tile unspecified -- so that a wave traces neighbouring pixels.
+ *  ray_ids_out (DEVICE int64 [n] or NULL) receives the ids in the new order,
+ *  for use as the target rows of dot_mse_loss.  The batch's content is
+ *  unchanged (the loss is a mean and the gradient a sum over it).
+ *  workspace: DEVICE, at least dot_pixel_batch_workspace(n, width, height,
+ *  n_cams) bytes, caller-owned, clobbered.  An id outside [0, n_cams*H*W) is a
+ *  contract violation; it is replaced by 0 so no access leaves the arrays.
+ *  Errors: DOT_EINVAL on n < 0, non-positive sizes, more than 2^31 pixels per
+ *  image, NULL buffers with n > 0, or a workspace that is too small.
+ */
+size_t dot_pixel_batch_workspace(int64_t n_rays, int32_t width, int32_t height, int32_t n_cams);
+int dot_pixel_batch(const int64_t *ray_ids, int64_t n_rays, int32_t width, int32_t height, int32_t n_cams,
+                    int32_t *cam_idx_out, int32_t *pix_idx_out, int64_t *ray_ids_out, void *workspace,
+                    size_t workspace_bytes, void *stream);
 
 /*
  * dot_mse_loss -- the photometric loss of a training step (Sec. 3 and Alg. 1:

@@ -238,6 +238,15 @@ class Octree:
         L.check(self.lib.dot_rmsprop_step(self.handle, _ptr(grad_sigma), _ptr(grad_sh), _ptr(state["v_sigma"]),
                                           _ptr(state["v_sh"]), C.byref(p), _stream()))
 
+    def backward_rmsprop(self, rays, rgb, nseg, grad_rgb, state, lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8,
+                         bg=(1.0, 1.0, 1.0), t_stop=1e-4):
+        """Adjoint and RMSProp step in one call (no dense gradient arrays)."""
+        op = render_opts(bg, t_stop)
+        p = L.dot_rmsprop_params(lr_sigma=lr_sigma, lr_sh=lr_sh, alpha=alpha, eps=eps)
+        L.check(self.lib.dot_render_backward_rmsprop(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
+                                                     _ptr(nseg), _ptr(grad_rgb), _ptr(state["v_sigma"]),
+                                                     _ptr(state["v_sh"]), C.byref(p), _stream()))
+
     def rmsprop_state(self):
         Ln = self.n_leaves
         z = lambda *s: torch.zeros(s, dtype=torch.float32, device=self.device)
@@ -260,6 +269,24 @@ class Octree:
         L.check(self.lib.dot_export(self.handle, child.ctypes.data if I else None, sigma.ctypes.data,
                                     sh.ctypes.data, depth.ctypes.data, _stream()))
         return dict(child=child, sigma=sigma, sh=sh, depth=depth)
+
+
+def pixel_batch(ray_ids, width, height, n_cams, workspace=None):
+    """(cam_idx int32, pix_idx int32, ray_ids int64) of the flat pixel ids
+    `ray_ids` (int64 device [n]) in screen-tile order; `workspace` (uint8
+    device tensor) is reused when large enough.  Returns also the workspace."""
+    lib = L.load()
+    n = int(ray_ids.shape[0])
+    assert ray_ids.dtype == torch.int64 and ray_ids.is_contiguous()
+    need = int(lib.dot_pixel_batch_workspace(n, width, height, n_cams))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=ray_ids.device)
+    cam = torch.empty(n, dtype=torch.int32, device=ray_ids.device)
+    pix = torch.empty(n, dtype=torch.int32, device=ray_ids.device)
+    ids = torch.empty(n, dtype=torch.int64, device=ray_ids.device)
+    L.check(lib.dot_pixel_batch(_ptr(ray_ids), C.c_int64(n), int(width), int(height), int(n_cams), _ptr(cam),
+                                _ptr(pix), _ptr(ids), _ptr(workspace), C.c_size_t(workspace.numel()), _stream()))
+    return cam, pix, ids, workspace
 
 
 def mse_loss(pred, target, target_idx=None, grad=True, loss=True):

@@ -381,6 +381,36 @@ int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opt
     return DOT_OK;
 }
 
+int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts,
+                                const float* rgb_fwd, const int32_t* nseg, const float* grad_rgb, float* v_sigma,
+                                float* v_sh, const dot_rmsprop_params* params, void* stream) {
+    if (!t || !params) return fail(DOT_EINVAL, "dot_render_backward_rmsprop: NULL tree or params");
+    if (t->storage != DOT_F32)
+        return fail(DOT_EUNSUPPORTED, "dot_render_backward_rmsprop: only FP32 leaf storage is trainable");
+    if (!(params->alpha >= 0.f && params->alpha < 1.f))
+        return fail(DOT_EINVAL, "dot_render_backward_rmsprop: alpha must be in [0, 1)");
+    if (!v_sigma || !v_sh) return fail(DOT_EINVAL, "dot_render_backward_rmsprop: square-average buffers are required");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_render_backward_rmsprop");
+    if (rc) return rc;
+    if (rb.n_rays > 0 && (!rgb_fwd || !nseg || !grad_rgb))
+        return fail(DOT_EINVAL, "dot_render_backward_rmsprop: rgb_fwd, nseg and grad_rgb are required");
+    BwdArgs a{};
+    float bg[3];
+    rc = fill_opts(opts, bg, a.thr, "dot_render_backward_rmsprop");
+    if (rc) return rc;
+    a.rgb_fwd = rgb_fwd;
+    a.nseg = nseg;
+    a.grad_rgb = grad_rgb;
+    a.v_sigma = v_sigma;
+    a.v_sh = v_sh;
+    a.rms = params;
+    hipError_t e = launch_render_bwd(*t, rb, a, static_cast<hipStream_t>(stream));
+    if (e == hipErrorOutOfMemory) return fail(DOT_ENOMEM, "dot_render_backward_rmsprop: scratch allocation failed");
+    if (e != hipSuccess) return hip_fail(e, "dot_render_backward_rmsprop: launch");
+    return DOT_OK;
+}
+
 int dot_render_stats(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, int64_t counts[4],
                      void* stream) {
     if (!t || !counts) return fail(DOT_EINVAL, "dot_render_stats: NULL argument");
@@ -434,6 +464,30 @@ int dot_sigma_signal(dot_tree_t t, float* signal_out, void* stream) {
     if (!t || !signal_out) return fail(DOT_EINVAL, "dot_sigma_signal: NULL argument");
     hipError_t e = launch_sigma_signal(*t, signal_out, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_sigma_signal: launch");
+    return DOT_OK;
+}
+
+size_t dot_pixel_batch_workspace(int64_t n_rays, int32_t width, int32_t height, int32_t n_cams) {
+    if (n_rays < 0 || width <= 0 || height <= 0 || n_cams <= 0) return 0;
+    return pixel_batch_workspace_bytes(n_rays, width, height, n_cams);
+}
+
+int dot_pixel_batch(const int64_t* ray_ids, int64_t n_rays, int32_t width, int32_t height, int32_t n_cams,
+                    int32_t* cam_idx_out, int32_t* pix_idx_out, int64_t* ray_ids_out, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+    if (n_rays < 0) return fail(DOT_EINVAL, "dot_pixel_batch: n_rays < 0");
+    if (width <= 0 || height <= 0 || n_cams <= 0)
+        return fail(DOT_EINVAL, "dot_pixel_batch: width, height and n_cams must be positive");
+    if ((int64_t)width * height > INT32_MAX) return fail(DOT_EINVAL, "dot_pixel_batch: image larger than 2^31 pixels");
+    if (n_rays > (int64_t)UINT32_MAX) return fail(DOT_EINVAL, "dot_pixel_batch: more than 2^32 - 1 rays");
+    if (n_rays == 0) return DOT_OK;
+    if (!ray_ids || !cam_idx_out || !pix_idx_out || !workspace)
+        return fail(DOT_EINVAL, "dot_pixel_batch: NULL ids, outputs or workspace");
+    if (workspace_bytes < pixel_batch_workspace_bytes(n_rays, width, height, n_cams))
+        return fail(DOT_EINVAL, "dot_pixel_batch: workspace too small");
+    hipError_t e = launch_pixel_batch(ray_ids, n_rays, width, height, n_cams, cam_idx_out, pix_idx_out, ray_ids_out,
+                                      workspace, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_pixel_batch: launch");
     return DOT_OK;
 }
 

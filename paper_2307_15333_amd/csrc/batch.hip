@@ -1,0 +1,104 @@
+// Training-batch preparation: a batch of training rays given as flat pixel ids
+// (cam * H * W + v * W + u, a slice of the epoch's random permutation) becomes
+// a (camera, pixel) ray list grouped by screen tile, so that the 64 lanes of a
+// wave trace neighbouring pixels of one camera and share the leaves they
+// fetch.  A counting sort: per-tile counts, an exclusive scan, a scatter.
+// The batch's content is unchanged; only its order is (the loss is a mean and
+// the gradient a sum over the batch).
+#include <hip/hip_runtime.h>
+
+#include "dot_internal.h"
+
+namespace dot {
+
+namespace {
+
+struct PixelGeo {
+    int32_t W, H, shift, tw;
+    int64_t tpv;      // tiles per camera
+    int64_t total;    // n_cams * W * H
+    int64_t bins;     // n_cams * tpv
+};
+
+// tile edge 2^shift chosen so a tile holds about one wave of the batch's rays
+PixelGeo make_geo(int64_t n, int32_t W, int32_t H, int32_t n_cams) {
+    PixelGeo g;
+    g.W = W;
+    g.H = H;
+    g.total = (int64_t)n_cams * W * H;
+    const double density = g.total > 0 ? (double)n / (double)g.total : 1.0;
+    int shift = 3;
+    while (shift < 7 && (double)(1 << (2 * shift)) * density < 64.0) ++shift;
+    g.shift = shift;
+    g.tw = (W + (1 << shift) - 1) >> shift;
+    g.tpv = (int64_t)g.tw * ((H + (1 << shift) - 1) >> shift);
+    g.bins = (int64_t)n_cams * g.tpv;
+    return g;
+}
+
+__device__ __forceinline__ int64_t tile_bin(int64_t& id, const PixelGeo& g, int32_t& cam, int32_t& pix) {
+    if (id < 0 || id >= g.total) id = 0;   // outside the image set: replaced by ray 0 (documented)
+    const int64_t hw = (int64_t)g.W * g.H;
+    cam = (int32_t)(id / hw);
+    pix = (int32_t)(id - (int64_t)cam * hw);
+    const int v = pix / g.W, u = pix - v * g.W;
+    return (int64_t)cam * g.tpv + (int64_t)(v >> g.shift) * g.tw + (u >> g.shift);
+}
+
+__global__ void k_pb_zero(uint32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_pb_count(const int64_t* __restrict__ ids, int64_t n, PixelGeo g, uint32_t* __restrict__ count) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t id = ids[r];
+        int32_t cam, pix;
+        atomicAdd(&count[tile_bin(id, g, cam, pix)], 1u);
+    }
+}
+
+__global__ void k_pb_scatter(const int64_t* __restrict__ ids, int64_t n, PixelGeo g, uint32_t* __restrict__ cursor,
+                             int32_t* __restrict__ cam_out, int32_t* __restrict__ pix_out,
+                             int64_t* __restrict__ id_out) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t id = ids[r];
+        int32_t cam, pix;
+        const int64_t b = tile_bin(id, g, cam, pix);
+        const uint32_t pos = atomicAdd(&cursor[b], 1u);
+        cam_out[pos] = cam;
+        pix_out[pos] = pix;
+        if (id_out) id_out[pos] = id;
+    }
+}
+
+unsigned grid_of(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+}  // namespace
+
+size_t pixel_batch_workspace_bytes(int64_t n, int32_t W, int32_t H, int32_t n_cams) {
+    const PixelGeo g = make_geo(n, W, H, n_cams);
+    return sizeof(uint32_t) * (size_t)(2 * g.bins + scan_scratch_elems(g.bins) + 1);
+}
+
+hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t H, int32_t n_cams, int32_t* cam_out,
+                              int32_t* pix_out, int64_t* id_out, void* ws, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const PixelGeo g = make_geo(n, W, H, n_cams);
+    uint32_t* count = static_cast<uint32_t*>(ws);
+    uint32_t* cursor = count + g.bins;
+    uint32_t* bsum = cursor + g.bins;
+    uint32_t* tot = bsum + scan_scratch_elems(g.bins);
+    hipLaunchKernelGGL(k_pb_zero, dim3(grid_of(g.bins)), dim3(256), 0, s, count, g.bins);
+    hipLaunchKernelGGL(k_pb_count, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, count);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = scan_u32(count, cursor, g.bins, bsum, tot, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pb_scatter, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, cursor, cam_out, pix_out, id_out);
+    return hipGetLastError();
+}
+
+}  // namespace dot

@@ -118,7 +118,17 @@ struct BwdArgs {
     float* grad_sigma;
     float* grad_sh;
     float thr;
+    // fused RMSProp (grad_* unused): square averages and parameters, or null
+    float* v_sigma;
+    float* v_sh;
+    const dot_rmsprop_params* rms;
 };
+
+// RMSProp on one parameter: v = alpha v + (1 - alpha) g^2; theta -= lr g / (sqrt(v) + eps)
+__device__ __forceinline__ void rmsprop_update(float& theta, float& v, float g, float lr, float alpha, float eps) {
+    v = alpha * v + (1.f - alpha) * g * g;
+    theta -= lr * g / (sqrtf(v) + eps);
+}
 
 hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArgs& a, hipStream_t s);
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
@@ -137,6 +147,9 @@ hipError_t launch_rmsprop(const dot_tree& t, const float* gs, const float* gh, f
 hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s);
 hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx, int64_t n, float* grad,
                       double* loss, hipStream_t s);
+size_t pixel_batch_workspace_bytes(int64_t n, int32_t W, int32_t H, int32_t n_cams);
+hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t H, int32_t n_cams, int32_t* cam_out,
+                              int32_t* pix_out, int64_t* id_out, void* ws, hipStream_t s);
 size_t jobs_workspace_bytes(int n_jobs);
 int launch_render_jobs(const dot_render_job* jobs, int n_jobs, void* ws, size_t ws_bytes, hipStream_t s);
 int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st,

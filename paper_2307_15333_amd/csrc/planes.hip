@@ -148,9 +148,10 @@ __global__ void rmsprop_kernel(float* __restrict__ sigma, float* __restrict__ sh
             theta = &sh[r * stride + c];
             lr = p.lr_sh;
         }
-        float v = p.alpha * *vp + (1.f - p.alpha) * g * g;
+        float v = *vp, th = *theta;
+        rmsprop_update(th, v, g, lr, p.alpha, p.eps);
         *vp = v;
-        *theta -= lr * g / (sqrtf(v) + p.eps);
+        *theta = th;
     }
 }
 

@@ -125,7 +125,11 @@ __global__ __launch_bounds__(BLOCK) void render_bwd_kernel(TreeView tv, RayBatch
 // leaves.  Instead: (1) count the contributing segments of every leaf, (2)
 // scan the counts into bucket offsets, (3) write each segment's gradient row
 // into its leaf's bucket (one integer atomic per segment picks the slot), and
-// (4) sum every bucket column-wise into the gradient arrays.
+// (4) reduce every bucket into the gradient arrays.  The SH gradient of a
+// segment is the outer product a_ch Y_k(d) with a_ch = g_ch w c_ch (1 - c_ch),
+// so a row stores dsigma, a[3] and the ray direction (8 floats; 4 at degree 0,
+// where Y is constant) and the reduction re-evaluates Y(d) -- 32 B per segment
+// instead of (1 + 3K) floats.
 // ---------------------------------------------------------------------------
 template <int DT>
 struct BwdCount {
@@ -140,16 +144,22 @@ struct BwdCount {
     }
 };
 
+// floats per bucket row: dsigma, a[3], then the direction when Y depends on it
+template <int DEG>
+constexpr int bwd_row_floats() { return DEG == 0 ? 4 : 8; }
+inline int bwd_row_floats_rt(int deg) { return deg == 0 ? 4 : 8; }
+
 template <int DT, int DEG>
 struct BwdEmit {
     static constexpr int K = (DEG + 1) * (DEG + 1);
-    static constexpr int RS = (1 + 3 * K + 3) / 4 * 4;   // row stride (floats), 16-byte rows
+    static constexpr int RS = bwd_row_floats<DEG>();
     const TreeView& tv;
     const uint32_t* offset;
     const uint32_t* count;
     uint32_t* cursor;
     float* rows;
     float Y[K];
+    float d[3];
     float S = 0.f, T = 1.f;
     float C[3], g[3];
     float P[3] = {0.f, 0.f, 0.f};
@@ -185,13 +195,13 @@ struct BwdEmit {
             }
             out[0] = gs * delta;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float f = g[ch] * w * c[ch] * (1.f - c[ch]);
-#pragma unroll
-                for (int k = 0; k < K; ++k) out[1 + ch * K + k] = f * Y[k];
+            for (int ch = 0; ch < 3; ++ch) out[1 + ch] = w > 0.f ? g[ch] * w * c[ch] * (1.f - c[ch]) : 0.f;
+            if constexpr (RS == 8) {
+                out[4] = d[0];
+                out[5] = d[1];
+                out[6] = d[2];
+                out[7] = 0.f;
             }
-#pragma unroll
-            for (int j = 1 + 3 * K; j < RS; ++j) out[j] = 0.f;
             // the bucket holds exactly the segments the counting pass found; a
             // slot past it is never written (the reduction reads written rows only)
             uint32_t k = atomicAdd(&cursor[leaf], 1u);
@@ -246,28 +256,86 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_kernel(TreeView tv, RayBatch r
         seg.g[ch] = a.grad_rgb[3 * rid + ch];
     }
     if (seg.g[0] == 0.f && seg.g[1] == 0.f && seg.g[2] == 0.f) return;
-    sh_basis<DEG>((float)r.dx, (float)r.dy, (float)r.dz, seg.Y);
+    seg.d[0] = (float)r.dx;
+    seg.d[1] = (float)r.dy;
+    seg.d[2] = (float)r.dz;
+    sh_basis<DEG>(seg.d[0], seg.d[1], seg.d[2], seg.Y);
     int desc = 0;
     traverse(tv, r, &stack_lds[tid], seg, desc);
 }
 
-// column sums of every leaf's bucket: thread (leaf, column), columns contiguous
-__global__ void bwd_reduce_kernel(int64_t L, int ncol, int rs, const uint32_t* __restrict__ offset,
-                                  const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor,
-                                  const float* __restrict__ rows, float* __restrict__ gsig, float* __restrict__ gsh) {
-    const int64_t n = L * ncol;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t l = i / ncol;
-        int c = (int)(i - l * ncol);
-        uint32_t m = min(count[l], cursor[l]);
-        if (m == 0) continue;
-        const float* p = rows + (int64_t)offset[l] * rs + c;
-        float acc = 0.f;
-        for (uint32_t r = 0; r < m; ++r) acc += p[(int64_t)r * rs];
-        if (c == 0)
-            gsig[l] += acc;
-        else
-            gsh[l * (ncol - 1) + (c - 1)] += acc;
+// Sum of one leaf's bucket: dsigma and, per channel, sum_rows a_ch Y_k(d_row).
+template <int DEG>
+__device__ __forceinline__ bool bucket_sum(int64_t l, const uint32_t* __restrict__ offset,
+                                           const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor,
+                                           const float* __restrict__ rows, float& gs, float* acc) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int RS = bwd_row_floats<DEG>();
+    const uint32_t m = min(count[l], cursor[l]);
+    gs = 0.f;
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) acc[j] = 0.f;
+    if (m == 0) return false;
+    const float4* p = reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS);
+    for (uint32_t r = 0; r < m; ++r) {
+        const float4 h = p[(int64_t)r * (RS / 4)];
+        float Y[K];
+        if constexpr (RS == 8) {
+            const float4 q = p[(int64_t)r * 2 + 1];
+            sh_basis<DEG>(q.x, q.y, q.z, Y);
+        } else {
+            sh_basis<DEG>(0.f, 0.f, 1.f, Y);
+        }
+        gs += h.x;
+        const float a[3] = {h.y, h.z, h.w};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[ch * K + k] += a[ch] * Y[k];
+    }
+    return true;
+}
+
+// one thread per leaf: add the leaf's bucket sums to the gradient arrays
+template <int DEG>
+__global__ void bwd_reduce_kernel(int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ count,
+                                  const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
+                                  float* __restrict__ gsig, float* __restrict__ gsh) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L; l += (int64_t)gridDim.x * blockDim.x) {
+        float gs, acc[3 * K];
+        if (!bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc)) continue;
+        gsig[l] += gs;
+        float* o = gsh + l * (3 * K);
+#pragma unroll
+        for (int j = 0; j < 3 * K; ++j) o[j] += acc[j];
+    }
+}
+
+// one thread per leaf, every leaf: the bucket sums are the leaf's gradient and
+// feed RMSProp directly (untouched leaves: g = 0, so only v decays)
+template <int DEG>
+__global__ void bwd_rmsprop_kernel(int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ count,
+                                   const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
+                                   float* __restrict__ sigma, float* __restrict__ sh, int stride,
+                                   float* __restrict__ vs, float* __restrict__ vh, dot_rmsprop_params p) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L; l += (int64_t)gridDim.x * blockDim.x) {
+        float gs, acc[3 * K];
+        bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc);
+        float th = sigma[l], v = vs[l];
+        rmsprop_update(th, v, gs, p.lr_sigma, p.alpha, p.eps);
+        sigma[l] = th;
+        vs[l] = v;
+        float* o = sh + l * stride;
+        float* w = vh + l * (3 * K);
+#pragma unroll
+        for (int j = 0; j < 3 * K; ++j) {
+            float t = o[j], u = w[j];
+            rmsprop_update(t, u, acc[j], p.lr_sh, p.alpha, p.eps);
+            o[j] = t;
+            w[j] = u;
+        }
     }
 }
 
@@ -343,13 +411,51 @@ static void launch_emit(int deg, const TreeView& tv, const RayBatch& rb, const B
 // bucket scratch beyond this many bytes falls back to the atomic adjoint
 static constexpr double kBucketBytesMax = 8.0 * (1ull << 30);
 
+static hipError_t bwd_rmsprop_dense(const dot_tree& t, const RayBatch& rb, const BwdArgs& a0, dim3 grid,
+                                    hipStream_t s);
+static hipError_t launch_rmsprop_zero_grad(const dot_tree& t, const BwdArgs& a, hipStream_t s) {
+    RayBatch none{};
+    return bwd_rmsprop_dense(t, none, a, dim3(1), s);
+}
+
+// Fused path when the buckets cannot be used: dense gradients from the atomic
+// adjoint, then the elementwise RMSProp step.
+static hipError_t bwd_rmsprop_dense(const dot_tree& t, const RayBatch& rb, const BwdArgs& a0, dim3 grid,
+                                    hipStream_t s) {
+    const int nv = 3 * (t.degree + 1) * (t.degree + 1);
+    float* g = static_cast<float*>(t.alloc.get((size_t)t.n_leaves * (1 + nv) * 4));
+    if (!g) return hipErrorOutOfMemory;
+    BwdArgs a = a0;
+    a.grad_sigma = g;
+    a.grad_sh = g + t.n_leaves;
+    const int64_t n = t.n_leaves * (1 + nv);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t*>(g), n);
+    hipError_t e = rb.n_tiles ? bwd_atomic(t, rb, a, grid, s) : hipGetLastError();
+    if (e == hipSuccess) e = launch_rmsprop(t, a.grad_sigma, a.grad_sh, a.v_sigma, a.v_sh, *a.rms, s);
+    t.alloc.put(g);
+    return e;
+}
+
+template <int DEG>
+static void launch_bwd_rmsprop(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* count,
+                               const uint32_t* cursor, const float* rows, hipStream_t s) {
+    const int64_t L = t.n_leaves;
+    unsigned rg = (unsigned)std::min<int64_t>((L + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(bwd_rmsprop_kernel<DEG>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows,
+                       static_cast<float*>(t.sigma), static_cast<float*>(t.sh), t.sh_stride, a.v_sigma, a.v_sh,
+                       *a.rms);
+}
+
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s) {
-    if (rb.n_tiles == 0) return hipSuccess;
+    const bool fused = a.rms != nullptr;
+    if (rb.n_tiles == 0) {
+        // no rays: a fused step still decays the square averages (g = 0)
+        return fused ? launch_rmsprop_zero_grad(t, a, s) : hipSuccess;
+    }
     dim3 grid((unsigned)((rb.n_tiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
     const int64_t L = t.n_leaves;
-    const int K = (t.degree + 1) * (t.degree + 1);
-    const int ncol = 1 + 3 * K;
-    const int rs = (ncol + 3) / 4 * 4;
+    const int rs = bwd_row_floats_rt(t.degree);
     TreeView tv = t.view();
     uint32_t* count = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
     uint32_t* offset = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
@@ -365,7 +471,7 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     };
     if (!count || !offset || !cursor || !bsum || !tot) {
         drop();
-        return bwd_atomic(t, rb, a, grid, s);
+        return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     unsigned fg = (unsigned)std::min<int64_t>((L + 255) / 256, 65536);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count, L);
@@ -387,16 +493,27 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     if ((double)m * rs * 4 <= kBucketBytesMax) rows = static_cast<float*>(t.alloc.get((size_t)std::max<uint32_t>(m, 1) * rs * 4));
     if (!rows) {
         drop();
-        return bwd_atomic(t, rb, a, grid, s);
+        return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     switch (t.storage) {
         case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
         case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
         default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
     }
-    unsigned rg = (unsigned)std::min<int64_t>((L * ncol + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(bwd_reduce_kernel, dim3(rg), dim3(256), 0, s, L, ncol, rs, offset, count, cursor, rows,
-                       a.grad_sigma, a.grad_sh);
+    unsigned rg = (unsigned)std::min<int64_t>((L + 255) / 256, 1 << 20);
+    if (fused) {
+        switch (t.degree) {
+            case 0: launch_bwd_rmsprop<0>(t, a, offset, count, cursor, rows, s); break;
+            case 1: launch_bwd_rmsprop<1>(t, a, offset, count, cursor, rows, s); break;
+            case 2: launch_bwd_rmsprop<2>(t, a, offset, count, cursor, rows, s); break;
+            default: launch_bwd_rmsprop<3>(t, a, offset, count, cursor, rows, s); break;
+        }
+    } else switch (t.degree) {
+        case 0: hipLaunchKernelGGL(bwd_reduce_kernel<0>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 1: hipLaunchKernelGGL(bwd_reduce_kernel<1>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 2: hipLaunchKernelGGL(bwd_reduce_kernel<2>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        default: hipLaunchKernelGGL(bwd_reduce_kernel<3>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+    }
     e = hipGetLastError();
     t.alloc.put(rows);
     drop();

@@ -12,8 +12,10 @@ features or, for the ablation without fusion, fresh zero-valued leaves.  The
 optimiser state restarts from zero after a refinement, since the leaf set
 changed.
 
-Everything per ray and per leaf runs in libdot's kernels; this module
-only sequences the calls and slices the permuted ray order into batches.
+Everything per ray and per leaf runs in libdot's kernels (a batch is put in
+screen-tile order by dot_pixel_batch before it is rendered, so a wave traces
+neighbouring pixels); this module only sequences the calls and slices the
+permuted ray order into batches.
 """
 from __future__ import annotations
 
@@ -45,6 +47,7 @@ class TrainConfig:
     recursive: bool = False
     reinit: bool = False            # ablation: new leaves start at zero instead of fused values
     refine: bool = True
+    fused: bool = True              # RMSProp applied inside the adjoint's per-leaf reduction
     bg: tuple = (1.0, 1.0, 1.0)
     t_stop: float = 1e-4
     seed: int = 0
@@ -78,13 +81,13 @@ class Trainer:
         self.gen.manual_seed(int(cfg.seed))
         self.epoch = 0
         self.opt_step = 0
+        self._ws = None
         self._reset_optimizer()
 
     def _reset_optimizer(self):
         t = self.tree
         self.state = t.rmsprop_state() if self.cfg.optimizer == "rmsprop" else t.adam_state()
-        self.gs = torch.zeros(t.n_leaves, dtype=torch.float32, device=self.device)
-        self.gh = torch.zeros((t.n_leaves, 3, t.K), dtype=torch.float32, device=self.device)
+        self.gs = self.gh = None      # dense gradients, for the unfused optimiser steps only
         self.opt_step = 0
 
     def permutation(self):
@@ -95,16 +98,25 @@ class Trainer:
         indices into the flattened [n_cams, H, W] images).  Returns the batch
         loss as a device float64 scalar."""
         c = self.cfg
-        hw = self.W * self.H
-        rays = core.Rays.pixels_device(self.cams_raw, self.n_cams, (idx // hw).to(torch.int32),
-                                       (idx % hw).to(torch.int32))
+        cam, pix, ids, self._ws = core.pixel_batch(idx.contiguous(), self.W, self.H, self.n_cams, self._ws)
+        rays = core.Rays.pixels_device(self.cams_raw, self.n_cams, cam, pix)
         mode = "sum" if c.signal == "sum" else "max"
         rgb, nseg = self.tree.render(rays, bg=c.bg, t_stop=c.t_stop, nseg=True, signal=signal, signal_mode=mode)
-        loss, grad = core.mse_loss(rgb, self.targets, idx)
-        self.gs.zero_()
-        self.gh.zero_()
-        self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop)
+        loss, grad = core.mse_loss(rgb, self.targets, ids)
         self.opt_step += 1
+        if c.optimizer == "rmsprop" and c.fused:
+            # adjoint and update in one call: the gradient never exists as dense arrays
+            self.tree.backward_rmsprop(rays, rgb, nseg, grad, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
+                                       alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop)
+            return loss
+        if self.gs is None:
+            t = self.tree
+            self.gs = torch.zeros(t.n_leaves, dtype=torch.float32, device=self.device)
+            self.gh = torch.zeros((t.n_leaves, 3, t.K), dtype=torch.float32, device=self.device)
+        else:
+            self.gs.zero_()
+            self.gh.zero_()
+        self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop)
         if c.optimizer == "rmsprop":
             self.tree.rmsprop_step(self.gs, self.gh, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
                                    alpha=c.alpha, eps=c.eps)

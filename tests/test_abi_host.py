@@ -144,3 +144,23 @@ def test_calls_on_null_handles_fail_cleanly():
     assert lib.dot_tree_info(None, C.byref(info)) == L.DOT_EINVAL
     p = L.dot_refine_params()
     assert lib.dot_refine(None, None, C.byref(p), None, None) == L.DOT_EINVAL
+    rp = L.dot_rmsprop_params(lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8)
+    assert lib.dot_rmsprop_step(None, None, None, None, None, C.byref(rp), None) == L.DOT_EINVAL
+    assert lib.dot_sigma_signal(None, None, None) == L.DOT_EINVAL
+
+
+def test_batch_and_loss_argument_checks_need_no_device():
+    lib = L.load()
+    assert lib.dot_mse_loss(None, None, None, -1, None, None, None) == L.DOT_EINVAL
+    assert lib.dot_mse_loss(None, None, None, 5, None, None, None) == L.DOT_EINVAL
+    assert lib.dot_pixel_batch(None, -1, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
+    assert lib.dot_pixel_batch(None, 4, 0, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
+    assert lib.dot_pixel_batch(None, 4, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
+    assert lib.dot_pixel_batch(None, 4, 70000, 70000, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
+    assert b"2^31" in lib.dot_last_error()
+    assert lib.dot_pixel_batch(None, 0, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_OK
+    # a sparser batch uses larger tiles (each holds ~64 of its rays), hence fewer bins
+    w_dense = lib.dot_pixel_batch_workspace(1 << 20, 800, 800, 2)
+    w_sparse = lib.dot_pixel_batch_workspace(1 << 10, 800, 800, 2)
+    assert 0 < w_sparse < w_dense
+    assert lib.dot_pixel_batch_workspace(4, 4, 4, 0) == 0

@@ -67,6 +67,47 @@ def test_mse_loss_matches_oracle():
         assert g2 is None and l2.item() == pytest.approx(ref_l, rel=1e-12, abs=0)
 
 
+def _tile_shift(n, total):
+    # documented rule: the smallest tile edge 2^s (8 <= 2^s <= 128) holding ~64 rays of the batch
+    s = 3
+    while s < 7 and (1 << (2 * s)) * (n / total) < 64.0:
+        s += 1
+    return s
+
+
+@pytest.mark.parametrize("n_cams,W,H,n", [(3, 40, 24, 0), (3, 40, 24, 1), (3, 40, 24, 2000), (100, 800, 800, 1 << 20),
+                                          (5, 37, 53, 9805)])
+def test_pixel_batch_orders_a_batch_by_tile(n_cams, W, H, n):
+    core = _core()
+    total = n_cams * W * H
+    rng = np.random.default_rng(n)
+    ids = rng.choice(total, size=n, replace=False).astype(np.int64)
+    cam, pix, out, _ = core.pixel_batch(torch.as_tensor(ids, device="cuda"), W, H, n_cams)
+    cam, pix, out = cam.cpu().numpy(), pix.cpu().numpy(), out.cpu().numpy()
+    assert np.array_equal(np.sort(out), np.sort(ids))                 # same rays
+    assert np.array_equal(out, cam.astype(np.int64) * W * H + pix)    # consistent lists
+    s = _tile_shift(n, total)
+    u, v = pix % W, pix // W
+    tw, th = -(-W // (1 << s)), -(-H // (1 << s))
+    b = cam.astype(np.int64) * tw * th + (v >> s) * tw + (u >> s)
+    assert np.all(np.diff(b) >= 0)                                     # tile order
+
+
+def test_pixel_batch_replaces_invalid_ids_and_checks_arguments():
+    from paper_2307_15333_amd import _lib as L
+    core = _core()
+    ids = torch.tensor([5, -3, 10 ** 9, 7], dtype=torch.int64, device="cuda")
+    cam, pix, out, ws = core.pixel_batch(ids, 4, 4, 2)
+    assert sorted(out.cpu().tolist()) == [0, 0, 5, 7]
+    lib = L.load()
+    with pytest.raises(L.DotError):
+        L.check(lib.dot_pixel_batch(None, 4, 4, 4, 2, None, None, None, None, 0, None))
+    with pytest.raises(L.DotError):
+        L.check(lib.dot_pixel_batch(ids.data_ptr(), 4, 4, 4, 2, cam.data_ptr(), pix.data_ptr(), None, ws.data_ptr(),
+                                    0, None))
+    assert lib.dot_pixel_batch_workspace(4, 0, 4, 2) == 0
+
+
 def test_rmsprop_step_matches_oracle():
     core = _core()
     s = synth.random_tree_scene(4, 2, seed=13)
@@ -88,6 +129,46 @@ def test_rmsprop_step_matches_oracle():
     np.testing.assert_allclose(ex["sh"], th_h, rtol=2e-6, atol=2e-6)
     np.testing.assert_allclose(st["v_sigma"].cpu().numpy(), v_s, rtol=2e-6, atol=0)
     np.testing.assert_allclose(st["v_sh"].cpu().numpy(), v_h, rtol=2e-6, atol=0)
+    tree.close()
+
+
+@pytest.mark.parametrize("degree", [0, 3])
+def test_fused_backward_rmsprop_matches_oracle(degree):
+    """Adjoint + RMSProp in one call against the oracle's gradient followed by
+    the FP64 RMSProp update (eps = 1e-4 keeps the update Lipschitz in the
+    gradient, see the loop tolerances below); then an empty batch, which only
+    decays the square averages."""
+    core = _core()
+    s = synth.random_tree_scene(5, degree, seed=40 + degree)
+    s = dataclasses.replace(s, sigma64=np.where(s.sigma64 < 1e-6, 0.0, s.sigma64))
+    views = synth.random_sphere_cameras(6, 3.5, 32, 32, seed=7)
+    ci, pi = synth.pixel_batch(6, 32, 32, 3000, seed=8)
+    rays = core.Rays.pixels(views, ci, pi)
+    o, d = O.camera_rays(views, ci, pi)
+    g = np.random.default_rng(9).normal(size=(ci.shape[0], 3)) * 1e-3
+    tree = core.Octree.from_scene(s)
+    st = tree.rmsprop_state()
+    v0s = np.random.default_rng(10).uniform(0, 1e-6, size=tree.n_leaves).astype(np.float32)
+    st["v_sigma"].copy_(torch.as_tensor(v0s))
+    rgb, ns = tree.render(rays, nseg=True)
+    tree.backward_rmsprop(rays, rgb, ns, torch.as_tensor(g, dtype=torch.float32, device="cuda"), st, eps=1e-4)
+    ex = tree.export()
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    gs, gh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64))
+    ws, vs = A.rmsprop(s.sigma.astype(np.float64), gs, v0s.astype(np.float64), 0.1, 0.99, 1e-4)
+    wh, vh = A.rmsprop(s.sh.astype(np.float64), gh, np.zeros_like(gh), 0.01, 0.99, 1e-4)
+    np.testing.assert_allclose(ex["sigma"], ws, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(ex["sh"], wh, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(st["v_sigma"].cpu().numpy(), vs, rtol=1e-4, atol=1e-18)
+    np.testing.assert_allclose(st["v_sh"].cpu().numpy(), vh, rtol=1e-4, atol=1e-18)
+    # an empty batch: g = 0 everywhere, values unchanged, averages decay by alpha
+    v1 = st["v_sigma"].clone()
+    empty = core.Rays.pixels(views, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    z = torch.zeros((0, 3), device="cuda")
+    tree.backward_rmsprop(empty, z, torch.zeros(0, dtype=torch.int32, device="cuda"), z, st, eps=1e-4)
+    ex2 = tree.export()
+    np.testing.assert_array_equal(ex2["sigma"], ex["sigma"])
+    np.testing.assert_array_equal(st["v_sigma"].cpu().numpy(), (v1 * np.float32(0.99)).cpu().numpy())
     tree.close()
 
 
