@@ -277,65 +277,107 @@ __device__ __forceinline__ bool bucket_sum(int64_t l, const uint32_t* __restrict
     for (int j = 0; j < 3 * K; ++j) acc[j] = 0.f;
     if (m == 0) return false;
     const float4* p = reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS);
-    for (uint32_t r = 0; r < m; ++r) {
-        const float4 h = p[(int64_t)r * (RS / 4)];
+    constexpr int Q = RS / 4;     // float4 per row
+    constexpr int U = 4;          // rows whose loads are issued together
+    auto add_row = [&](const float4 h, const float4 q) {
         float Y[K];
-        if constexpr (RS == 8) {
-            const float4 q = p[(int64_t)r * 2 + 1];
+        if constexpr (RS == 8)
             sh_basis<DEG>(q.x, q.y, q.z, Y);
-        } else {
+        else
             sh_basis<DEG>(0.f, 0.f, 1.f, Y);
-        }
         gs += h.x;
         const float a[3] = {h.y, h.z, h.w};
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
 #pragma unroll
             for (int k = 0; k < K; ++k) acc[ch * K + k] += a[ch] * Y[k];
+    };
+    uint32_t r = 0;
+    for (; r + U <= m; r += U) {
+        float4 h[U], q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            h[u] = p[(int64_t)(r + u) * Q];
+            q[u] = Q == 2 ? p[(int64_t)(r + u) * Q + (Q - 1)] : h[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add_row(h[u], q[u]);
+    }
+    for (; r < m; ++r) {
+        const float4 h = p[(int64_t)r * Q];
+        add_row(h, Q == 2 ? p[(int64_t)r * Q + (Q - 1)] : h);
     }
     return true;
 }
 
-// one thread per leaf: add the leaf's bucket sums to the gradient arrays
+// Bucket reductions: one thread per leaf sums its bucket into registers, the
+// block stages the SH sums of its 256 leaves in LDS, then all threads walk the
+// block's contiguous range of the [L][3K] arrays so that loads and stores are
+// coalesced (a thread-per-leaf row of 3K floats would touch a new cache line
+// per lane and instruction).
+constexpr int RED_BLOCK = 256;
+
 template <int DEG>
-__global__ void bwd_reduce_kernel(int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ count,
-                                  const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
-                                  float* __restrict__ gsig, float* __restrict__ gsh) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L; l += (int64_t)gridDim.x * blockDim.x) {
-        float gs, acc[3 * K];
-        if (!bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc)) continue;
-        gsig[l] += gs;
-        float* o = gsh + l * (3 * K);
+__global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const uint32_t* __restrict__ offset,
+                                                               const uint32_t* __restrict__ count,
+                                                               const uint32_t* __restrict__ cursor,
+                                                               const float* __restrict__ rows,
+                                                               float* __restrict__ gsig, float* __restrict__ gsh) {
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
+    __shared__ float stage[RED_BLOCK * NV];
+    const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
+    const int64_t l = l0 + threadIdx.x;
+    float gs = 0.f, acc[NV];
 #pragma unroll
-        for (int j = 0; j < 3 * K; ++j) o[j] += acc[j];
+    for (int j = 0; j < NV; ++j) acc[j] = 0.f;
+    if (l < L && bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc)) gsig[l] += gs;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) stage[threadIdx.x * NV + j] = acc[j];
+    __syncthreads();
+    const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
+    float* o = gsh + l0 * NV;
+    for (int i = threadIdx.x; i < nl * NV; i += RED_BLOCK) {
+        const float v = stage[i];
+        if (v != 0.f) o[i] += v;
     }
 }
 
-// one thread per leaf, every leaf: the bucket sums are the leaf's gradient and
-// feed RMSProp directly (untouched leaves: g = 0, so only v decays)
+// The same reduction feeding RMSProp for every leaf (untouched leaves have
+// g = 0: their square averages decay, their values stay).
 template <int DEG>
-__global__ void bwd_rmsprop_kernel(int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ count,
-                                   const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
-                                   float* __restrict__ sigma, float* __restrict__ sh, int stride,
-                                   float* __restrict__ vs, float* __restrict__ vh, dot_rmsprop_params p) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L; l += (int64_t)gridDim.x * blockDim.x) {
-        float gs, acc[3 * K];
+__global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const uint32_t* __restrict__ offset,
+                                                                const uint32_t* __restrict__ count,
+                                                                const uint32_t* __restrict__ cursor,
+                                                                const float* __restrict__ rows,
+                                                                float* __restrict__ sigma, float* __restrict__ sh,
+                                                                int stride, float* __restrict__ vs,
+                                                                float* __restrict__ vh, dot_rmsprop_params p) {
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
+    __shared__ float stage[RED_BLOCK * NV];
+    const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
+    const int64_t l = l0 + threadIdx.x;
+    float gs = 0.f, acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.f;
+    if (l < L) {
         bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc);
         float th = sigma[l], v = vs[l];
         rmsprop_update(th, v, gs, p.lr_sigma, p.alpha, p.eps);
         sigma[l] = th;
         vs[l] = v;
-        float* o = sh + l * stride;
-        float* w = vh + l * (3 * K);
+    }
 #pragma unroll
-        for (int j = 0; j < 3 * K; ++j) {
-            float t = o[j], u = w[j];
-            rmsprop_update(t, u, acc[j], p.lr_sh, p.alpha, p.eps);
-            o[j] = t;
-            w[j] = u;
-        }
+    for (int j = 0; j < NV; ++j) stage[threadIdx.x * NV + j] = acc[j];
+    __syncthreads();
+    const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
+    for (int i = threadIdx.x; i < nl * NV; i += RED_BLOCK) {
+        const int64_t r = l0 + i / NV;
+        const int c = i % NV;
+        float* t = sh + r * stride + c;
+        float th = *t, v = vh[l0 * NV + i];
+        rmsprop_update(th, v, stage[i], p.lr_sh, p.alpha, p.eps);
+        *t = th;
+        vh[l0 * NV + i] = v;
     }
 }
 
@@ -441,8 +483,8 @@ template <int DEG>
 static void launch_bwd_rmsprop(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* count,
                                const uint32_t* cursor, const float* rows, hipStream_t s) {
     const int64_t L = t.n_leaves;
-    unsigned rg = (unsigned)std::min<int64_t>((L + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(bwd_rmsprop_kernel<DEG>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows,
+    const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
+    hipLaunchKernelGGL(bwd_rmsprop_kernel<DEG>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows,
                        static_cast<float*>(t.sigma), static_cast<float*>(t.sh), t.sh_stride, a.v_sigma, a.v_sh,
                        *a.rms);
 }
@@ -500,7 +542,7 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
         default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
     }
-    unsigned rg = (unsigned)std::min<int64_t>((L + 255) / 256, 1 << 20);
+    const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
     if (fused) {
         switch (t.degree) {
             case 0: launch_bwd_rmsprop<0>(t, a, offset, count, cursor, rows, s); break;
@@ -509,10 +551,10 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
             default: launch_bwd_rmsprop<3>(t, a, offset, count, cursor, rows, s); break;
         }
     } else switch (t.degree) {
-        case 0: hipLaunchKernelGGL(bwd_reduce_kernel<0>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
-        case 1: hipLaunchKernelGGL(bwd_reduce_kernel<1>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
-        case 2: hipLaunchKernelGGL(bwd_reduce_kernel<2>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
-        default: hipLaunchKernelGGL(bwd_reduce_kernel<3>, dim3(rg), dim3(256), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 0: hipLaunchKernelGGL(bwd_reduce_kernel<0>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 1: hipLaunchKernelGGL(bwd_reduce_kernel<1>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 2: hipLaunchKernelGGL(bwd_reduce_kernel<2>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        default: hipLaunchKernelGGL(bwd_reduce_kernel<3>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
     }
     e = hipGetLastError();
     t.alloc.put(rows);
