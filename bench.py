@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--no-config3", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--alg1-epochs", type=int, default=4, help="epochs of the end-to-end training loop (0: skip)")
+    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "config3"],
+                    help="run one secondary measurement alone and print its JSON (for profiling it)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
     args = ap.parse_args()
@@ -94,9 +96,19 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
+    if args.only in ("train", "config3"):
+        fn = {"train": train_step, "config3": config3_precision}[args.only]
+        print(json.dumps(fn(torch, core, synth, args)), flush=True)
+        return
     scene = synth.config2_scene()
     cams = synth.config2_cameras()
     log(f"config2 scene: {scene.n_leaves} leaves, {scene.n_internal} internal ({time.time() - t0:.1f}s)")
+    if args.only:
+        fn = {"alg1": lambda: alg1_loop(torch, core, synth, scene, args),
+              "refine": lambda: refine_pass(torch, core, synth, scene),
+              "serve": lambda: serving(torch, core, synth, scene, args)}[args.only]
+        print(json.dumps(fn()), flush=True)
+        return
     tree = core.Octree.from_scene(scene, "f32")
     rays = core.Rays.cameras(cams)
     n_rays = rays.n_rays
@@ -139,6 +151,12 @@ def main():
     kt = time_kernel(step, max(5, args.steps // 2), torch)
     achieved = leaf_bytes / kt / 1e9
     other = stats["child_reads"] * 4 + n_rays * 12 + stats["sh_fetches"] * 4
+    # compulsory bytes: every distinct leaf the frame composites, fetched once
+    # (leaves with a positive signal received a positive weight, hence an SH fetch)
+    signal.zero_()
+    step()
+    n_touched = int((signal > 0).sum().item())
+    compulsory = n_touched * (4 + 3 * K * 4)
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -148,7 +166,9 @@ def main():
                 "per_unit": "4 B sigma per segment + 192 B SH per segment with sigma*delta > 0",
                 "units_per_launch": {"segments": stats["segments"], "sh_fetches": stats["sh_fetches"]},
                 "other_bytes_per_launch": {"child_reads": stats["child_reads"] * 4, "rgb": n_rays * 12,
-                                           "signal_reads": stats["sh_fetches"] * 4, "total": int(other)}}
+                                           "signal_reads": stats["sh_fetches"] * 4, "total": int(other)},
+                "compulsory_bytes_per_launch": compulsory, "distinct_leaves_composited": n_touched,
+                "compulsory_GBps": round(compulsory / kt / 1e9, 1)}
     log(f"render kernel {kt * 1e3:.3f} ms; leaf-fetch {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak);"
         f" segments/ray {stats['segments'] / n_rays:.2f}")
 
@@ -392,9 +412,18 @@ def _cpu_result(T, cams):
         total += time.perf_counter() - t1
         n += o.shape[0]
     v = n / total / 1e6
-    log(f"cpu oracle: {n} rays in {total:.2f}s = {v:.3f} Mrays/s on {O.num_threads()} threads")
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    log(f"cpu oracle: {n} rays in {total:.2f}s = {v:.3f} Mrays/s on {O.num_threads()} threads ({model})")
     return {"value": round(v, 4), "unit": "Mrays/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"all {n} rays of the 8 800x800 views (render calls only, FP64, OpenMP)"}
+            "sample": f"all {n} rays of the 8 800x800 views (render calls only, FP64, OpenMP, "
+                      f"{O.num_threads()} threads of {os.cpu_count()} CPUs, {model})"}
 
 
 if __name__ == "__main__":
