@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--no-config3", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--alg1-epochs", type=int, default=4, help="epochs of the end-to-end training loop (0: skip)")
-    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "config3"],
+    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "config3", "palette"],
                     help="run one secondary measurement alone and print its JSON (for profiling it)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
@@ -105,6 +105,7 @@ def main():
     log(f"config2 scene: {scene.n_leaves} leaves, {scene.n_internal} internal ({time.time() - t0:.1f}s)")
     if args.only:
         fn = {"alg1": lambda: alg1_loop(torch, core, synth, scene, args),
+              "palette": lambda: palette_render(torch, core, scene, core.Rays.cameras(cams), None, args),
               "refine": lambda: refine_pass(torch, core, synth, scene),
               "serve": lambda: serving(torch, core, synth, scene, args)}[args.only]
         print(json.dumps(fn()), flush=True)
@@ -224,6 +225,7 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
             res[f"render_{storage}_speedup_vs_f32"] = round(mr / base, 3)
             tree.close()
         log(f"render {storage}: {kt * 1e3:.3f} ms, {mr:.1f} Mrays/s")
+    res.update(palette_render(torch, core, scene, rays, base, args))
     res.update(train_step(torch, core, synth, args))
     if args.alg1_epochs > 0:
         res.update(alg1_loop(torch, core, synth, scene, args))
@@ -232,6 +234,41 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
     if not args.no_config3:
         res.update(config3_precision(torch, core, synth, args))
     return res
+
+
+def palette_render(torch, core, scene, rays, base_mrays, args):
+    """Config 2 compressed by the median-cut palette (2^16 FP16 rows, FP16 sigma,
+    uint16 index per leaf): build time, render Mrays/s with the fused signal,
+    and the image difference against the FP32 tree."""
+    import ctypes as C
+    from paper_2307_15333_amd import _lib as L
+    ref_tree = core.Octree.from_scene(scene, "f32")
+    ref = ref_tree.render(rays)
+    ref_tree.close()
+    tree = core.Octree.from_scene(scene, "f32")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tree.quantize_sh(16)
+    torch.cuda.synchronize()
+    t_q = time.perf_counter() - t
+    sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
+    rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device="cuda")
+    op = core.render_opts()
+
+    def fn():
+        L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op), C.c_void_p(rgb.data_ptr()), None,
+                                    C.c_void_p(sig.data_ptr()), core._stream()))
+
+    kt = time_kernel(fn, max(5, args.steps // 2), torch)
+    mr = rays.n_rays / kt / 1e6
+    mse = float(((rgb - ref) ** 2).mean())
+    psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+    tree.close()
+    speed = mr / base_mrays if base_mrays else None
+    log(f"render pal16 (median cut, 2^16 rows): quantize {t_q * 1e3:.0f} ms, {kt * 1e3:.3f} ms, {mr:.1f} Mrays/s "
+        f"(x{speed if speed is None else round(speed, 2)} FP32), PSNR vs FP32 tree {psnr:.1f} dB")
+    return {"render_pal16_mrays": round(mr, 1), "render_pal16_speedup_vs_f32": None if speed is None else round(speed, 3),
+            "pal16_quantize_ms": round(t_q * 1e3, 1), "pal16_psnr_vs_f32_db": round(psnr, 2)}
 
 
 def refine_pass(torch, core, synth, scene):

@@ -51,8 +51,10 @@ enum {
     DOT_EUNSUPPORTED = -4  /* valid request this build does not implement */
 };
 
-/* leaf storage precision of the sigma and SH planes; arithmetic is FP32 */
-enum { DOT_F32 = 0, DOT_F16 = 1, DOT_BF16 = 2 };
+/* leaf storage precision of the sigma and SH planes; arithmetic is FP32.
+ * DOT_PAL16 (made only by dot_quantize_sh): FP16 sigma, a uint16 palette index
+ * per leaf and an FP16 palette of SH rows. */
+enum { DOT_F32 = 0, DOT_F16 = 1, DOT_BF16 = 2, DOT_PAL16 = 3 };
 
 /* how rays are given */
 enum {
@@ -129,6 +131,9 @@ typedef struct {
     void *sh;                     /* device [n_leaves][sh_stride]; row = [3][K] then padding */
     void *leaf_depth;             /* device uint8 [n_leaves] */
     float bbox_min[3], bbox_size;
+    void *palette;                /* DOT_PAL16: device FP16 [2^palette_bits][sh_stride]; else NULL.
+                                     sh is then the uint16 index plane [n_leaves] */
+    int32_t palette_bits, reserved;
 } dot_tree_info_t;
 
 /*
@@ -336,6 +341,25 @@ int dot_pixel_batch(const int64_t *ray_ids, int64_t n_rays, int32_t width, int32
  */
 int dot_mse_loss(const float *pred, const float *target, const int64_t *target_idx, int64_t n_rays,
                  float *grad_rgb_out, double *loss_out, void *stream);
+
+/*
+ * dot_quantize_sh -- compress the tree's SH coefficients into a palette (the
+ *  compressed octrees of Sec. 4.1, quantised with Heckbert's median cut).
+ *  Each leaf's SH row (3K values as stored) is a point; `bits` rounds each cut
+ *  every box at the median of its widest dimension (largest max - min, ties:
+ *  lowest dimension; members ordered by value then leaf index, -0.0 = +0.0;
+ *  the lower n/2 go to box 2b, the rest to 2b + 1), giving 2^bits boxes (some
+ *  empty when there are few leaves).  A palette row is the FP64 mean of its
+ *  box rounded once to FP16 (zero for an empty box); each leaf keeps the
+ *  uint16 index of its box.  The tree becomes DOT_PAL16 in place (sigma
+ *  rounded to FP16).  Rendering, serving, the signal calls and dot_export
+ *  accept it; dot_render_backward, the optimiser steps and dot_refine return
+ *  DOT_EUNSUPPORTED.  Needs scratch of about 2 N (3K + 4) * 4 bytes from the
+ *  tree's allocator; synchronises `stream`.
+ *  Errors: DOT_EINVAL on bits outside 1..16 or an already compressed tree;
+ *  DOT_ENOMEM when the scratch cannot be allocated.
+ */
+int dot_quantize_sh(dot_tree_t tree, int32_t bits, void *stream);
 
 /*
  * dot_export -- copy the tree back to host memory in canonical form:

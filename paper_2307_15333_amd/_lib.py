@@ -12,13 +12,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdot.so")
 
 DOT_OK, DOT_EINVAL, DOT_ENOMEM, DOT_EHIP, DOT_EUNSUPPORTED = 0, -1, -2, -3, -4
-DOT_F32, DOT_F16, DOT_BF16 = 0, 1, 2
+DOT_F32, DOT_F16, DOT_BF16, DOT_PAL16 = 0, 1, 2, 3
 DOT_RAYS_CAMERAS, DOT_RAYS_PIXELS, DOT_RAYS_EXPLICIT = 0, 1, 2
 DOT_SIGNAL_MAX, DOT_SIGNAL_SUM = 0, 1
 DOT_MAX_DEPTH = 16
 
 STORAGE = {"f32": DOT_F32, "f16": DOT_F16, "bf16": DOT_BF16}
-STORAGE_NAME = {v: k for k, v in STORAGE.items()}
+STORAGE_NAME = {**{v: k for k, v in STORAGE.items()}, DOT_PAL16: "pal16"}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -55,7 +55,8 @@ class dot_tree_info_t(C.Structure):
     _fields_ = [("n_internal", C.c_int64), ("n_leaves", C.c_int64), ("sh_degree", C.c_int32),
                 ("storage", C.c_int32), ("max_depth", C.c_int32), ("sh_stride", C.c_int32),
                 ("child", C.c_void_p), ("sigma", C.c_void_p), ("sh", C.c_void_p),
-                ("leaf_depth", C.c_void_p), ("bbox_min", C.c_float * 3), ("bbox_size", C.c_float)]
+                ("leaf_depth", C.c_void_p), ("bbox_min", C.c_float * 3), ("bbox_size", C.c_float),
+                ("palette", C.c_void_p), ("palette_bits", C.c_int32), ("reserved", C.c_int32)]
 
 
 class dot_refine_params(C.Structure):
@@ -111,6 +112,7 @@ SIGNATURES = {
                                   C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dot_mse_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
+    "dot_quantize_sh": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "dot_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_render_stats": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                    C.POINTER(C.c_int64), C.c_void_p]),

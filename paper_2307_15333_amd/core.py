@@ -259,6 +259,20 @@ class Octree:
         L.check(self.lib.dot_sigma_signal(self.handle, _ptr(out), _stream()))
         return out
 
+    def quantize_sh(self, bits=16):
+        """Median-cut palette compression of the SH rows (in place; storage becomes 'pal16')."""
+        L.check(self.lib.dot_quantize_sh(self.handle, int(bits), _stream()))
+
+    def palette_views(self):
+        """(index [L] int16 view of the uint16 indices, palette [2^bits, 3, K] FP16) of a 'pal16' tree."""
+        i = self.info()
+        if int(i.storage) != L.DOT_PAL16:
+            raise ValueError("not a palette-compressed tree")
+        Ln, P, st = int(i.n_leaves), 1 << int(i.palette_bits), int(i.sh_stride)
+        idx = self.alloc.tensor(i.sh, Ln * 2).view(torch.int16)
+        pal = self.alloc.tensor(i.palette, P * st * 2).view(torch.float16).view(P, st)[:, :3 * self.K]
+        return idx, pal.unflatten(1, (3, self.K))
+
     def export(self):
         i = self.info()
         I, Ln = int(i.n_internal), int(i.n_leaves)

@@ -171,10 +171,34 @@ static void release(dot_tree* t) {
     t->alloc.put(t->sigma);
     t->alloc.put(t->sh);
     t->alloc.put(t->leaf_depth);
+    t->alloc.put(t->palette);
     t->child = nullptr;
     t->sigma = nullptr;
     t->sh = nullptr;
     t->leaf_depth = nullptr;
+    t->palette = nullptr;
+}
+
+// SH rows of a palette tree decoded to host FP32 [rows][nv], through staging
+static int download_palette_sh(const dot_tree& t, float* host, hipStream_t s) {
+    const int nv = 3 * (t.degree + 1) * (t.degree + 1);
+    const int64_t rows = t.n_leaves;
+    const int64_t chunk = std::min<int64_t>(rows, std::max<int64_t>(1, (64ll << 20) / ((int64_t)nv * 4)));
+    float* stage = static_cast<float*>(t.alloc.get((size_t)chunk * nv * 4));
+    if (!stage) return fail(DOT_ENOMEM, "dot_export: staging allocation failed");
+    int rc = DOT_OK;
+    for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+        const int64_t n = std::min(chunk, rows - r0);
+        hipError_t e = launch_decode_palette(t, stage, n, r0, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(host + r0 * nv, stage, (size_t)n * nv * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "dot_export: download");
+            break;
+        }
+    }
+    t.alloc.put(stage);
+    return rc;
 }
 
 static int make_batch(const dot_rays* r, RayBatch& rb, const char* who) {
@@ -319,6 +343,9 @@ int dot_tree_info(dot_tree_t t, dot_tree_info_t* out) {
     out->leaf_depth = t->leaf_depth;
     for (int a = 0; a < 3; ++a) out->bbox_min[a] = t->bmin[a];
     out->bbox_size = t->size;
+    out->palette = t->palette;
+    out->palette_bits = t->palette_bits;
+    out->reserved = 0;
     return DOT_OK;
 }
 
@@ -362,6 +389,8 @@ int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opt
                         const int32_t* nseg, const float* grad_rgb, float* grad_sigma, float* grad_sh,
                         void* stream) {
     if (!t) return fail(DOT_EINVAL, "dot_render_backward: tree is NULL");
+    if (t->storage == DOT_PAL16)
+        return fail(DOT_EUNSUPPORTED, "dot_render_backward: a palette-compressed tree is not differentiable");
     RayBatch rb;
     int rc = make_batch(rays, rb, "dot_render_backward");
     if (rc) return rc;
@@ -513,8 +542,14 @@ int dot_export(dot_tree_t t, int32_t* child, float* sigma, float* sh, uint8_t* l
     if (e != hipSuccess) return hip_fail(e, "dot_export");
     int nv = 3 * (t->degree + 1) * (t->degree + 1);
     int rc = DOT_OK;
-    if (sigma) rc = download_plane(t->alloc, t->storage, t->sigma, sigma, t->n_leaves, 1, 1, s);
-    if (!rc && sh) rc = download_plane(t->alloc, t->storage, t->sh, sh, t->n_leaves, nv, t->sh_stride, s);
+    const int sst = t->storage == DOT_PAL16 ? DOT_F16 : t->storage;
+    if (sigma) rc = download_plane(t->alloc, sst, t->sigma, sigma, t->n_leaves, 1, 1, s);
+    if (!rc && sh) {
+        if (t->storage == DOT_PAL16)
+            rc = download_palette_sh(*t, sh, s);
+        else
+            rc = download_plane(t->alloc, t->storage, t->sh, sh, t->n_leaves, nv, t->sh_stride, s);
+    }
     return rc;
 }
 
@@ -522,12 +557,21 @@ int dot_refine(dot_tree_t t, const float* signal, const dot_refine_params* p, do
                void* stream) {
     if (!t || !p) return fail(DOT_EINVAL, "dot_refine: NULL argument");
     if (!signal) return fail(DOT_EINVAL, "dot_refine: signal is NULL");
+    if (t->storage == DOT_PAL16)
+        return fail(DOT_EUNSUPPORTED, "dot_refine: a palette-compressed tree cannot be refined");
     if (!(p->sample_frac >= 0.f && p->sample_frac <= 1.f))
         return fail(DOT_EINVAL, "dot_refine: sample_frac must be in [0, 1]");
     if (p->max_depth < 0 || p->max_depth > DOT_MAX_DEPTH)
         return fail(DOT_EINVAL, "dot_refine: max_depth must be in 0..DOT_MAX_DEPTH");
     if (!std::isfinite(p->prune_tau)) return fail(DOT_EINVAL, "dot_refine: prune_tau must be finite");
     return refine_tree(*t, signal, *p, stats, static_cast<hipStream_t>(stream));
+}
+
+int dot_quantize_sh(dot_tree_t t, int32_t bits, void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_quantize_sh: tree is NULL");
+    if (bits < 1 || bits > 16) return fail(DOT_EINVAL, "dot_quantize_sh: bits must be in 1..16");
+    if (t->storage == DOT_PAL16) return fail(DOT_EINVAL, "dot_quantize_sh: the tree is already palette-compressed");
+    return quantize_sh(*t, bits, static_cast<hipStream_t>(stream));
 }
 
 size_t dot_render_jobs_workspace(int32_t n_jobs) { return jobs_workspace_bytes(n_jobs < 0 ? 0 : n_jobs); }

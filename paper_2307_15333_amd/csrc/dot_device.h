@@ -41,7 +41,7 @@ __device__ __forceinline__ float load_sigma(const void* __restrict__ p, int64_t 
         return static_cast<const float*>(p)[i];
     } else {
         uint32_t h = static_cast<const uint16_t*>(p)[i];
-        return DT == DOT_F16 ? f16_to_f32(h) : bf16_to_f32(h);
+        return (DT == DOT_F16 || DT == DOT_PAL16) ? f16_to_f32(h) : bf16_to_f32(h);
     }
 }
 
@@ -350,6 +350,10 @@ struct FwdSeg {
                 if (4 * c + 2 < NW) packed[4 * c + 2] = v.z;
                 if (4 * c + 3 < NW) packed[4 * c + 3] = v.w;
             }
+        } else if constexpr (DT == DOT_PAL16) {
+            // the row lives in the palette: one dependent load after the index
+            const uint32_t pi = static_cast<const uint16_t*>(tv.sh)[leaf];
+            load_sh_row<DOT_F16, 3 * K>(tv.palette, pi, row);
         } else {
             load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
         }

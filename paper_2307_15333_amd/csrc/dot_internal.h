@@ -34,7 +34,8 @@ struct TreeView {
     float bmin[3];
     float scale;      // lattice cells per world unit = LAT_N / bbox_size
     int max_steps;    // safety bound on traversal steps per ray
-    int sh_stride;
+    int sh_stride;    // elements per SH row (of the palette for DOT_PAL16)
+    const void* palette;   // DOT_PAL16: FP16 palette rows; `sh` holds uint16 indices
 };
 
 struct Alloc {
@@ -56,6 +57,8 @@ struct dot_tree {
     void* sigma = nullptr;        // device
     void* sh = nullptr;           // device
     uint8_t* leaf_depth = nullptr;  // device
+    void* palette = nullptr;        // device, DOT_PAL16 only
+    int32_t palette_bits = 0;
 
     dot::TreeView view() const {
         dot::TreeView v;
@@ -69,6 +72,7 @@ struct dot_tree {
         int md = max_depth < 1 ? 1 : max_depth;
         v.max_steps = 3 * (1 << md) + 64;
         v.sh_stride = sh_stride;
+        v.palette = palette;
         return v;
     }
 };
@@ -152,6 +156,8 @@ hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t 
                               int32_t* pix_out, int64_t* id_out, void* ws, hipStream_t s);
 size_t jobs_workspace_bytes(int n_jobs);
 int launch_render_jobs(const dot_render_job* jobs, int n_jobs, void* ws, size_t ws_bytes, hipStream_t s);
+int quantize_sh(dot_tree& t, int bits, hipStream_t s);
+hipError_t launch_decode_palette(const dot_tree& t, float* dst, int64_t rows, int64_t row0, hipStream_t s);
 int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st,
                 hipStream_t s);
 

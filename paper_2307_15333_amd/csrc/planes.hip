@@ -174,7 +174,7 @@ hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s) {
     dim3 g(grid_for(t.n_leaves));
     if (t.storage == DOT_F32)
         hipLaunchKernelGGL(sigma_signal_kernel<DOT_F32>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);
-    else if (t.storage == DOT_F16)
+    else if (t.storage == DOT_F16 || t.storage == DOT_PAL16)
         hipLaunchKernelGGL(sigma_signal_kernel<DOT_F16>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);
     else
         hipLaunchKernelGGL(sigma_signal_kernel<DOT_BF16>, g, dim3(256), 0, s, t.sigma, t.n_leaves, out);

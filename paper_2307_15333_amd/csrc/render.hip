@@ -414,6 +414,7 @@ hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArg
     switch (t.storage) {
         case DOT_F32: return fwd_dispatch_deg<DOT_F32>(t.degree, tv, rb, a, grid, s);
         case DOT_F16: return fwd_dispatch_deg<DOT_F16>(t.degree, tv, rb, a, grid, s);
+        case DOT_PAL16: return fwd_dispatch_deg<DOT_PAL16>(t.degree, tv, rb, a, grid, s);
         default: return fwd_dispatch_deg<DOT_BF16>(t.degree, tv, rb, a, grid, s);
     }
 }

@@ -81,6 +81,7 @@ __global__ __launch_bounds__(BLOCK) void render_jobs_kernel(const JobDev* __rest
         switch (j.storage) {
             case DOT_F32: tile_dt<DOT_F32>(j, lt, lane, &stack_lds[tid]); break;
             case DOT_F16: tile_dt<DOT_F16>(j, lt, lane, &stack_lds[tid]); break;
+            case DOT_PAL16: tile_dt<DOT_PAL16>(j, lt, lane, &stack_lds[tid]); break;
             default: tile_dt<DOT_BF16>(j, lt, lane, &stack_lds[tid]); break;
         }
     }

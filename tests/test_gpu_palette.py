@@ -1,0 +1,166 @@
+"""Median-cut palette compression on the GPU against the palette oracle.
+
+Indices are integer work: bit-exact.  Palette rows are FP64 means rounded once
+to FP16 on both sides (summation order differs, so 1 FP16 ulp is allowed and
+counted).  Rendering a compressed tree is compared with the FP64 oracle
+rendering the decoded tree (tolerance 1e-5, as for every FP32-arithmetic
+render).  At config-2 size the median-cut invariants are checked instead.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import palette as P
+from paper_2307_15333_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _core():
+    from paper_2307_15333_amd import core
+    return core
+
+
+def _f16_ulps(a, b):
+    ai = np.asarray(a, np.float32).astype(np.float16).view(np.int16).astype(np.int64)
+    bi = np.asarray(b, np.float32).astype(np.float16).view(np.int16).astype(np.int64)
+    return np.abs(ai - bi)
+
+
+def _quantize_both(scene, bits, storage="f32"):
+    core = _core()
+    tree = core.Octree.from_scene(scene, storage)
+    stored = tree.export()          # the values as stored, decoded to FP32
+    tree.quantize_sh(bits)
+    idx_d, pal_d = tree.palette_views()
+    idx = idx_d.cpu().numpy().view(np.uint16).astype(np.int64)
+    pal = pal_d.float().cpu().numpy()
+    s16, oidx, opal, dec = P.quantize_tree(stored["sigma"].astype(np.float64), stored["sh"].astype(np.float64), bits)
+    return tree, stored, idx, pal, (s16, oidx, opal, dec)
+
+
+@pytest.mark.parametrize("storage,bits,degree", [("f32", 6, 2), ("f32", 10, 3), ("f16", 8, 1), ("bf16", 5, 0)])
+def test_palette_matches_oracle(storage, bits, degree):
+    s = synth.random_tree_scene(5, degree, seed=50 + bits, p_split=0.5)
+    tree, stored, idx, pal, (s16, oidx, opal, dec) = _quantize_both(s, bits, storage)
+    assert tree.storage == "pal16"
+    np.testing.assert_array_equal(idx, oidx)
+    u = _f16_ulps(pal, opal)
+    print(f"{storage} bits {bits} deg {degree}: {s.n_leaves} leaves, palette values off by 1 ulp: {int((u > 0).sum())}")
+    assert u.max() <= 1
+    ex = tree.export()
+    np.testing.assert_array_equal(ex["sigma"], s16.astype(np.float32))
+    np.testing.assert_array_equal(ex["sh"], pal[idx])
+    tree.close()
+
+
+def test_palette_with_more_boxes_than_leaves():
+    s = synth.random_tree_scene(2, 1, seed=3, p_split=0.6)
+    tree, stored, idx, pal, (s16, oidx, opal, dec) = _quantize_both(s, 12)
+    assert s.n_leaves < 4096
+    np.testing.assert_array_equal(idx, oidx)
+    assert np.all(pal[np.setdiff1d(np.arange(4096), idx)] == 0.0)
+    tree.close()
+
+
+def test_palette_render_matches_oracle():
+    core = _core()
+    s = synth.config1_scene()
+    tree, stored, idx, pal, _ = _quantize_both(s, 9)
+    cams = synth.config1_camera()
+    rays = core.Rays.cameras(cams)
+    sig = torch.zeros(tree.n_leaves, device="cuda")
+    rgb = tree.render(rays, signal=sig).cpu().numpy().astype(np.float64)
+    ex = tree.export()
+    T = O.OracleTree(s.child, ex["sigma"].astype(np.float64), ex["sh"].astype(np.float64), s.degree, s.bbox_min,
+                     s.bbox_size)
+    o, d = O.camera_rays(cams)
+    ref = O.render(T, o.reshape(-1, 3), d.reshape(-1, 3), signal=True)
+    err = np.minimum(np.abs(rgb - ref["rgb"]).max(1), np.minimum(np.abs(rgb - ref["rgb_early"]).max(1),
+                                                               np.abs(rgb - ref["rgb_late"]).max(1)))
+    print(f"palette render max err {err.max():.2e}")
+    assert err.max() <= TOL
+    g = sig.cpu().numpy()
+    assert np.all(g >= ref["sig_lo"] - TOL) and np.all(g <= ref["sig_hi"] + TOL)
+    # the density signal decodes FP16
+    np.testing.assert_array_equal(tree.sigma_signal().cpu().numpy(), np.maximum(ex["sigma"], 0.0))
+    tree.close()
+
+
+def test_palette_tree_in_the_serving_kernel():
+    from paper_2307_15333_amd import serve
+    core = _core()
+    s = synth.config1_scene()
+    tree = core.Octree.from_scene(s)
+    tree.quantize_sh(8)
+    cam = synth.config1_camera()
+    ref = tree.render(core.Rays.cameras(cam)).cpu().numpy().reshape(64, 64, 3)
+    srv = serve.Server([tree], out_budget_bytes=1 << 26)
+    req = serve.Request(rid=0, tree=0, cam=cam[0], width=64, height=64, arrival=0.0)
+    got = {}
+    srv.run([req], keep_outputs=True, on_complete=lambda r: got.setdefault("img", r.out.cpu().numpy()))
+    np.testing.assert_array_equal(got["img"], ref)
+    tree.close()
+
+
+def test_palette_rejections():
+    from paper_2307_15333_amd import _lib as L
+    core = _core()
+    s = synth.random_tree_scene(3, 1, seed=4)
+    tree = core.Octree.from_scene(s)
+    for bits in (0, 17):
+        with pytest.raises(L.DotError) as e:
+            tree.quantize_sh(bits)
+        assert e.value.code == L.DOT_EINVAL
+    tree.quantize_sh(4)
+    with pytest.raises(L.DotError) as e:
+        tree.quantize_sh(4)
+    assert e.value.code == L.DOT_EINVAL
+    sig = torch.zeros(tree.n_leaves, device="cuda")
+    with pytest.raises(L.DotError) as e:
+        tree.refine(sig)
+    assert e.value.code == L.DOT_EUNSUPPORTED
+    rays = core.Rays.cameras(synth.config1_camera())
+    rgb, ns = tree.render(rays, nseg=True)
+    z = torch.zeros(tree.n_leaves, device="cuda")
+    with pytest.raises(L.DotError) as e:
+        tree.backward(rays, rgb, ns, torch.zeros_like(rgb), z, torch.zeros((tree.n_leaves, 3, tree.K), device="cuda"))
+    assert e.value.code == L.DOT_EUNSUPPORTED
+    tree.close()
+
+
+def test_palette_config2_full_size_invariants():
+    """3.54M leaves, 2^16 boxes: box sizes are the repeated halvings of N, and
+    sampled palette rows equal the FP16-rounded mean of their members."""
+    core = _core()
+    s = synth.config2_scene()
+    tree = core.Octree.from_scene(s)
+    torch.cuda.synchronize()
+    tree.quantize_sh(16)
+    idx_d, pal_d = tree.palette_views()
+    idx = idx_d.cpu().numpy().view(np.uint16).astype(np.int64)
+    pal = pal_d.float().cpu().numpy()
+    N = s.n_leaves
+    cnt = np.bincount(idx, minlength=1 << 16)
+    assert set(np.unique(cnt).tolist()) <= {N >> 16, (N + (1 << 16) - 1) >> 16}
+    rng = np.random.default_rng(0)
+    boxes = rng.choice(1 << 16, 64, replace=False)
+    sh = s.sh32.reshape(N, -1).astype(np.float64)
+    order = np.argsort(idx, kind="stable")
+    starts = np.searchsorted(idx[order], np.arange((1 << 16) + 1))
+    for b in boxes:
+        m = order[starts[b]:starts[b + 1]]
+        want = O.round_storage(sh[m].mean(0), "f16")
+        assert _f16_ulps(pal[b].reshape(-1), want).max() <= 1
+    # the 2^16 box means fit the rows better than the one global mean (median
+    # cut refines the one-box partition; the seeded SH rows are independent
+    # draws, so most of the spread of the higher coefficients remains)
+    ex = tree.export()
+    sse = float(((ex["sh"].reshape(N, -1) - sh) ** 2).sum())
+    sse1 = float(((sh - sh.mean(0)) ** 2).sum())
+    print(f"config-2 palette: SSE {sse:.4e} vs one-box {sse1:.4e}, mean |err| "
+          f"{np.abs(ex['sh'].reshape(N, -1) - sh).mean():.3e}")
+    assert sse < sse1
+    tree.close()
