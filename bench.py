@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--no-config3", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--alg1-epochs", type=int, default=4, help="epochs of the end-to-end training loop (0: skip)")
-    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "config3", "palette"],
+    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "config3", "palette", "ablation"],
                     help="run one secondary measurement alone and print its JSON (for profiling it)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
@@ -106,6 +106,7 @@ def main():
     if args.only:
         fn = {"alg1": lambda: alg1_loop(torch, core, synth, scene, args),
               "palette": lambda: palette_render(torch, core, scene, core.Rays.cameras(cams), None, args),
+              "ablation": lambda: ablation(torch, core, synth, scene, cams, args),
               "refine": lambda: refine_pass(torch, core, synth, scene),
               "serve": lambda: serving(torch, core, synth, scene, args)}[args.only]
         print(json.dumps(fn()), flush=True)
@@ -269,6 +270,63 @@ def palette_render(torch, core, scene, rays, base_mrays, args):
         f"(x{speed if speed is None else round(speed, 2)} FP32), PSNR vs FP32 tree {psnr:.1f} dB")
     return {"render_pal16_mrays": round(mr, 1), "render_pal16_speedup_vs_f32": None if speed is None else round(speed, 3),
             "pal16_quantize_ms": round(t_q * 1e3, 1), "pal16_psnr_vs_f32_db": round(psnr, 2)}
+
+
+def ablation(torch, core, synth, scene, cams, args):
+    """Synthetic stand-in for the paper's signal and fusion ablations (Tab. 3,
+    App. C.1) on the config-2 tree: targets are the generator tree's renders
+    from 100 random 400x400 views (16M rays per epoch); training starts from
+    SH + N(0, 0.1^2); 4 epochs of 2^20-ray batches with RMSProp and a
+    refinement after epochs 2 and 4.  Prune-only runs (gamma = 0) compare the
+    max and sum of ray weights (Q) with the density (Pr_sigma, its tau chosen
+    to prune about as many leaves as Q-max does first); fusion against
+    re-initialised new leaves uses pruning and sampling (gamma = 1 %).  For each
+    run: leaves, FP32 render Mrays/s of the 8 benchmark cameras, and PSNR of
+    those images against the generator tree."""
+    from paper_2307_15333_amd import train as TR
+    views = synth.random_sphere_cameras(100, 4.0, 400, 400, seed=31)
+    gt = core.Octree.from_scene(scene)
+    target = gt.render(core.Rays.cameras(views))
+    bench_rays = core.Rays.cameras(cams)
+    ref = gt.render(bench_rays)
+    gt.close()
+    start = synth.perturb_sh(scene, 0.1, seed=32)
+
+    def run(name, **kw):
+        tree = core.Octree.from_scene(start)
+        cfg = TR.TrainConfig(interval=2, batch_rays=1 << 20, max_depth=10, seed=33, **kw)
+        tr = TR.Trainer(tree, views, target, cfg)
+        hist = tr.train(epochs=4)
+        rgb = tree.render(bench_rays)
+        mse = float(((rgb - ref) ** 2).mean())
+        sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
+        kt = time_kernel(lambda: tree.render(bench_rays, signal=sig), 5, torch)
+        out = {"leaves": tree.n_leaves, "leaves_after_first_refine": hist[1]["leaves"],
+               "render_mrays": round(bench_rays.n_rays / kt / 1e6, 1),
+               "psnr_db": round(float(10 * np.log10(1.0 / mse)), 2) if mse > 0 else None,
+               "loss_first_last": [float(hist[0]["losses"].mean()), float(hist[-1]["losses"].mean())]}
+        tree.close()
+        log(f"ablation {name}: {out}")
+        return out
+
+    res = {"ablation_start_leaves": scene.n_leaves}
+    res["prune_q_max"] = run("prune Q max (tau 1e-3)", signal="max", tau=1e-3, gamma=0.0)
+    res["prune_q_sum"] = run("prune Q sum (tau 1)", signal="sum", tau=1.0, gamma=0.0)
+    # Pr_sigma: the density threshold that prunes about as many leaves as Q-max's first pruning
+    target_removed = scene.n_leaves - res["prune_q_max"]["leaves_after_first_refine"]
+    tau_s, best = None, None
+    for t in (0.1, 1.0, 3.0, 10.0, 20.0, 30.0, 40.0, 50.0):
+        tree = core.Octree.from_scene(start)
+        st = tree.refine(tree.sigma_signal(), prune_tau=t, sample_frac=0.0, max_depth=10)
+        tree.close()
+        gap = abs((st["leaves_before"] - st["leaves_after"]) - target_removed)
+        if best is None or gap < best:
+            tau_s, best = t, gap
+    res["prune_sigma"] = run(f"prune sigma (tau {tau_s})", signal="sigma", tau=tau_s, gamma=0.0)
+    res["prune_sigma"]["tau"] = tau_s
+    res["fusion"] = run("prune + sample, fused", signal="max", tau=1e-3, gamma=0.01)
+    res["reinit"] = run("prune + sample, re-initialised", signal="max", tau=1e-3, gamma=0.01, reinit=True)
+    return res
 
 
 def refine_pass(torch, core, synth, scene):
