@@ -178,6 +178,18 @@ int dot_render(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opt
                int32_t *nseg_out, float *signal_inout, void *stream);
 
 /*
+ * dot_render_train -- the forward pass of a training step: dot_render with
+ *  nseg_out required, plus leaf_count_out: DEVICE uint32 [n_leaves],
+ *  overwritten with, per leaf, the number of this batch's segments whose
+ *  leaf has sigma > 0 -- the segments whose gradient rows the adjoint emits.
+ *  Given to dot_render_backward / dot_render_backward_rmsprop with the same
+ *  tree, rays and opts, it lets the adjoint skip its own counting traversal.
+ *  FP32 storage only (DOT_EUNSUPPORTED otherwise).
+ */
+int dot_render_train(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts, float *rgb_out,
+                     int32_t *nseg_out, float *signal_inout, uint32_t *leaf_count_out, void *stream);
+
+/*
  * dot_accumulate_signal -- the signal pass alone (same traversal and weights as
  * dot_render, no colour output): signal_inout DEVICE float [n_leaves], required.
  */
@@ -203,11 +215,14 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  once to size it; beyond 8 GiB of
  *  scratch, or if it cannot be allocated, the terms go straight to the
  *  arrays with FP32 atomics.  Summation order, hence the last bits, depends
- *  on scheduling.
+ *  on scheduling.  leaf_count: NULL, or the counts dot_render_train wrote
+ *  for the same tree, rays and opts (the counting traversal is then skipped;
+ *  counts from another batch give wrong gradients, never an access outside
+ *  the buffers).
  */
 int dot_render_backward(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                         const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,
-                        float *grad_sigma, float *grad_sh, void *stream);
+                        float *grad_sigma, float *grad_sh, const uint32_t *leaf_count, void *stream);
 
 typedef struct {
     float prune_tau;     /* prune selection: signal <= tau (prune_le) or < tau */
@@ -293,7 +308,8 @@ int dot_rmsprop_step(dot_tree_t tree, const float *grad_sigma, const float *grad
  */
 int dot_render_backward_rmsprop(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                                 const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb, float *v_sigma,
-                                float *v_sh, const dot_rmsprop_params *params, void *stream);
+                                float *v_sh, const dot_rmsprop_params *params, const uint32_t *leaf_count,
+                                void *stream);
 
 /*
  * dot_sigma_signal -- the density as the training signal (the paper's Pr_sigma

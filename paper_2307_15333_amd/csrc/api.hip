@@ -368,6 +368,30 @@ int dot_render(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, 
     return DOT_OK;
 }
 
+int dot_render_train(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, float* rgb_out,
+                     int32_t* nseg_out, float* signal_inout, uint32_t* leaf_count_out, void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_render_train: tree is NULL");
+    if (t->storage != DOT_F32) return fail(DOT_EUNSUPPORTED, "dot_render_train: only FP32 leaf storage is trainable");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_render_train");
+    if (rc) return rc;
+    if (!leaf_count_out) return fail(DOT_EINVAL, "dot_render_train: leaf_count_out is NULL");
+    if (rb.n_rays > 0 && (!rgb_out || !nseg_out)) return fail(DOT_EINVAL, "dot_render_train: rgb_out and nseg_out are required");
+    FwdArgs a{};
+    rc = fill_opts(opts, a.bg, a.thr, "dot_render_train");
+    if (rc) return rc;
+    a.rgb = rgb_out;
+    a.nseg = nseg_out;
+    a.signal = signal_inout;
+    a.signal_mode = opts ? opts->signal_mode : DOT_SIGNAL_MAX;
+    a.leaf_count = leaf_count_out;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_fill_u32(leaf_count_out, t->n_leaves, s);
+    if (e == hipSuccess) e = launch_render_fwd(*t, rb, a, s);
+    if (e != hipSuccess) return hip_fail(e, "dot_render_train: launch");
+    return DOT_OK;
+}
+
 int dot_accumulate_signal(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, float* signal_inout,
                           void* stream) {
     if (!t) return fail(DOT_EINVAL, "dot_accumulate_signal: tree is NULL");
@@ -387,7 +411,7 @@ int dot_accumulate_signal(dot_tree_t t, const dot_rays* rays, const dot_render_o
 
 int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, const float* rgb_fwd,
                         const int32_t* nseg, const float* grad_rgb, float* grad_sigma, float* grad_sh,
-                        void* stream) {
+                        const uint32_t* leaf_count, void* stream) {
     if (!t) return fail(DOT_EINVAL, "dot_render_backward: tree is NULL");
     if (t->storage == DOT_PAL16)
         return fail(DOT_EUNSUPPORTED, "dot_render_backward: a palette-compressed tree is not differentiable");
@@ -405,6 +429,7 @@ int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opt
     a.grad_rgb = grad_rgb;
     a.grad_sigma = grad_sigma;
     a.grad_sh = grad_sh;
+    a.leaf_count = leaf_count;
     hipError_t e = launch_render_bwd(*t, rb, a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_render_backward: launch");
     return DOT_OK;
@@ -412,7 +437,8 @@ int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opt
 
 int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts,
                                 const float* rgb_fwd, const int32_t* nseg, const float* grad_rgb, float* v_sigma,
-                                float* v_sh, const dot_rmsprop_params* params, void* stream) {
+                                float* v_sh, const dot_rmsprop_params* params, const uint32_t* leaf_count,
+                                void* stream) {
     if (!t || !params) return fail(DOT_EINVAL, "dot_render_backward_rmsprop: NULL tree or params");
     if (t->storage != DOT_F32)
         return fail(DOT_EUNSUPPORTED, "dot_render_backward_rmsprop: only FP32 leaf storage is trainable");
@@ -434,6 +460,7 @@ int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_re
     a.v_sigma = v_sigma;
     a.v_sh = v_sh;
     a.rms = params;
+    a.leaf_count = leaf_count;
     hipError_t e = launch_render_bwd(*t, rb, a, static_cast<hipStream_t>(stream));
     if (e == hipErrorOutOfMemory) return fail(DOT_ENOMEM, "dot_render_backward_rmsprop: scratch allocation failed");
     if (e != hipSuccess) return hip_fail(e, "dot_render_backward_rmsprop: launch");

@@ -72,6 +72,68 @@ __global__ void k_pb_scatter(const int64_t* __restrict__ ids, int64_t n, PixelGe
     }
 }
 
+// Few bins: every workgroup counts (and ranks) its chunk of rays in LDS, so a
+// bin takes one global atomic per workgroup instead of one per ray.
+constexpr int LDS_BINS = 4096;
+constexpr int ITEMS = 16;               // rays per thread
+constexpr int CHUNK = 256 * ITEMS;      // rays per workgroup
+
+__global__ __launch_bounds__(256) void k_pb_count_lds(const int64_t* __restrict__ ids, int64_t n, PixelGeo g,
+                                                      uint32_t* __restrict__ count) {
+    __shared__ uint32_t h[LDS_BINS];
+    for (int i = threadIdx.x; i < g.bins; i += 256) h[i] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * CHUNK;
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t r = base + (int64_t)j * 256 + threadIdx.x;
+        if (r < n) {
+            int64_t id = ids[r];
+            int32_t cam, pix;
+            atomicAdd(&h[tile_bin(id, g, cam, pix)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < g.bins; i += 256)
+        if (h[i]) atomicAdd(&count[i], h[i]);
+}
+
+// cursor holds each bin's exclusive offset; a workgroup reserves one range per
+// bin for its rays, then places each ray at its LDS rank within that range
+__global__ __launch_bounds__(256) void k_pb_scatter_lds(const int64_t* __restrict__ ids, int64_t n, PixelGeo g,
+                                                        uint32_t* __restrict__ cursor, int32_t* __restrict__ cam_out,
+                                                        int32_t* __restrict__ pix_out, int64_t* __restrict__ id_out) {
+    __shared__ uint32_t h[LDS_BINS];
+    __shared__ uint32_t b0[LDS_BINS];
+    for (int i = threadIdx.x; i < g.bins; i += 256) h[i] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * CHUNK;
+    uint32_t bin[ITEMS], rank[ITEMS];
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t r = base + (int64_t)j * 256 + threadIdx.x;
+        if (r < n) {
+            int64_t id = ids[r];
+            int32_t cam, pix;
+            bin[j] = (uint32_t)tile_bin(id, g, cam, pix);
+            rank[j] = atomicAdd(&h[bin[j]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < g.bins; i += 256) b0[i] = h[i] ? atomicAdd(&cursor[i], h[i]) : 0u;
+    __syncthreads();
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t r = base + (int64_t)j * 256 + threadIdx.x;
+        if (r < n) {
+            int64_t id = ids[r];
+            int32_t cam, pix;
+            (void)tile_bin(id, g, cam, pix);
+            const uint32_t pos = b0[bin[j]] + rank[j];
+            cam_out[pos] = cam;
+            pix_out[pos] = pix;
+            if (id_out) id_out[pos] = id;
+        }
+    }
+}
+
 unsigned grid_of(int64_t n) {
     int64_t g = (n + 255) / 256;
     return (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
@@ -92,12 +154,21 @@ hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t 
     uint32_t* cursor = count + g.bins;
     uint32_t* bsum = cursor + g.bins;
     uint32_t* tot = bsum + scan_scratch_elems(g.bins);
+    const bool lds = g.bins <= LDS_BINS;
+    const unsigned gl = (unsigned)((n + CHUNK - 1) / CHUNK);
     hipLaunchKernelGGL(k_pb_zero, dim3(grid_of(g.bins)), dim3(256), 0, s, count, g.bins);
-    hipLaunchKernelGGL(k_pb_count, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, count);
+    if (lds)
+        hipLaunchKernelGGL(k_pb_count_lds, dim3(gl), dim3(256), 0, s, ids, n, g, count);
+    else
+        hipLaunchKernelGGL(k_pb_count, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, count);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = scan_u32(count, cursor, g.bins, bsum, tot, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pb_scatter, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, cursor, cam_out, pix_out, id_out);
+    if (lds)
+        hipLaunchKernelGGL(k_pb_scatter_lds, dim3(gl), dim3(256), 0, s, ids, n, g, cursor, cam_out, pix_out, id_out);
+    else
+        hipLaunchKernelGGL(k_pb_scatter, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, cursor, cam_out, pix_out,
+                           id_out);
     return hipGetLastError();
 }
 

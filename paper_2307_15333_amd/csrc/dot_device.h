@@ -315,7 +315,7 @@ __device__ __forceinline__ void traverse(const TreeView& tv, const Ray& r, int* 
 // Per-ray compositing state for the forward pass.  S is the optical depth so
 // far (log of the transmittance, kept in FP32), T = exp(-S).  A segment's
 // weight is w = T_i - T_{i+1} = T_i (1 - exp(-tau_i)).
-template <int DT, int DEG>
+template <int DT, int DEG, bool COUNT = false>
 struct FwdSeg {
     static constexpr int K = (DEG + 1) * (DEG + 1);
     const TreeView& tv;
@@ -360,6 +360,9 @@ struct FwdSeg {
         float tau = sg * delta;
         ++n;
         fetched += tau > 0.f;
+        // a training forward counts, per leaf, the segments its adjoint will emit
+        if constexpr (COUNT)
+            if (sg > 0.f) atomicAdd(&a.leaf_count[leaf], 1u);
         {
             float Sn = S + tau;
             float Tn = __expf(-Sn);

@@ -113,6 +113,7 @@ struct FwdArgs {
     float bg[3];
     float thr;          // -ln(t_stop), +inf when disabled
     unsigned long long* stats;  // may be null
+    uint32_t* leaf_count;       // may be null: per leaf, the segments with sigma > 0 (for the adjoint)
 };
 
 struct BwdArgs {
@@ -122,6 +123,8 @@ struct BwdArgs {
     float* grad_sigma;
     float* grad_sh;
     float thr;
+    // per-leaf contributing-segment counts from the forward pass, or null (counted here)
+    const uint32_t* leaf_count;
     // fused RMSProp (grad_* unused): square averages and parameters, or null
     float* v_sigma;
     float* v_sh;
@@ -136,6 +139,7 @@ __device__ __forceinline__ void rmsprop_update(float& theta, float& v, float g, 
 
 hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArgs& a, hipStream_t s);
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_encode_planes(int storage, const float* src, void* dst, int64_t rows, int src_cols,
                                 int dst_stride, hipStream_t s);
 hipError_t launch_decode_planes(int storage, const void* src, float* dst, int64_t rows, int dst_cols,

@@ -7,7 +7,9 @@
 
 namespace dot {
 
-template <int DT, int DEG, bool STATS>
+// MODE 0: plain; 1: with the traversal counters of dot_render_stats; 2: with
+// the per-leaf segment counts of a training forward
+template <int DT, int DEG, int MODE>
 __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(TreeView tv, RayBatch rb, FwdArgs a) {
     __shared__ int stack_lds[LAT * BLOCK];
     const int tid = threadIdx.x;
@@ -18,7 +20,7 @@ __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(TreeView tv, RayBatch
     Ray r;
     int64_t rid;
     if (!make_ray(rb, tile, lane, r, rid)) return;
-    FwdSeg<DT, DEG> seg(tv, a);
+    FwdSeg<DT, DEG, MODE == 2> seg(tv, a);
     sh_basis<DEG>((float)r.dx, (float)r.dy, (float)r.dz, seg.Y);
     int desc = 0;
     traverse(tv, r, &stack_lds[tid], seg, desc);
@@ -29,7 +31,7 @@ __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(TreeView tv, RayBatch
         a.rgb[3 * rid + 2] = fmaf(Te, a.bg[2], seg.C[2]);
     }
     if (a.nseg) a.nseg[rid] = seg.n;
-    if constexpr (STATS) {
+    if constexpr (MODE == 1) {
         atomicAdd(&a.stats[0], 1ull);
         atomicAdd(&a.stats[1], (unsigned long long)seg.n);
         atomicAdd(&a.stats[2], (unsigned long long)seg.fetched);
@@ -381,18 +383,117 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const
     }
 }
 
+// Heavy buckets (many rows per leaf, e.g. a small tree under a large batch):
+// one wave per leaf, lanes stride over the rows, then a butterfly reduction of
+// the 1 + 3K sums across the wave; lane j then owns column j.  FUSED applies
+// RMSProp to every leaf, otherwise the sums are added to the gradient arrays.
+template <int DEG, bool FUSED>
+__global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
+    int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ count,
+    const uint32_t* __restrict__ cursor, const float* __restrict__ rows, float* __restrict__ gsig,
+    float* __restrict__ gsh, float* __restrict__ sigma, float* __restrict__ sh, int stride, float* __restrict__ vs,
+    float* __restrict__ vh, dot_rmsprop_params p) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int NV = 3 * K;
+    constexpr int RS = bwd_row_floats<DEG>();
+    constexpr int Q = RS / 4;
+    static_assert(NV <= WAVE, "one lane per column");
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    for (int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; l < L; l += nw) {
+        const uint32_t m = min(count[l], cursor[l]);
+        const float4* p4 = reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS);
+        float gs = 0.f, acc[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] = 0.f;
+        for (uint32_t r = lane; r < m; r += WAVE) {
+            const float4 h = p4[(int64_t)r * Q];
+            float Y[K];
+            if constexpr (RS == 8) {
+                const float4 q = p4[(int64_t)r * Q + 1];
+                sh_basis<DEG>(q.x, q.y, q.z, Y);
+            } else {
+                sh_basis<DEG>(0.f, 0.f, 1.f, Y);
+            }
+            gs += h.x;
+            const float a[3] = {h.y, h.z, h.w};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc[ch * K + k] += a[ch] * Y[k];
+        }
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) {
+            gs += __shfl_xor(gs, off, WAVE);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) acc[j] += __shfl_xor(acc[j], off, WAVE);
+        }
+        float mine = 0.f;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (lane == j) mine = acc[j];
+        if constexpr (FUSED) {
+            if (lane < NV) {
+                float t = sh[l * stride + lane], v = vh[l * NV + lane];
+                rmsprop_update(t, v, mine, p.lr_sh, p.alpha, p.eps);
+                sh[l * stride + lane] = t;
+                vh[l * NV + lane] = v;
+            }
+            if (lane == 0) {
+                float t = sigma[l], v = vs[l];
+                rmsprop_update(t, v, gs, p.lr_sigma, p.alpha, p.eps);
+                sigma[l] = t;
+                vs[l] = v;
+            }
+        } else if (m > 0) {
+            if (lane < NV && mine != 0.f) gsh[l * NV + lane] += mine;
+            if (lane == 0) gsig[l] += gs;
+        }
+    }
+}
+
+template <int DEG>
+static void launch_reduce_wave(const dot_tree& t, const BwdArgs& a, bool fused, const uint32_t* offset,
+                               const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
+    const int64_t L = t.n_leaves;
+    const unsigned g = (unsigned)std::min<int64_t>((L + RED_BLOCK / WAVE - 1) / (RED_BLOCK / WAVE), 1 << 16);
+    const dot_rmsprop_params p = fused ? *a.rms : dot_rmsprop_params{};
+    if (fused)
+        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, true>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, count, cursor,
+                           rows, nullptr, nullptr, static_cast<float*>(t.sigma), static_cast<float*>(t.sh),
+                           t.sh_stride, a.v_sigma, a.v_sh, p);
+    else
+        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, false>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, count,
+                           cursor, rows, a.grad_sigma, a.grad_sh, nullptr, nullptr, 0, nullptr, nullptr, p);
+}
+
+// buckets holding at least this many rows on average are reduced a wave per leaf
+static constexpr uint32_t kWaveRowsPerLeaf = 32;
+
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 template <int DT, int DEG>
 static hipError_t fwd_dispatch_stats(const TreeView& tv, const RayBatch& rb, const FwdArgs& a,
                                      dim3 grid, hipStream_t s) {
     if (a.stats)
-        hipLaunchKernelGGL((render_fwd_kernel<DT, DEG, true>), grid, dim3(BLOCK), 0, s, tv, rb, a);
-    else
-        hipLaunchKernelGGL((render_fwd_kernel<DT, DEG, false>), grid, dim3(BLOCK), 0, s, tv, rb, a);
+        hipLaunchKernelGGL((render_fwd_kernel<DT, DEG, 1>), grid, dim3(BLOCK), 0, s, tv, rb, a);
+    else if constexpr (DT == DOT_F32) {
+        if (a.leaf_count)
+            hipLaunchKernelGGL((render_fwd_kernel<DT, DEG, 2>), grid, dim3(BLOCK), 0, s, tv, rb, a);
+        else
+            hipLaunchKernelGGL((render_fwd_kernel<DT, DEG, 0>), grid, dim3(BLOCK), 0, s, tv, rb, a);
+    } else {
+        hipLaunchKernelGGL((render_fwd_kernel<DT, DEG, 0>), grid, dim3(BLOCK), 0, s, tv, rb, a);
+    }
     return hipGetLastError();
 }
 
@@ -500,13 +601,15 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     const int64_t L = t.n_leaves;
     const int rs = bwd_row_floats_rt(t.degree);
     TreeView tv = t.view();
-    uint32_t* count = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
+    // the forward's counts when given, else our own (filled by the counting pass)
+    uint32_t* count_own = a.leaf_count ? nullptr : static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
+    uint32_t* count = a.leaf_count ? const_cast<uint32_t*>(a.leaf_count) : count_own;
     uint32_t* offset = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
     uint32_t* cursor = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
     uint32_t* bsum = static_cast<uint32_t*>(t.alloc.get((size_t)scan_scratch_elems(L) * 4));
     uint32_t* tot = static_cast<uint32_t*>(t.alloc.get(16));
     auto drop = [&]() {
-        t.alloc.put(count);
+        t.alloc.put(count_own);
         t.alloc.put(offset);
         t.alloc.put(cursor);
         t.alloc.put(bsum);
@@ -517,12 +620,14 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     unsigned fg = (unsigned)std::min<int64_t>((L + 255) / 256, 65536);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count, L);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L);
-    switch (t.storage) {
-        case DOT_F32: hipLaunchKernelGGL(bwd_count_kernel<DOT_F32>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
-        case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
-        default: hipLaunchKernelGGL(bwd_count_kernel<DOT_BF16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+    if (!a.leaf_count) {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count, L);
+        switch (t.storage) {
+            case DOT_F32: hipLaunchKernelGGL(bwd_count_kernel<DOT_F32>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+            case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+            default: hipLaunchKernelGGL(bwd_count_kernel<DOT_BF16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+        }
     }
     hipError_t e = scan_u32(count, offset, L, bsum, tot, s);
     uint32_t m = 0;
@@ -544,7 +649,14 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
     }
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
-    if (fused) {
+    if ((uint64_t)m >= (uint64_t)kWaveRowsPerLeaf * (uint64_t)L) {
+        switch (t.degree) {
+            case 0: launch_reduce_wave<0>(t, a, fused, offset, count, cursor, rows, s); break;
+            case 1: launch_reduce_wave<1>(t, a, fused, offset, count, cursor, rows, s); break;
+            case 2: launch_reduce_wave<2>(t, a, fused, offset, count, cursor, rows, s); break;
+            default: launch_reduce_wave<3>(t, a, fused, offset, count, cursor, rows, s); break;
+        }
+    } else if (fused) {
         switch (t.degree) {
             case 0: launch_bwd_rmsprop<0>(t, a, offset, count, cursor, rows, s); break;
             case 1: launch_bwd_rmsprop<1>(t, a, offset, count, cursor, rows, s); break;

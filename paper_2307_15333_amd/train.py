@@ -88,6 +88,7 @@ class Trainer:
         t = self.tree
         self.state = t.rmsprop_state() if self.cfg.optimizer == "rmsprop" else t.adam_state()
         self.gs = self.gh = None      # dense gradients, for the unfused optimiser steps only
+        self._cnt = None              # per-leaf segment counts of the current batch
         self.opt_step = 0
 
     def permutation(self):
@@ -101,13 +102,16 @@ class Trainer:
         cam, pix, ids, self._ws = core.pixel_batch(idx.contiguous(), self.W, self.H, self.n_cams, self._ws)
         rays = core.Rays.pixels_device(self.cams_raw, self.n_cams, cam, pix)
         mode = "sum" if c.signal == "sum" else "max"
-        rgb, nseg = self.tree.render(rays, bg=c.bg, t_stop=c.t_stop, nseg=True, signal=signal, signal_mode=mode)
+        # the training forward also counts each leaf's segments, so the adjoint
+        # sizes its buckets without a traversal of its own
+        rgb, nseg, self._cnt = self.tree.render_train(rays, bg=c.bg, t_stop=c.t_stop, signal=signal, signal_mode=mode,
+                                                      leaf_count=self._cnt)
         loss, grad = core.mse_loss(rgb, self.targets, ids)
         self.opt_step += 1
         if c.optimizer == "rmsprop" and c.fused:
             # adjoint and update in one call: the gradient never exists as dense arrays
             self.tree.backward_rmsprop(rays, rgb, nseg, grad, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
-                                       alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop)
+                                       alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt)
             return loss
         if self.gs is None:
             t = self.tree
@@ -116,7 +120,7 @@ class Trainer:
         else:
             self.gs.zero_()
             self.gh.zero_()
-        self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop)
+        self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt)
         if c.optimizer == "rmsprop":
             self.tree.rmsprop_step(self.gs, self.gh, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
                                    alpha=c.alpha, eps=c.eps)

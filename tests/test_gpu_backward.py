@@ -143,3 +143,32 @@ def test_export_roundtrip_all_storages():
         np.testing.assert_array_equal(ex["sigma"], O.round_storage(s.sigma.astype(np.float64), storage))
         np.testing.assert_array_equal(ex["sh"], O.round_storage(s.sh.astype(np.float64), storage))
         tree.close()
+
+
+def test_training_forward_counts_and_backward_with_them():
+    """dot_render_train's per-leaf counts (t_stop = 0: every segment of every
+    ray) equal the oracle's segment lists, bit for bit; the adjoint fed with
+    them equals the adjoint that counts by itself."""
+    core = _core()
+    s = synth.random_tree_scene(5, 2, seed=61, p_split=0.5)
+    views = synth.random_sphere_cameras(5, 3.5, 24, 24, seed=62)
+    ci, pi = synth.pixel_batch(5, 24, 24, 2000, seed=63)
+    rays = core.Rays.pixels(views, ci, pi)
+    tree = core.Octree.from_scene(s)
+    rgb, ns, cnt = tree.render_train(rays, t_stop=0.0)
+    o, d = O.camera_rays(views, ci, pi)
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    want = np.zeros(tree.n_leaves, np.int64)
+    for r in range(o.shape[0]):
+        leaf, delta = O.ray_segments(T, o[r], d[r])
+        np.add.at(want, leaf[s.sigma[leaf] > 0], 1)
+    np.testing.assert_array_equal(cnt.cpu().numpy().astype(np.int64), want)
+    g = torch.as_tensor(np.random.default_rng(64).normal(size=(ci.shape[0], 3)), dtype=torch.float32, device="cuda")
+    Ln, K = tree.n_leaves, tree.K
+    gs1, gh1 = torch.zeros(Ln, device="cuda"), torch.zeros((Ln, 3, K), device="cuda")
+    gs2, gh2 = torch.zeros(Ln, device="cuda"), torch.zeros((Ln, 3, K), device="cuda")
+    tree.backward(rays, rgb, ns, g, gs1, gh1, t_stop=0.0)
+    tree.backward(rays, rgb, ns, g, gs2, gh2, t_stop=0.0, leaf_count=cnt)
+    np.testing.assert_allclose(gs2.cpu().numpy(), gs1.cpu().numpy(), rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(gh2.cpu().numpy(), gh1.cpu().numpy(), rtol=1e-5, atol=1e-7)
+    tree.close()
