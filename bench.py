@@ -160,6 +160,7 @@ def main():
     n_touched = int((signal > 0).sum().item())
     compulsory = n_touched * (4 + 3 * K * 4)
     traffic = read_traffic()
+    achievable = stream_read_gbps(torch, L, lib)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
@@ -170,7 +171,9 @@ def main():
                 "other_bytes_per_launch": {"child_reads": stats["child_reads"] * 4, "rgb": n_rays * 12,
                                            "signal_reads": stats["sh_fetches"] * 4, "total": int(other)},
                 "compulsory_bytes_per_launch": compulsory, "distinct_leaves_composited": n_touched,
-                "compulsory_GBps": round(compulsory / kt / 1e9, 1)}
+                "compulsory_GBps": round(compulsory / kt / 1e9, 1),
+                "achievable_read_GBps": round(achievable, 1),
+                "traffic_GBps": None if traffic is None else round(traffic["hbm_bytes_per_launch"] / kt / 1e9, 1)}
     log(f"render kernel {kt * 1e3:.3f} ms; leaf-fetch {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak);"
         f" segments/ray {stats['segments'] / n_rays:.2f}")
 
@@ -197,6 +200,25 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def stream_read_gbps(torch, L, lib):
+    """Achievable HBM read bandwidth: dot_stream_read over a 4 GiB buffer."""
+    import ctypes as C
+    from paper_2307_15333_amd import core
+    nbytes = 4 << 30
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def fn():
+        L.check(lib.dot_stream_read(C.c_void_p(buf.data_ptr()), C.c_size_t(nbytes), C.c_void_p(sink.data_ptr()),
+                                    core._stream()))
+
+    kt = time_kernel(fn, 10, torch)
+    del buf
+    gbps = nbytes / kt / 1e9
+    log(f"stream read: {gbps:.1f} GB/s achievable ({gbps / HBM_PEAK_GBS:.1%} of the 8 TB/s peak)")
+    return gbps
 
 
 def measure_extra(torch, core, synth, scene, cams, tree_f32, args):

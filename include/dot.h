@@ -429,6 +429,15 @@ size_t dot_render_jobs_workspace(int32_t n_jobs);
 int dot_render_jobs(const dot_render_job *jobs, int32_t n_jobs, void *workspace, size_t workspace_bytes,
                     void *stream);
 
+/*
+ * dot_stream_read -- support kernel, not part of the method: reads `bytes`
+ *  (rounded down to 16) of the DEVICE buffer `buf` once with 16-byte loads,
+ *  to measure the achievable HBM read bandwidth that the renderer's roofline is
+ *  set against.  sink: DEVICE float, receives a value only to keep the loads
+ *  live.  Errors: DOT_EINVAL on a NULL or unaligned buffer.
+ */
+int dot_stream_read(const void *buf, size_t bytes, float *sink, void *stream);
+
 /* dot_last_error -- message of the last failure on this thread ("" if none). */
 const char *dot_last_error(void);
 

@@ -120,6 +120,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_int64), C.c_void_p]),
     "dot_render_jobs_workspace": (C.c_size_t, [C.c_int32]),
     "dot_render_jobs": (C.c_int, [C.POINTER(dot_render_job), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dot_stream_read": (C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "dot_last_error": (C.c_char_p, []),
 }
 

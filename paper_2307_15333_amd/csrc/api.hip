@@ -601,6 +601,14 @@ int dot_quantize_sh(dot_tree_t t, int32_t bits, void* stream) {
     return quantize_sh(*t, bits, static_cast<hipStream_t>(stream));
 }
 
+int dot_stream_read(const void* buf, size_t bytes, float* sink, void* stream) {
+    if (bytes > 0 && (!buf || !sink)) return fail(DOT_EINVAL, "dot_stream_read: NULL buffer or sink");
+    if (reinterpret_cast<uintptr_t>(buf) % 16 != 0) return fail(DOT_EINVAL, "dot_stream_read: buffer not 16-byte aligned");
+    hipError_t e = launch_stream_read(buf, bytes, sink, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_stream_read: launch");
+    return DOT_OK;
+}
+
 size_t dot_render_jobs_workspace(int32_t n_jobs) { return jobs_workspace_bytes(n_jobs < 0 ? 0 : n_jobs); }
 
 int dot_render_jobs(const dot_render_job* jobs, int32_t n_jobs, void* workspace, size_t workspace_bytes,

@@ -217,3 +217,16 @@ def test_config2_full_size_sampled():
     print(f"C2 sampled: max err {e.max():.3e} mean {e.mean():.3e} straddle {ref['straddle'].sum()}")
     assert e.max() <= TOL32
     tree.close()
+
+
+def test_stream_read_probe():
+    import ctypes as C
+    from paper_2307_15333_amd import _lib as L
+    lib = L.load()
+    buf = torch.empty(1 << 24, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, device="cuda")
+    L.check(lib.dot_stream_read(C.c_void_p(buf.data_ptr()), C.c_size_t(1 << 24), C.c_void_p(sink.data_ptr()), None))
+    L.check(lib.dot_stream_read(C.c_void_p(buf.data_ptr()), C.c_size_t(100), C.c_void_p(sink.data_ptr()), None))
+    torch.cuda.synchronize()
+    assert lib.dot_stream_read(C.c_void_p(buf.data_ptr() + 4), C.c_size_t(64), C.c_void_p(sink.data_ptr()),
+                               None) == L.DOT_EINVAL
