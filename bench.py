@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s render & train step (FP32 vs FP16 leaves); p50/p99 served latency"
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "render_fwd_config2_traffic.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "render_fwd_torus_box_traffic.md")
 
 
 def log(*a):
@@ -76,10 +76,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--no-config3", action="store_true")
+    ap.add_argument("--no-terrain", action="store_true", help="skip the 19M-leaf terrain precision run")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--alg1-epochs", type=int, default=4, help="epochs of the end-to-end training loop (0: skip)")
-    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "config3", "palette", "ablation"],
+    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "terrain", "palette", "ablation"],
                     help="run one secondary measurement alone and print its JSON (for profiling it)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
@@ -96,13 +96,13 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    if args.only in ("train", "config3"):
-        fn = {"train": train_step, "config3": config3_precision}[args.only]
+    if args.only in ("train", "terrain"):
+        fn = {"train": train_step, "terrain": terrain_precision}[args.only]
         print(json.dumps(fn(torch, core, synth, args)), flush=True)
         return
-    scene = synth.config2_scene()
-    cams = synth.config2_cameras()
-    log(f"config2 scene: {scene.n_leaves} leaves, {scene.n_internal} internal ({time.time() - t0:.1f}s)")
+    scene = synth.torus_box_scene()
+    cams = synth.ring_cameras()
+    log(f"torus+box scene: {scene.n_leaves} leaves, {scene.n_internal} internal ({time.time() - t0:.1f}s)")
     if args.only:
         fn = {"alg1": lambda: alg1_loop(torch, core, synth, scene, args),
               "palette": lambda: palette_render(torch, core, scene, core.Rays.cameras(cams), None, args),
@@ -191,7 +191,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded SDF octree, random SH; stands in for NeRF-synthetic 800x800 views)",
-        "config": {"workload": "config2: torus+box SDF octree, depth 9, %d leaves, SH degree 3, FP32 leaves, "
+        "config": {"workload": "torus+box SDF octree, depth 9, %d leaves, SH degree 3, FP32 leaves, "
                                "8 cameras x 800x800 on the radius-4 sphere, white bg, t_stop 1e-4, fused "
                                "max-weight signal" % scene.n_leaves,
                    "rays_per_step": n_rays, "parallelism": "single GPU"},
@@ -254,13 +254,13 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
         res.update(alg1_loop(torch, core, synth, scene, args))
     res.update(refine_pass(torch, core, synth, scene))
     res.update(serving(torch, core, synth, scene, args))
-    if not args.no_config3:
-        res.update(config3_precision(torch, core, synth, args))
+    if not args.no_terrain:
+        res.update(terrain_precision(torch, core, synth, args))
     return res
 
 
 def palette_render(torch, core, scene, rays, base_mrays, args):
-    """Config 2 compressed by the median-cut palette (2^16 FP16 rows, FP16 sigma,
+    """The torus+box octree compressed by the median-cut palette (2^16 FP16 rows, FP16 sigma,
     uint16 index per leaf): build time, render Mrays/s with the fused signal,
     and the image difference against the FP32 tree."""
     import ctypes as C
@@ -296,7 +296,7 @@ def palette_render(torch, core, scene, rays, base_mrays, args):
 
 def ablation(torch, core, synth, scene, cams, args):
     """Synthetic stand-in for the paper's signal and fusion ablations (Tab. 3,
-    App. C.1) on the config-2 tree: targets are the generator tree's renders
+    App. C.1) on the torus+box octree: targets are the generator tree's renders
     from 100 random 400x400 views (16M rays per epoch); training starts from
     SH + N(0, 0.1^2); 4 epochs of 2^20-ray batches with RMSProp and a
     refinement after epochs 2 and 4.  Prune-only runs (gamma = 0) compare the
@@ -352,10 +352,10 @@ def ablation(torch, core, synth, scene, cams, args):
 
 
 def refine_pass(torch, core, synth, scene):
-    """Config 2 refinement: max-weight signal over 100 random 800x800 views,
+    """Refinement of the torus+box octree: max-weight signal over 100 random 800x800 views,
     then top 5% subdivided (max depth 10) and signal <= 1e-3 pruned."""
     tree = core.Octree.from_scene(scene, "f32")
-    views = synth.config2_refine_views(100)
+    views = synth.sphere_views(100)
     sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
     n_rays = 0
     torch.cuda.synchronize()
@@ -378,12 +378,12 @@ def refine_pass(torch, core, synth, scene):
 
 
 def serving(torch, core, synth, c2_scene, args):
-    """Config 5: four resident FP16 trees (two config-1 size, two config-2 size),
+    """Serving: four resident FP16 trees (two 8.6k-leaf spheres, two 3.5M-leaf torus+box trees),
     Poisson arrivals at 200 req/s, resolutions uniform over {128^2, 256^2, 512^2,
     800^2, 1920x1080}, continuous batching; latency percentiles after a warm-up."""
     from paper_2307_15333_amd import serve
     import dataclasses
-    s1a = synth.config1_scene()
+    s1a = synth.sphere_scene()
     s1b = synth.make_scene(synth.sdf_sphere(0.5), 5, 2, seed=40)
     rng = np.random.default_rng(41)
     sh_b = c2_scene.sh32.copy()
@@ -406,22 +406,22 @@ def serving(torch, core, synth, c2_scene, args):
             "serve_launches": st["launches"]}
 
 
-def config3_precision(torch, core, synth, args):
-    """Config 3: 19M-leaf terrain + ellipsoids octree, 4 views at 1920x1080,
+def terrain_precision(torch, core, synth, args):
+    """Precision on the 19M-leaf terrain + ellipsoids octree, 4 views at 1920x1080,
     leaves stored in FP32 / FP16 / BF16; throughput per dtype and error against
     the FP64 oracle on the generator values (4096 sampled rays)."""
     from oracle import oracle as O
     t0 = time.time()
-    s = synth.config3_scene()
-    cams = synth.config3_cameras()
-    log(f"config3 scene: {s.n_leaves} leaves ({time.time() - t0:.0f}s)")
+    s = synth.terrain_scene()
+    cams = synth.terrain_cameras()
+    log(f"terrain scene: {s.n_leaves} leaves ({time.time() - t0:.0f}s)")
     rays = core.Rays.cameras(cams)
     rng = np.random.default_rng(0)
     idx = rng.choice(rays.n_rays, 4096, replace=False)
     npx = 1920 * 1080
     o, d = O.camera_rays(cams, (idx // npx).astype(np.int32), (idx % npx).astype(np.int32))
     ref = O.render(O.OracleTree.from_scene(s), o, d)
-    out = {"config3_leaves": s.n_leaves}
+    out = {"terrain_leaves": s.n_leaves}
     for storage in ("f32", "f16", "bf16"):
         tree = core.Octree.from_scene(s, storage)
         rgb = tree.render(rays)
@@ -429,22 +429,22 @@ def config3_precision(torch, core, synth, args):
         g = rgb.cpu().numpy()[idx].astype(np.float64)
         e = np.minimum(np.abs(g - ref["rgb"]).max(1),
                        np.minimum(np.abs(g - ref["rgb_early"]).max(1), np.abs(g - ref["rgb_late"]).max(1)))
-        out[f"config3_{storage}"] = {"mrays": round(rays.n_rays / kt / 1e6, 1), "err_max": float(e.max()),
+        out[f"terrain_{storage}"] = {"mrays": round(rays.n_rays / kt / 1e6, 1), "err_max": float(e.max()),
                                      "err_p99": float(np.quantile(e, 0.99)), "err_mean": float(e.mean())}
-        log(f"config3 {storage}: {rays.n_rays / kt / 1e6:.0f} Mrays/s, err max {e.max():.2e} "
+        log(f"terrain {storage}: {rays.n_rays / kt / 1e6:.0f} Mrays/s, err max {e.max():.2e} "
             f"p99 {np.quantile(e, 0.99):.2e} mean {e.mean():.2e}")
         tree.close()
     return out
 
 
 def train_step(torch, core, synth, args):
-    """Config 4: one optimisation step -- forward, MSE, hand-written backward,
-    Adam -- over 2^18 random rays of 100 views of the config-1 octree (SH
+    """One optimisation step -- forward, MSE, hand-written backward, Adam --
+    over 2^18 random rays of 100 64x64 views of the 8.6k-leaf sphere octree (SH
     perturbed by N(0, 0.05^2)), through the training driver."""
     from paper_2307_15333_amd import train as TR
-    gt = synth.config1_scene()
+    gt = synth.sphere_scene()
     start = synth.perturb_sh(gt, 0.05, seed=3)
-    views = synth.config4_views(100)
+    views = synth.training_views(100)
     gt_tree = core.Octree.from_scene(gt)
     target = gt_tree.render(core.Rays.cameras(views))           # [100*64*64, 3]
     gt_tree.close()
@@ -471,13 +471,13 @@ def train_step(torch, core, synth, args):
 
 
 def alg1_loop(torch, core, synth, scene, args):
-    """Alg. 1 end to end on the config-2 octree: 100 random 800x800 views of
+    """Alg. 1 end to end on the torus+box octree: 100 random 800x800 views of
     the generator scene as targets (64M rays per epoch), training copy with SH
     perturbed by N(0, 0.05^2); epochs of 2^20-ray batches, RMSProp (lr 0.1 /
     0.01), refinement every 2nd epoch from the fused max-weight signal (prune
     <= 1e-3, top 1% subdivided up to depth 10)."""
     from paper_2307_15333_amd import train as TR
-    views = synth.config2_refine_views(100)
+    views = synth.sphere_views(100)
     gt = core.Octree.from_scene(scene)
     W, H = int(views[0]["width"]), int(views[0]["height"])
     target = torch.empty((len(views) * W * H, 3), dtype=torch.float32, device="cuda")

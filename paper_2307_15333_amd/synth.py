@@ -484,41 +484,41 @@ def random_explicit_rays(n, seed, radius=3.0, spread=1.0):
 # ----------------------------------------------------------------------------
 
 
-def config1_scene():
+def sphere_scene():
     """Sphere r=0.5, depth 5, degree 2, seed 0."""
     return make_scene(sdf_sphere(0.5), max_depth=5, degree=2, seed=0)
 
 
-def config1_camera():
+def sphere_camera():
     """One 64x64 camera at radius 4, azimuth 30, elevation 20, 40 deg FOV."""
     return cameras([(30.0, 20.0, 4.0, 64, 64)])
 
 
-def config2_scene():
+def torus_box_scene():
     """Torus (R=0.55, r=0.18) union box (half 0.3), depth 9, degree 3, seed 1."""
     return make_scene(sdf_torus_box(), max_depth=9, degree=3, seed=1)
 
 
-def config2_cameras(width=800, height=800):
+def ring_cameras(width=800, height=800):
     """Eight views on the radius-4 sphere: azimuth 45j, elevation +-30 alternating."""
     return cameras([(45.0 * j, 30.0 if j % 2 == 0 else -30.0, 4.0, width, height)
                     for j in range(8)])
 
 
-def config2_refine_views(n=100, width=800, height=800, seed=11):
+def sphere_views(n=100, width=800, height=800, seed=11):
     return random_sphere_cameras(n, 4.0, width, height, seed)
 
 
-def config3_scene():
+def terrain_scene():
     """Terrain + 20 ellipsoids, depth 10, degree 3, seed 2."""
     return make_scene(sdf_terrain_ellipsoids(seed=2), max_depth=10, degree=3, seed=2)
 
 
-def config3_cameras(width=1920, height=1080):
+def terrain_cameras(width=1920, height=1080):
     return cameras([(90.0 * j + 20.0, 25.0, 4.0, width, height) for j in range(4)])
 
 
-def config4_views(n=100, size=64, seed=3):
+def training_views(n=100, size=64, seed=3):
     return random_sphere_cameras(n, 4.0, size, size, seed + 100)
 
 

@@ -42,10 +42,10 @@ def _grads(scene, rays_gpu, o, d, g, t_stop, bg=(1.0, 1.0, 1.0)):
 
 
 @pytest.mark.parametrize("t_stop", [0.0, 1e-4])
-def test_backward_matches_oracle_config1(t_stop):
+def test_backward_matches_oracle_sphere(t_stop):
     core = _core()
-    s = synth.config1_scene()
-    views = synth.config4_views(n=9)
+    s = synth.sphere_scene()
+    views = synth.training_views(n=9)
     ci, pi = synth.pixel_batch(9, 64, 64, 8192, seed=1)
     rng = np.random.default_rng(2)
     g = rng.normal(size=(ci.shape[0], 3))
@@ -73,7 +73,7 @@ def test_backward_random_tree_explicit_rays():
 
 def test_autograd_function_mse():
     core = _core()
-    s = synth.config1_scene()
+    s = synth.sphere_scene()
     cams = synth.cameras([(40.0, 30.0, 4.0, 48, 40)])
     tree = core.Octree.from_scene(s)
     rays = core.Rays.cameras(cams)

@@ -4,7 +4,7 @@ Indices are integer work: bit-exact.  Palette rows are FP64 means rounded once
 to FP16 on both sides (summation order differs, so 1 FP16 ulp is allowed and
 counted).  Rendering a compressed tree is compared with the FP64 oracle
 rendering the decoded tree (tolerance 1e-5, as for every FP32-arithmetic
-render).  At config-2 size the median-cut invariants are checked instead.
+render).  On the 3.5M-leaf torus+box tree the median-cut invariants are checked instead.
 """
 import numpy as np
 import pytest
@@ -67,9 +67,9 @@ def test_palette_with_more_boxes_than_leaves():
 
 def test_palette_render_matches_oracle():
     core = _core()
-    s = synth.config1_scene()
+    s = synth.sphere_scene()
     tree, stored, idx, pal, _ = _quantize_both(s, 9)
-    cams = synth.config1_camera()
+    cams = synth.sphere_camera()
     rays = core.Rays.cameras(cams)
     sig = torch.zeros(tree.n_leaves, device="cuda")
     rgb = tree.render(rays, signal=sig).cpu().numpy().astype(np.float64)
@@ -92,10 +92,10 @@ def test_palette_render_matches_oracle():
 def test_palette_tree_in_the_serving_kernel():
     from paper_2307_15333_amd import serve
     core = _core()
-    s = synth.config1_scene()
+    s = synth.sphere_scene()
     tree = core.Octree.from_scene(s)
     tree.quantize_sh(8)
-    cam = synth.config1_camera()
+    cam = synth.sphere_camera()
     ref = tree.render(core.Rays.cameras(cam)).cpu().numpy().reshape(64, 64, 3)
     srv = serve.Server([tree], out_budget_bytes=1 << 26)
     req = serve.Request(rid=0, tree=0, cam=cam[0], width=64, height=64, arrival=0.0)
@@ -122,7 +122,7 @@ def test_palette_rejections():
     with pytest.raises(L.DotError) as e:
         tree.refine(sig)
     assert e.value.code == L.DOT_EUNSUPPORTED
-    rays = core.Rays.cameras(synth.config1_camera())
+    rays = core.Rays.cameras(synth.sphere_camera())
     rgb, ns = tree.render(rays, nseg=True)
     z = torch.zeros(tree.n_leaves, device="cuda")
     with pytest.raises(L.DotError) as e:
@@ -131,11 +131,11 @@ def test_palette_rejections():
     tree.close()
 
 
-def test_palette_config2_full_size_invariants():
+def test_palette_torus_box_full_size_invariants():
     """3.54M leaves, 2^16 boxes: box sizes are the repeated halvings of N, and
     sampled palette rows equal the FP16-rounded mean of their members."""
     core = _core()
-    s = synth.config2_scene()
+    s = synth.torus_box_scene()
     tree = core.Octree.from_scene(s)
     torch.cuda.synchronize()
     tree.quantize_sh(16)
@@ -160,7 +160,7 @@ def test_palette_config2_full_size_invariants():
     ex = tree.export()
     sse = float(((ex["sh"].reshape(N, -1) - sh) ** 2).sum())
     sse1 = float(((sh - sh.mean(0)) ** 2).sum())
-    print(f"config-2 palette: SSE {sse:.4e} vs one-box {sse1:.4e}, mean |err| "
+    print(f"torus+box palette: SSE {sse:.4e} vs one-box {sse1:.4e}, mean |err| "
           f"{np.abs(ex['sh'].reshape(N, -1) - sh).mean():.3e}")
     assert sse < sse1
     tree.close()

@@ -140,7 +140,7 @@ def test_refine_reinit(recursive):
 def test_refine_then_render_matches_oracle():
     """Refined trees stay renderable: subdivision leaves every pixel unchanged."""
     core = _core()
-    s = synth.config1_scene()
+    s = synth.sphere_scene()
     tree = core.Octree.from_scene(s)
     cams = synth.cameras([(30.0, 20.0, 4.0, 48, 48)])
     rays = core.Rays.cameras(cams)
@@ -157,8 +157,8 @@ def test_refine_end_to_end_signal_from_oracle_render():
     """GPU signal -> GPU refine versus oracle signal -> oracle refine; leaves whose
     signal is within 1e-5 of tau or of the k-th key may differ (counted)."""
     core = _core()
-    s = synth.config1_scene()
-    views = synth.config4_views(n=6)
+    s = synth.sphere_scene()
+    views = synth.training_views(n=6)
     tree = core.Octree.from_scene(s)
     sig = torch.zeros(tree.n_leaves, device="cuda")
     tree.accumulate_signal(core.Rays.cameras(views), sig)
@@ -182,9 +182,9 @@ def test_refine_end_to_end_signal_from_oracle_render():
     tree.close()
 
 
-def test_refine_config2_full_size():
+def test_refine_torus_box_full_size():
     """The 3.54M-leaf octree with a seeded signal: top 5%, tau = 1e-3, max depth 10."""
-    s = synth.config2_scene()
+    s = synth.torus_box_scene()
     sig = _seeded_signal(s.n_leaves, 21, 0.4)
     st, n_ulp = _compare(s, sig, prune_tau=1e-3, sample_frac=0.05, max_depth=10)
-    print(f"config2 refine: {st}, values off by 1 ulp: {n_ulp}")
+    print(f"torus+box refine: {st}, values off by 1 ulp: {n_ulp}")

@@ -40,8 +40,8 @@ def oracle_tree(scene, storage="f32"):
 
 
 @pytest.fixture(scope="module")
-def c1():
-    return synth.config1_scene()
+def sphere():
+    return synth.sphere_scene()
 
 
 def _render(scene, rays, storage="f32", **kw):
@@ -57,50 +57,50 @@ def _render(scene, rays, storage="f32", **kw):
 
 
 @pytest.mark.parametrize("t_stop", [1e-4, 0.0])
-def test_config1_fp32_parity(c1, t_stop):
+def test_sphere_fp32_parity(sphere, t_stop):
     core = _core()
-    cams = synth.config1_camera()
-    rgb, ns, sig = _render(c1, core.Rays.cameras(cams), t_stop=t_stop)
+    cams = synth.sphere_camera()
+    rgb, ns, sig = _render(sphere, core.Rays.cameras(cams), t_stop=t_stop)
     o, d = O.camera_rays(cams)
-    ref = O.render(oracle_tree(c1), o, d, t_stop=t_stop, signal=True)
+    ref = O.render(oracle_tree(sphere), o, d, t_stop=t_stop, signal=True)
     e = rgb_err(rgb, ref)
-    print(f"C1 t_stop={t_stop}: max err {e.max():.3e} mean {e.mean():.3e} straddle {ref['straddle'].sum()}")
+    print(f"sphere t_stop={t_stop}: max err {e.max():.3e} mean {e.mean():.3e} straddle {ref['straddle'].sum()}")
     assert e.max() <= TOL32
     assert np.all(sig >= ref["sig_lo"] - TOL32) and np.all(sig <= ref["sig_hi"] + TOL32)
     same = (ns == ref["nseg"]) | ref["straddle"]
     assert same.mean() >= 0.999, same.mean()
 
 
-def test_signal_sum_mode(c1):
+def test_signal_sum_mode(sphere):
     core = _core()
-    cams = synth.config1_camera()
-    tree = core.Octree.from_scene(c1)
+    cams = synth.sphere_camera()
+    tree = core.Octree.from_scene(sphere)
     sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
     tree.accumulate_signal(core.Rays.cameras(cams), sig, t_stop=0.0, signal_mode="sum")
     o, d = O.camera_rays(cams)
-    ref = O.render(oracle_tree(c1), o, d, t_stop=0.0, signal=True, signal_mode="sum")
+    ref = O.render(oracle_tree(sphere), o, d, t_stop=0.0, signal=True, signal_mode="sum")
     got = sig.cpu().numpy()
     np.testing.assert_allclose(got, ref["sig"], atol=1e-4, rtol=1e-5)
     tree.close()
 
 
 @pytest.mark.parametrize("w,h", [(61, 37), (1, 1), (8, 8), (9, 17), (130, 3)])
-def test_ragged_images(c1, w, h):
+def test_ragged_images(sphere, w, h):
     core = _core()
     cams = synth.cameras([(30.0, 20.0, 4.0, w, h), (200.0, -40.0, 3.5, w, h)])
-    rgb, ns, sig = _render(c1, core.Rays.cameras(cams))
+    rgb, ns, sig = _render(sphere, core.Rays.cameras(cams))
     o, d = O.camera_rays(cams)
-    ref = O.render(oracle_tree(c1), o, d, signal=True)
+    ref = O.render(oracle_tree(sphere), o, d, signal=True)
     assert rgb_err(rgb, ref).max() <= TOL32
 
 
-def test_pixel_list_mode(c1):
+def test_pixel_list_mode(sphere):
     core = _core()
-    views = synth.config4_views(n=7)
+    views = synth.training_views(n=7)
     ci, pi = synth.pixel_batch(7, 64, 64, 3001, seed=5)
-    rgb, ns, sig = _render(c1, core.Rays.pixels(views, ci, pi))
+    rgb, ns, sig = _render(sphere, core.Rays.pixels(views, ci, pi))
     o, d = O.camera_rays(views, ci, pi)
-    ref = O.render(oracle_tree(c1), o, d, signal=True)
+    ref = O.render(oracle_tree(sphere), o, d, signal=True)
     assert rgb_err(rgb, ref).max() <= TOL32
     assert np.all(sig >= ref["sig_lo"] - TOL32) and np.all(sig <= ref["sig_hi"] + TOL32)
 
@@ -149,13 +149,13 @@ def test_degenerate_trees():
         assert rgb_err(rgb, ref).max() <= TOL32
 
 
-def test_empty_batches(c1):
+def test_empty_batches(sphere):
     core = _core()
-    tree = core.Octree.from_scene(c1)
+    tree = core.Octree.from_scene(sphere)
     rays = core.Rays.explicit(np.zeros((0, 3)), np.zeros((0, 3)))
     rgb = tree.render(rays)
     assert rgb.shape == (0, 3)
-    cams = synth.config1_camera()
+    cams = synth.sphere_camera()
     r = core.Rays.cameras(cams)
     r.struct.n_cams = 0
     tree.render(r)
@@ -163,10 +163,10 @@ def test_empty_batches(c1):
     tree.close()
 
 
-def test_render_is_deterministic(c1):
+def test_render_is_deterministic(sphere):
     core = _core()
     cams = synth.cameras([(30.0, 20.0, 4.0, 64, 64), (100.0, 10.0, 4.0, 64, 64)])
-    tree = core.Octree.from_scene(c1)
+    tree = core.Octree.from_scene(sphere)
     rays = core.Rays.cameras(cams)
     outs = []
     for _ in range(3):
@@ -179,16 +179,16 @@ def test_render_is_deterministic(c1):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_reduced_precision_leaves(c1, storage):
+def test_reduced_precision_leaves(sphere, storage):
     core = _core()
-    cams = synth.config1_camera()
-    rgb, ns, sig = _render(c1, core.Rays.cameras(cams), storage=storage)
+    cams = synth.sphere_camera()
+    rgb, ns, sig = _render(sphere, core.Rays.cameras(cams), storage=storage)
     o, d = O.camera_rays(cams)
     # arithmetic-only: the oracle reads the same rounded leaves
-    ref_r = O.render(oracle_tree(c1, storage), o, d)
+    ref_r = O.render(oracle_tree(sphere, storage), o, d)
     e_arith = rgb_err(rgb, ref_r)
     # quantisation-inclusive: the oracle reads the FP64 generator values
-    ref_q = O.render(O.OracleTree.from_scene(c1), o, d)
+    ref_q = O.render(O.OracleTree.from_scene(sphere), o, d)
     e_q = rgb_err(rgb, ref_q)
     print(f"{storage}: arithmetic max {e_arith.max():.3e}; vs FP64 values max {e_q.max():.3e} "
           f"p99 {np.quantile(e_q, 0.99):.3e} mean {e_q.mean():.3e}")
@@ -196,12 +196,12 @@ def test_reduced_precision_leaves(c1, storage):
     assert e_q.max() <= TOL16
 
 
-def test_config2_full_size_sampled():
+def test_torus_box_full_size_sampled():
     """The 800x800 x 8-camera workload as benchmarked; 4096 sampled pixels
     checked against the oracle, all pixels checked for range."""
     core = _core()
-    s = synth.config2_scene()
-    cams = synth.config2_cameras()
+    s = synth.torus_box_scene()
+    cams = synth.ring_cameras()
     tree = core.Octree.from_scene(s)
     rays = core.Rays.cameras(cams)
     sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
@@ -214,7 +214,7 @@ def test_config2_full_size_sampled():
     o, d = O.camera_rays(cams, ci, pi)
     ref = O.render(oracle_tree(s), o, d)
     e = rgb_err(rgb[idx], ref)
-    print(f"C2 sampled: max err {e.max():.3e} mean {e.mean():.3e} straddle {ref['straddle'].sum()}")
+    print(f"torus+box sampled: max err {e.max():.3e} mean {e.mean():.3e} straddle {ref['straddle'].sum()}")
     assert e.max() <= TOL32
     tree.close()
 

@@ -22,7 +22,7 @@ def _mods():
 @pytest.fixture(scope="module")
 def trees():
     core, _ = _mods()
-    scenes = [synth.config1_scene(),
+    scenes = [synth.sphere_scene(),
               synth.make_scene(synth.sdf_sphere(0.4, (0.1, -0.1, 0.0)), 5, 2, seed=7),
               synth.random_tree_scene(6, 3, seed=3, p_split=0.4, sigma_max=15.0),
               synth.random_tree_scene(6, 3, seed=4, p_split=0.4, sigma_max=15.0)]

@@ -1,4 +1,4 @@
-"""Config 3 at full size (19M leaves, 4 x 1920x1080): FP32, FP16 and BF16 leaf
+"""The terrain octree at full size (19M leaves, 4 x 1920x1080): FP32, FP16 and BF16 leaf
 storage against the FP64 oracle on the generator values, sampled rays.
 Tolerances: 1e-5 for FP32 leaves, 2e-3 for FP16/BF16 leaves (quantisation
 included)."""
@@ -11,11 +11,11 @@ from paper_2307_15333_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-def test_config3_full_size_per_dtype():
+def test_terrain_full_size_per_dtype():
     from paper_2307_15333_amd import core
-    s = synth.config3_scene()
+    s = synth.terrain_scene()
     assert 15_000_000 <= s.n_leaves <= 20_000_000
-    cams = synth.config3_cameras()
+    cams = synth.terrain_cameras()
     rays = core.Rays.cameras(cams)
     rng = np.random.default_rng(1)
     idx = rng.choice(rays.n_rays, 4096, replace=False)
@@ -28,5 +28,5 @@ def test_config3_full_size_per_dtype():
         tree.close()
         e = np.minimum(np.abs(g - ref["rgb"]).max(1),
                        np.minimum(np.abs(g - ref["rgb_early"]).max(1), np.abs(g - ref["rgb_late"]).max(1)))
-        print(f"config3 {storage}: max {e.max():.3e} p99 {np.quantile(e, 0.99):.3e} mean {e.mean():.3e}")
+        print(f"terrain {storage}: max {e.max():.3e} p99 {np.quantile(e, 0.99):.3e} mean {e.mean():.3e}")
         assert e.max() <= tol, (storage, e.max())

@@ -216,7 +216,7 @@ LOOP_EPS = 1e-4
 
 
 def loop_inputs():
-    sc = synth.config1_scene()
+    sc = synth.sphere_scene()
     cams = synth.random_sphere_cameras(N_VIEWS, 4.0, SIZE, SIZE, seed=21)
     o, d = O.camera_rays(cams)
     o, d = o.reshape(-1, 3), d.reshape(-1, 3)

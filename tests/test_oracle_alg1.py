@@ -65,7 +65,7 @@ def test_sigma_signal_is_the_clamped_density():
 
 
 def _setup(n_views=3, size=16, seed=5):
-    sc = synth.config1_scene()
+    sc = synth.sphere_scene()
     cams = synth.random_sphere_cameras(n_views, 4.0, size, size, seed=seed)
     o, d = O.camera_rays(cams)
     return sc, cams, o.reshape(-1, 3), d.reshape(-1, 3)

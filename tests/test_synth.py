@@ -39,9 +39,9 @@ def _check_canonical(s):
         assert order == list(range(s.n_leaves))
 
 
-def test_config1_scene_shape_and_determinism():
-    a = synth.config1_scene()
-    b = synth.config1_scene()
+def test_sphere_scene_shape_and_determinism():
+    a = synth.sphere_scene()
+    b = synth.sphere_scene()
     assert a.n_leaves == b.n_leaves and np.array_equal(a.child, b.child)
     assert np.array_equal(a.sh32, b.sh32) and np.array_equal(a.sigma64, b.sigma64)
     assert a.degree == 2 and a.sh32.shape == (a.n_leaves, 3, 9)
@@ -61,7 +61,7 @@ def test_random_and_uniform_trees_are_canonical():
 
 
 def test_tree_from_cells_matches_level_construction():
-    s = synth.config1_scene()
+    s = synth.sphere_scene()
     rng = np.random.default_rng(0)
     perm = rng.permutation(s.n_leaves)
     child, order = synth.tree_from_cells(s.leaf_depth[perm], s.leaf_ijk[perm], 5)
@@ -70,7 +70,7 @@ def test_tree_from_cells_matches_level_construction():
 
 
 def test_cameras_look_at_origin():
-    cams = synth.config2_cameras()
+    cams = synth.ring_cameras()
     assert cams.shape == (8,)
     for c in cams:
         M = c["c2w"].reshape(3, 4).astype(np.float64)
