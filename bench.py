@@ -85,8 +85,9 @@ def main():
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md and is not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the renderer would shard by rays "
+              "with the tree replicated and one all-reduce (max) of the signal, which is not run here.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -48,7 +48,7 @@ enum {
     DOT_EINVAL = -1,       /* malformed argument or tree */
     DOT_ENOMEM = -2,       /* allocation failed */
     DOT_EHIP = -3,         /* HIP runtime error (message from hipGetErrorString) */
-    DOT_EUNSUPPORTED = -4  /* valid request this build does not implement */
+    DOT_EUNSUPPORTED = -4  /* valid request the library does not support (e.g. training reduced-precision leaves) */
 };
 
 /* leaf storage precision of the sigma and SH planes; arithmetic is FP32.
