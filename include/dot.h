@@ -184,10 +184,21 @@ int dot_render(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opt
  *  leaf has sigma > 0 -- the segments whose gradient rows the adjoint emits.
  *  Given to dot_render_backward / dot_render_backward_rmsprop with the same
  *  tree, rays and opts, it lets the adjoint skip its own counting traversal.
- *  FP32 storage only (DOT_EUNSUPPORTED otherwise).
+ *  records: DEVICE buffer or NULL.  When given, the forward also records each
+ *  ray's first `max_segments` segments whose leaf has sigma > 0 (leaf, delta,
+ *  optical depth and colour; 24 bytes each), max_segments being the largest
+ *  count for which dot_render_train_records_bytes(n_rays, max_segments) fits
+ *  in records_bytes (at most 1024).  The adjoint then replays them instead of
+ *  traversing the tree and fetching the leaves again, and re-traverses only
+ *  the rays that had more.  The layout is private to the library; the buffer
+ *  stays the caller's.
+ *  FP32 storage only (DOT_EUNSUPPORTED otherwise); DOT_EINVAL on a records
+ *  buffer too small for one segment per ray.
  */
+size_t dot_render_train_records_bytes(int64_t n_rays, int32_t max_segments);
 int dot_render_train(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts, float *rgb_out,
-                     int32_t *nseg_out, float *signal_inout, uint32_t *leaf_count_out, void *stream);
+                     int32_t *nseg_out, float *signal_inout, uint32_t *leaf_count_out, void *records,
+                     size_t records_bytes, void *stream);
 
 /*
  * dot_accumulate_signal -- the signal pass alone (same traversal and weights as
@@ -218,11 +229,13 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  on scheduling.  leaf_count: NULL, or the counts dot_render_train wrote
  *  for the same tree, rays and opts (the counting traversal is then skipped;
  *  counts from another batch give wrong gradients, never an access outside
- *  the buffers).
+ *  the buffers).  records: NULL, or the records that same dot_render_train
+ *  call wrote (requires leaf_count; `records_bytes` as given to it).
  */
 int dot_render_backward(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                         const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,
-                        float *grad_sigma, float *grad_sh, const uint32_t *leaf_count, void *stream);
+                        float *grad_sigma, float *grad_sh, const uint32_t *leaf_count, const void *records,
+                        size_t records_bytes, void *stream);
 
 typedef struct {
     float prune_tau;     /* prune selection: signal <= tau (prune_le) or < tau */
@@ -309,7 +322,7 @@ int dot_rmsprop_step(dot_tree_t tree, const float *grad_sigma, const float *grad
 int dot_render_backward_rmsprop(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                                 const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb, float *v_sigma,
                                 float *v_sh, const dot_rmsprop_params *params, const uint32_t *leaf_count,
-                                void *stream);
+                                const void *records, size_t records_bytes, void *stream);
 
 /*
  * dot_sigma_signal -- the density as the training signal (the paper's Pr_sigma

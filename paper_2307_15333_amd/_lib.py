@@ -92,13 +92,14 @@ SIGNATURES = {
     "dot_tree_info": (C.c_int, [C.c_void_p, C.POINTER(dot_tree_info_t)]),
     "dot_render": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts), C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dot_render_train_records_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dot_render_train": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts), C.c_void_p,
-                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dot_accumulate_signal": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                         C.c_void_p, C.c_void_p]),
     "dot_render_backward": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                      C.c_void_p, C.c_void_p]),
+                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dot_refine": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(dot_refine_params),
                              C.POINTER(dot_refine_stats), C.c_void_p]),
     "dot_adam_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -107,7 +108,8 @@ SIGNATURES = {
                                    C.POINTER(dot_rmsprop_params), C.c_void_p]),
     "dot_render_backward_rmsprop": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                              C.POINTER(dot_rmsprop_params), C.c_void_p, C.c_void_p]),
+                                              C.POINTER(dot_rmsprop_params), C.c_void_p, C.c_void_p, C.c_size_t,
+                                              C.c_void_p]),
     "dot_sigma_signal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_pixel_batch_workspace": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     "dot_pixel_batch": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,

@@ -193,16 +193,23 @@ class Octree:
                                     _ptr(signal), _stream()))
         return (rgb, ns) if nseg else rgb
 
-    def render_train(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max", leaf_count=None):
-        """Training forward: (rgb, nseg, leaf_count) -- leaf_count feeds the adjoint's buckets."""
+    def render_train(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max", leaf_count=None,
+                     records=None):
+        """Training forward: (rgb, nseg, leaf_count) -- leaf_count feeds the adjoint's buckets; `records`
+        (uint8 device buffer of records_bytes(n) bytes, or None) receives the segments the adjoint replays."""
         rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device=self.device)
         ns = torch.empty(rays.n_rays, dtype=torch.int32, device=self.device)
         if leaf_count is None or leaf_count.numel() < self.n_leaves:
             leaf_count = torch.empty(self.n_leaves, dtype=torch.int32, device=self.device)
         op = render_opts(bg, t_stop, signal_mode)
         L.check(self.lib.dot_render_train(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb), _ptr(ns),
-                                          _ptr(signal), _ptr(leaf_count), _stream()))
+                                          _ptr(signal), _ptr(leaf_count), _ptr(records),
+                                          C.c_size_t(records.numel() if records is not None else 0), _stream()))
         return rgb, ns, leaf_count
+
+    @staticmethod
+    def records_bytes(n_rays, max_segments=96):
+        return int(L.load().dot_render_train_records_bytes(int(n_rays), int(max_segments)))
 
     def accumulate_signal(self, rays, signal, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal_mode="max"):
         op = render_opts(bg, t_stop, signal_mode)
@@ -211,11 +218,12 @@ class Octree:
         return signal
 
     def backward(self, rays, rgb, nseg, grad_rgb, grad_sigma, grad_sh, bg=(1.0, 1.0, 1.0), t_stop=1e-4,
-                 leaf_count=None):
+                 leaf_count=None, records=None):
         op = render_opts(bg, t_stop)
         L.check(self.lib.dot_render_backward(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
                                              _ptr(nseg), _ptr(grad_rgb), _ptr(grad_sigma), _ptr(grad_sh),
-                                             _ptr(leaf_count), _stream()))
+                                             _ptr(leaf_count), _ptr(records),
+                                             C.c_size_t(records.numel() if records is not None else 0), _stream()))
 
     def render_stats(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
         op = render_opts(bg, t_stop)
@@ -251,13 +259,15 @@ class Octree:
                                           _ptr(state["v_sh"]), C.byref(p), _stream()))
 
     def backward_rmsprop(self, rays, rgb, nseg, grad_rgb, state, lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8,
-                         bg=(1.0, 1.0, 1.0), t_stop=1e-4, leaf_count=None):
+                         bg=(1.0, 1.0, 1.0), t_stop=1e-4, leaf_count=None, records=None):
         """Adjoint and RMSProp step in one call (no dense gradient arrays)."""
         op = render_opts(bg, t_stop)
         p = L.dot_rmsprop_params(lr_sigma=lr_sigma, lr_sh=lr_sh, alpha=alpha, eps=eps)
         L.check(self.lib.dot_render_backward_rmsprop(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
                                                      _ptr(nseg), _ptr(grad_rgb), _ptr(state["v_sigma"]),
-                                                     _ptr(state["v_sh"]), C.byref(p), _ptr(leaf_count), _stream()))
+                                                     _ptr(state["v_sh"]), C.byref(p), _ptr(leaf_count), _ptr(records),
+                                                     C.c_size_t(records.numel() if records is not None else 0),
+                                                     _stream()))
 
     def rmsprop_state(self):
         Ln = self.n_leaves

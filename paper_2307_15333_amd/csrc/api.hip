@@ -368,8 +368,23 @@ int dot_render(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, 
     return DOT_OK;
 }
 
+size_t dot_render_train_records_bytes(int64_t n_rays, int32_t max_segments) {
+    if (n_rays < 0 || max_segments < 1 || max_segments > SEG_CAP_MAX) return 0;
+    return seg_records_bytes(n_rays, max_segments);
+}
+
+// the records view of a caller's buffer for a batch of n rays (validated)
+static int records_for(const void* records, size_t bytes, int64_t n, SegRecords& out, const char* who) {
+    out = SegRecords{};
+    if (!records || n == 0) return DOT_OK;
+    out = seg_records_view(const_cast<void*>(records), n, bytes);
+    if (!out.a) return fail(DOT_EINVAL, std::string(who) + ": records buffer too small for one segment per ray");
+    return DOT_OK;
+}
+
 int dot_render_train(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, float* rgb_out,
-                     int32_t* nseg_out, float* signal_inout, uint32_t* leaf_count_out, void* stream) {
+                     int32_t* nseg_out, float* signal_inout, uint32_t* leaf_count_out, void* records,
+                     size_t records_bytes, void* stream) {
     if (!t) return fail(DOT_EINVAL, "dot_render_train: tree is NULL");
     if (t->storage != DOT_F32) return fail(DOT_EUNSUPPORTED, "dot_render_train: only FP32 leaf storage is trainable");
     RayBatch rb;
@@ -385,8 +400,11 @@ int dot_render_train(dot_tree_t t, const dot_rays* rays, const dot_render_opts* 
     a.signal = signal_inout;
     a.signal_mode = opts ? opts->signal_mode : DOT_SIGNAL_MAX;
     a.leaf_count = leaf_count_out;
+    rc = records_for(records, records_bytes, rb.n_rays, a.rec, "dot_render_train");
+    if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_fill_u32(leaf_count_out, t->n_leaves, s);
+    if (e == hipSuccess && a.rec.a) e = launch_fill_u32(a.rec.overflow, 1, s);
     if (e == hipSuccess) e = launch_render_fwd(*t, rb, a, s);
     if (e != hipSuccess) return hip_fail(e, "dot_render_train: launch");
     return DOT_OK;
@@ -411,7 +429,7 @@ int dot_accumulate_signal(dot_tree_t t, const dot_rays* rays, const dot_render_o
 
 int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, const float* rgb_fwd,
                         const int32_t* nseg, const float* grad_rgb, float* grad_sigma, float* grad_sh,
-                        const uint32_t* leaf_count, void* stream) {
+                        const uint32_t* leaf_count, const void* records, size_t records_bytes, void* stream) {
     if (!t) return fail(DOT_EINVAL, "dot_render_backward: tree is NULL");
     if (t->storage == DOT_PAL16)
         return fail(DOT_EUNSUPPORTED, "dot_render_backward: a palette-compressed tree is not differentiable");
@@ -430,6 +448,11 @@ int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opt
     a.grad_sigma = grad_sigma;
     a.grad_sh = grad_sh;
     a.leaf_count = leaf_count;
+    if (records && !leaf_count) return fail(DOT_EINVAL, "dot_render_backward: records need leaf_count");
+    if (records && t->storage != DOT_F32)
+        return fail(DOT_EINVAL, "dot_render_backward: records come from dot_render_train on an FP32 tree");
+    rc = records_for(records, records_bytes, rb.n_rays, a.rec, "dot_render_backward");
+    if (rc) return rc;
     hipError_t e = launch_render_bwd(*t, rb, a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_render_backward: launch");
     return DOT_OK;
@@ -438,7 +461,7 @@ int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opt
 int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts,
                                 const float* rgb_fwd, const int32_t* nseg, const float* grad_rgb, float* v_sigma,
                                 float* v_sh, const dot_rmsprop_params* params, const uint32_t* leaf_count,
-                                void* stream) {
+                                const void* records, size_t records_bytes, void* stream) {
     if (!t || !params) return fail(DOT_EINVAL, "dot_render_backward_rmsprop: NULL tree or params");
     if (t->storage != DOT_F32)
         return fail(DOT_EUNSUPPORTED, "dot_render_backward_rmsprop: only FP32 leaf storage is trainable");
@@ -461,6 +484,9 @@ int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_re
     a.v_sh = v_sh;
     a.rms = params;
     a.leaf_count = leaf_count;
+    if (records && !leaf_count) return fail(DOT_EINVAL, "dot_render_backward_rmsprop: records need leaf_count");
+    rc = records_for(records, records_bytes, rb.n_rays, a.rec, "dot_render_backward_rmsprop");
+    if (rc) return rc;
     hipError_t e = launch_render_bwd(*t, rb, a, static_cast<hipStream_t>(stream));
     if (e == hipErrorOutOfMemory) return fail(DOT_ENOMEM, "dot_render_backward_rmsprop: scratch allocation failed");
     if (e != hipSuccess) return hip_fail(e, "dot_render_backward_rmsprop: launch");

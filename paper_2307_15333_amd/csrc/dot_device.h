@@ -186,6 +186,32 @@ __device__ __forceinline__ bool make_ray(const RayBatch& rb, int64_t tile, int l
     return true;
 }
 
+// The ray with output index `rid` of the batch (the index make_ray reports).
+__device__ __forceinline__ Ray ray_of(const RayBatch& rb, int64_t rid) {
+    Ray r;
+    if (rb.kind == DOT_RAYS_CAMERAS) {
+        const int64_t hw = (int64_t)rb.width * rb.height;
+        const int cam = (int)(rid / hw);
+        const int p = (int)(rid - (int64_t)cam * hw);
+        const int v = p / rb.width;
+        return camera_ray(rb.cams[cam], p - v * rb.width, v);
+    }
+    if (rb.kind == DOT_RAYS_PIXELS) {
+        const dot_camera& c = rb.cams[rb.cam_idx[rid]];
+        const int p = rb.pix_idx[rid];
+        const int v = p / c.width;
+        return camera_ray(c, p - v * c.width, v);
+    }
+    r.ox = (double)rb.origins[3 * rid + 0];
+    r.oy = (double)rb.origins[3 * rid + 1];
+    r.oz = (double)rb.origins[3 * rid + 2];
+    r.dx = (double)rb.dirs[3 * rid + 0];
+    r.dy = (double)rb.dirs[3 * rid + 1];
+    r.dz = (double)rb.dirs[3 * rid + 2];
+    normalise(r);
+    return r;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
 // XCD receives a contiguous range of tiles (neighbouring tiles share leaves,
 // and each XCD has its own L2).
@@ -325,6 +351,8 @@ struct FwdSeg {
     float C[3] = {0.f, 0.f, 0.f};
     int n = 0;
     int fetched = 0;
+    int64_t rid = 0;    // COUNT: the ray's index in the batch (record column)
+    int nrec = 0;       // COUNT: composited segments recorded so far
 
     __device__ FwdSeg(const TreeView& tv_, const FwdArgs& a_) : tv(tv_), a(a_) {}
 
@@ -367,6 +395,7 @@ struct FwdSeg {
             float Sn = S + tau;
             float Tn = __expf(-Sn);
             float w = fmaxf(T - Tn, 0.f);
+            float cv[3];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 float x = 0.f;
@@ -382,7 +411,19 @@ struct FwdSeg {
                     }
                     x = fmaf(cf, Y[k], x);
                 }
-                C[ch] = fmaf(w, sigmoidf_(x), C[ch]);
+                cv[ch] = sigmoidf_(x);
+                C[ch] = fmaf(w, cv[ch], C[ch]);
+            }
+            // the record the adjoint replays: leaf, delta, tau and the colour
+            if constexpr (COUNT) {
+                if (sg > 0.f && a.rec.a) {
+                    if (nrec < a.rec.cap) {
+                        const int64_t j = (int64_t)nrec * a.rec.n + rid;
+                        a.rec.a[j] = make_float4(__int_as_float(leaf), delta, tau, cv[0]);
+                        a.rec.b[j] = make_float2(cv[1], cv[2]);
+                    }
+                    ++nrec;
+                }
             }
             if (a.signal) {
                 if (a.signal_mode == DOT_SIGNAL_MAX) {

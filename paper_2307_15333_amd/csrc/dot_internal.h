@@ -105,6 +105,25 @@ struct RayBatch {
     int64_t n_tiles;   // 64-ray units
 };
 
+// Segment records of a training forward, replayed by the adjoint instead of a
+// second traversal: per ray up to `cap` composited segments (sigma > 0), slot
+// major ([slot][ray]) so one step's writes and reads are coalesced.  A ray
+// with more records keeps only its count and is replayed by traversal.  The
+// buffer's size sets `cap`.
+constexpr int SEG_CAP_MAX = 1024;
+struct SegRecords {
+    float4* a = nullptr;          // [cap][n]: leaf id bits, delta, tau, c0
+    float2* b = nullptr;          // [cap][n]: c1, c2
+    int32_t* count = nullptr;     // [n]: records of the ray
+    uint32_t* overflow = nullptr; // [1]: rays with more than `cap` records
+    int32_t* olist = nullptr;     // [n]: ids of those rays (first `overflow` entries)
+    int64_t n = 0;                // rays the buffer holds (the slot stride)
+    int cap = 0;                  // records per ray
+};
+size_t seg_records_bytes(int64_t n_rays, int cap);
+// view of a buffer of `bytes` for n rays; cap = 0 when it is too small for one record
+SegRecords seg_records_view(void* base, int64_t n_rays, size_t bytes);
+
 struct FwdArgs {
     float* rgb;         // may be null
     int32_t* nseg;      // may be null
@@ -114,6 +133,7 @@ struct FwdArgs {
     float thr;          // -ln(t_stop), +inf when disabled
     unsigned long long* stats;  // may be null
     uint32_t* leaf_count;       // may be null: per leaf, the segments with sigma > 0 (for the adjoint)
+    SegRecords rec;             // training forward: segment records (a == null: none)
 };
 
 struct BwdArgs {
@@ -125,6 +145,8 @@ struct BwdArgs {
     float thr;
     // per-leaf contributing-segment counts from the forward pass, or null (counted here)
     const uint32_t* leaf_count;
+    // the forward's segment records (a == null: replay by traversal)
+    SegRecords rec;
     // fused RMSProp (grad_* unused): square averages and parameters, or null
     float* v_sigma;
     float* v_sh;

@@ -21,9 +21,16 @@ __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(TreeView tv, RayBatch
     int64_t rid;
     if (!make_ray(rb, tile, lane, r, rid)) return;
     FwdSeg<DT, DEG, MODE == 2> seg(tv, a);
+    seg.rid = rid;
     sh_basis<DEG>((float)r.dx, (float)r.dy, (float)r.dz, seg.Y);
     int desc = 0;
     traverse(tv, r, &stack_lds[tid], seg, desc);
+    if constexpr (MODE == 2) {
+        if (a.rec.a) {
+            a.rec.count[rid] = seg.nrec;
+            if (seg.nrec > a.rec.cap) a.rec.olist[atomicAdd(a.rec.overflow, 1u)] = (int32_t)rid;
+        }
+    }
     if (a.rgb) {
         float Te = seg.T;
         a.rgb[3 * rid + 0] = fmaf(Te, a.bg[0], seg.C[0]);
@@ -264,6 +271,131 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_kernel(TreeView tv, RayBatch r
     sh_basis<DEG>(seg.d[0], seg.d[1], seg.d[2], seg.Y);
     int desc = 0;
     traverse(tv, r, &stack_lds[tid], seg, desc);
+}
+
+// Re-traversal of the rays whose records overflowed (their ids listed by the
+// forward): one ray per lane, in list order.
+template <int DT, int DEG>
+__global__ __launch_bounds__(BLOCK) void bwd_emit_list_kernel(TreeView tv, RayBatch rb, BwdArgs a, const int32_t* list,
+                                                              int64_t nlist, const uint32_t* offset,
+                                                              const uint32_t* count, uint32_t* cursor, float* rows) {
+    __shared__ int stack_lds[LAT * BLOCK];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + tid;
+    if (i >= nlist) return;
+    const int64_t rid = list[i];
+    if (rid < 0 || rid >= rb.n_rays) return;
+    Ray r = ray_of(rb, rid);
+    BwdEmit<DT, DEG> seg(tv, offset, count, cursor, rows);
+    seg.limit = a.nseg[rid];
+    if (seg.limit <= 0) return;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        seg.C[ch] = a.rgb_fwd[3 * rid + ch];
+        seg.g[ch] = a.grad_rgb[3 * rid + ch];
+    }
+    if (seg.g[0] == 0.f && seg.g[1] == 0.f && seg.g[2] == 0.f) return;
+    seg.d[0] = (float)r.dx;
+    seg.d[1] = (float)r.dy;
+    seg.d[2] = (float)r.dz;
+    sh_basis<DEG>(seg.d[0], seg.d[1], seg.d[2], seg.Y);
+    int desc = 0;
+    traverse(tv, r, &stack_lds[tid], seg, desc);
+}
+
+// Replay of the forward's segment records (rays with at most `cap` of them):
+// the same per-segment arithmetic as BwdEmit, without the traversal and the
+// leaf fetches.  Same ray-to-lane mapping as the traversal kernels.
+template <int DEG>
+__global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArgs a, int64_t L, const uint32_t* offset,
+                                                             const uint32_t* count, uint32_t* cursor, float* rows) {
+    constexpr int RS = bwd_row_floats<DEG>();
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (tid >> 6);
+    if (tile >= rb.n_tiles) return;
+    Ray r;
+    int64_t rid;
+    if (!make_ray(rb, tile, lane, r, rid)) return;
+    const int nrec = a.rec.count[rid];
+    if (nrec <= 0 || nrec > a.rec.cap) return;
+    float g[3], C[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        C[ch] = a.rgb_fwd[3 * rid + ch];
+        g[ch] = a.grad_rgb[3 * rid + ch];
+    }
+    if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) return;
+    const float d[3] = {(float)r.dx, (float)r.dy, (float)r.dz};
+    float S = 0.f, T = 1.f, P[3] = {0.f, 0.f, 0.f};
+    for (int i = 0; i < nrec; ++i) {
+        const int64_t j = (int64_t)i * a.rec.n + rid;
+        const float4 A = a.rec.a[j];
+        const float2 B = a.rec.b[j];
+        const int leaf = __float_as_int(A.x);
+        if ((uint64_t)(uint32_t)leaf >= (uint64_t)L) break;   // records of another tree: stop, stay in bounds
+        const float delta = A.y, tau = A.z;
+        const float c[3] = {A.w, B.x, B.y};
+        const float Sn = S + tau;
+        const float Tn = __expf(-Sn);
+        const float w = fmaxf(T - Tn, 0.f);
+        float out[RS];
+        float gs = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            P[ch] = fmaf(w, c[ch], P[ch]);
+            gs = fmaf(g[ch], Tn * c[ch] - (C[ch] - P[ch]), gs);
+        }
+        out[0] = gs * delta;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) out[1 + ch] = w > 0.f ? g[ch] * w * c[ch] * (1.f - c[ch]) : 0.f;
+        if constexpr (RS == 8) {
+            out[4] = d[0];
+            out[5] = d[1];
+            out[6] = d[2];
+            out[7] = 0.f;
+        }
+        const uint32_t k = atomicAdd(&cursor[leaf], 1u);
+        if (k < count[leaf]) {
+            float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)offset[leaf] + k) * RS);
+#pragma unroll
+            for (int q = 0; q < RS / 4; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        }
+        S = Sn;
+        T = Tn;
+    }
+}
+
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t seg_records_bytes(int64_t n, int cap) {
+    return 256 + 2 * up256((size_t)n * 4) + up256((size_t)cap * n * 16) + up256((size_t)cap * n * 8);
+}
+
+SegRecords seg_records_view(void* base, int64_t n, size_t bytes) {
+    SegRecords r;
+    if (n <= 0) return r;
+    // the largest cap the buffer holds
+    int cap = 0;
+    for (int c = SEG_CAP_MAX; c >= 1; c = c > 8 ? c - 8 : c - 1)
+        if (seg_records_bytes(n, c) <= bytes) {
+            cap = c;
+            break;
+        }
+    if (cap == 0) return r;
+    char* p = static_cast<char*>(base);
+    r.overflow = reinterpret_cast<uint32_t*>(p);
+    p += 256;
+    r.count = reinterpret_cast<int32_t*>(p);
+    p += up256((size_t)n * 4);
+    r.olist = reinterpret_cast<int32_t*>(p);
+    p += up256((size_t)n * 4);
+    r.a = reinterpret_cast<float4*>(p);
+    p += up256((size_t)cap * n * 16);
+    r.b = reinterpret_cast<float2*>(p);
+    r.n = n;
+    r.cap = cap;
+    return r;
 }
 
 // Sum of one leaf's bucket: dsigma and, per channel, sum_rows a_ch Y_k(d_row).
@@ -630,8 +762,9 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         }
     }
     hipError_t e = scan_u32(count, offset, L, bsum, tot, s);
-    uint32_t m = 0;
+    uint32_t m = 0, overflow = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&m, tot, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && a.rec.a) e = hipMemcpyAsync(&overflow, a.rec.overflow, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         drop();
@@ -643,10 +776,31 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         drop();
         return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
-    switch (t.storage) {
-        case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
-        case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
-        default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
+    if (a.rec.a) {
+        // replay the recorded segments; re-traverse only the rays that overflowed
+        switch (t.degree) {
+            case 0: hipLaunchKernelGGL(bwd_emit_rec_kernel<0>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
+            case 1: hipLaunchKernelGGL(bwd_emit_rec_kernel<1>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
+            case 2: hipLaunchKernelGGL(bwd_emit_rec_kernel<2>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
+            default: hipLaunchKernelGGL(bwd_emit_rec_kernel<3>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
+        }
+    }
+    if (!a.rec.a) {
+        switch (t.storage) {
+            case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
+            case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
+            default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
+        }
+    } else if (overflow > 0) {
+        // only FP32 trees record (training storage)
+        const int64_t no = std::min<int64_t>(overflow, rb.n_rays);
+        const dim3 lg((unsigned)((no + BLOCK - 1) / BLOCK));
+        switch (t.degree) {
+            case 0: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 0>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
+            case 1: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 1>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
+            case 2: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 2>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
+            default: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 3>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
+        }
     }
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
     if ((uint64_t)m >= (uint64_t)kWaveRowsPerLeaf * (uint64_t)L) {

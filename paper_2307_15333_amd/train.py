@@ -48,6 +48,7 @@ class TrainConfig:
     reinit: bool = False            # ablation: new leaves start at zero instead of fused values
     refine: bool = True
     fused: bool = True              # RMSProp applied inside the adjoint's per-leaf reduction
+    record_segments: int = 96       # segments per ray the forward records for the adjoint's replay
     bg: tuple = (1.0, 1.0, 1.0)
     t_stop: float = 1e-4
     seed: int = 0
@@ -82,6 +83,7 @@ class Trainer:
         self.epoch = 0
         self.opt_step = 0
         self._ws = None
+        self._rec = None        # segment records of the current batch (forward -> adjoint)
         self._reset_optimizer()
 
     def _reset_optimizer(self):
@@ -102,16 +104,20 @@ class Trainer:
         cam, pix, ids, self._ws = core.pixel_batch(idx.contiguous(), self.W, self.H, self.n_cams, self._ws)
         rays = core.Rays.pixels_device(self.cams_raw, self.n_cams, cam, pix)
         mode = "sum" if c.signal == "sum" else "max"
-        # the training forward also counts each leaf's segments, so the adjoint
-        # sizes its buckets without a traversal of its own
+        # the training forward also counts each leaf's segments and records the
+        # composited segments, so the adjoint neither traverses nor refetches
+        need = core.Octree.records_bytes(idx.shape[0], c.record_segments)
+        if self._rec is None or self._rec.numel() < need:
+            self._rec = torch.empty(need, dtype=torch.uint8, device=self.device)
         rgb, nseg, self._cnt = self.tree.render_train(rays, bg=c.bg, t_stop=c.t_stop, signal=signal, signal_mode=mode,
-                                                      leaf_count=self._cnt)
+                                                      leaf_count=self._cnt, records=self._rec)
         loss, grad = core.mse_loss(rgb, self.targets, ids)
         self.opt_step += 1
         if c.optimizer == "rmsprop" and c.fused:
             # adjoint and update in one call: the gradient never exists as dense arrays
             self.tree.backward_rmsprop(rays, rgb, nseg, grad, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
-                                       alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt)
+                                       alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt,
+                                       records=self._rec)
             return loss
         if self.gs is None:
             t = self.tree
@@ -120,7 +126,8 @@ class Trainer:
         else:
             self.gs.zero_()
             self.gh.zero_()
-        self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt)
+        self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt,
+                           records=self._rec)
         if c.optimizer == "rmsprop":
             self.tree.rmsprop_step(self.gs, self.gh, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
                                    alpha=c.alpha, eps=c.eps)

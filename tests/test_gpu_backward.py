@@ -169,6 +169,59 @@ def test_training_forward_counts_and_backward_with_them():
     gs2, gh2 = torch.zeros(Ln, device="cuda"), torch.zeros((Ln, 3, K), device="cuda")
     tree.backward(rays, rgb, ns, g, gs1, gh1, t_stop=0.0)
     tree.backward(rays, rgb, ns, g, gs2, gh2, t_stop=0.0, leaf_count=cnt)
-    np.testing.assert_allclose(gs2.cpu().numpy(), gs1.cpu().numpy(), rtol=1e-5, atol=1e-7)
-    np.testing.assert_allclose(gh2.cpu().numpy(), gh1.cpu().numpy(), rtol=1e-5, atol=1e-7)
+    # same terms, bucket order decided by scheduling: equal up to FP32 summation order
+    assert _rel(gs2.cpu().numpy(), gs1.cpu().numpy()) <= 1e-5
+    assert _rel(gh2.cpu().numpy(), gh1.cpu().numpy()) <= 1e-5
     tree.close()
+
+
+@pytest.mark.parametrize("scene_kind,max_segments", [("random", 96), ("uniform", 16), ("uniform", 96)])
+def test_backward_replaying_forward_records(scene_kind, max_segments):
+    """The adjoint replaying the training forward's segment records (and
+    re-traversing only the rays with more recorded segments than the buffer
+    holds -- the uniform depth-5 tree with sigma > 0 everywhere has rays of up
+    to ~90) equals the adjoint that traverses by itself; the fused RMSProp
+    path too."""
+    core = _core()
+    if scene_kind == "random":
+        s = synth.random_tree_scene(5, 3, seed=71, p_split=0.5)
+    else:
+        s = synth.uniform_scene(5, 1, 0.3, seed=72)
+    views = synth.random_sphere_cameras(5, 3.5, 24, 24, seed=73)
+    ci, pi = synth.pixel_batch(5, 24, 24, 2500, seed=74)
+    rays = core.Rays.pixels(views, ci, pi)
+    tree = core.Octree.from_scene(s)
+    rec = torch.empty(core.Octree.records_bytes(ci.shape[0], max_segments), dtype=torch.uint8, device="cuda")
+    rgb, ns, cnt = tree.render_train(rays, t_stop=0.0, records=rec)
+    rgb0 = tree.render(rays, t_stop=0.0)
+    # the training kernel is a separate instantiation: FP32 contraction may differ by an ulp
+    np.testing.assert_allclose(rgb.cpu().numpy(), rgb0.cpu().numpy(), rtol=0, atol=1e-6)
+    nmax = int(ns.max().item())
+    print(f"{scene_kind}: max segments per ray {nmax}")
+    if scene_kind == "uniform":
+        assert nmax > 32
+    # the buffer size sets the records per ray
+    from paper_2307_15333_amd import _lib as L
+    assert L.load().dot_render_train_records_bytes(100, 0) == 0
+    g = torch.as_tensor(np.random.default_rng(75).normal(size=(ci.shape[0], 3)), dtype=torch.float32, device="cuda")
+    Ln, K = tree.n_leaves, tree.K
+    z = lambda *sh: torch.zeros(sh, device="cuda")
+    gs1, gh1, gs2, gh2 = z(Ln), z(Ln, 3, K), z(Ln), z(Ln, 3, K)
+    tree.backward(rays, rgb, ns, g, gs1, gh1, t_stop=0.0)
+    tree.backward(rays, rgb, ns, g, gs2, gh2, t_stop=0.0, leaf_count=cnt, records=rec)
+    assert _rel(gs2.cpu().numpy(), gs1.cpu().numpy()) <= 1e-5
+    assert _rel(gh2.cpu().numpy(), gh1.cpu().numpy()) <= 1e-5
+    # the fused RMSProp step with records against the unfused step on the same gradients
+    t2 = core.Octree.from_scene(s)
+    st1, st2 = tree.rmsprop_state(), t2.rmsprop_state()
+    tree.rmsprop_step(gs1, gh1, st1, eps=1e-4)
+    t2.backward_rmsprop(rays, rgb, ns, g, st2, eps=1e-4, t_stop=0.0, leaf_count=cnt, records=rec)
+    e1, e2 = tree.export(), t2.export()
+    np.testing.assert_allclose(e2["sigma"], e1["sigma"], rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(e2["sh"], e1["sh"], rtol=1e-5, atol=1e-5)
+    # records too small for the batch are refused
+    from paper_2307_15333_amd import _lib as L
+    with pytest.raises(L.DotError):
+        tree.render_train(rays, records=rec[:1000])
+    tree.close()
+    t2.close()
