@@ -153,7 +153,7 @@ def main():
     leaf_bytes = stats["segments"] * 4 + stats["sh_fetches"] * 3 * K * 4
     kt = time_kernel(step, max(5, args.steps // 2), torch)
     achieved = leaf_bytes / kt / 1e9
-    other = stats["child_reads"] * 4 + n_rays * 12 + stats["sh_fetches"] * 4
+    other = stats["index_reads"] * 4 + n_rays * 12 + stats["sh_fetches"] * 4
     # compulsory bytes: every distinct leaf the frame composites, fetched once
     # (leaves with a positive signal received a positive weight, hence an SH fetch)
     signal.zero_()
@@ -169,7 +169,7 @@ def main():
                 "algorithmic_bytes_per_launch": int(leaf_bytes),
                 "per_unit": "4 B sigma per segment + 192 B SH per segment with sigma*delta > 0",
                 "units_per_launch": {"segments": stats["segments"], "sh_fetches": stats["sh_fetches"]},
-                "other_bytes_per_launch": {"child_reads": stats["child_reads"] * 4, "rgb": n_rays * 12,
+                "other_bytes_per_launch": {"child_and_link_reads": stats["index_reads"] * 4, "rgb": n_rays * 12,
                                            "signal_reads": stats["sh_fetches"] * 4, "total": int(other)},
                 "compulsory_bytes_per_launch": compulsory, "distinct_leaves_composited": n_touched,
                 "compulsory_GBps": round(compulsory / kt / 1e9, 1),

@@ -134,6 +134,7 @@ typedef struct {
     void *palette;                /* DOT_PAL16: device FP16 [2^palette_bits][sh_stride]; else NULL.
                                      sh is then the uint16 index plane [n_leaves] */
     int32_t palette_bits, reserved;
+    void *links;                  /* device uint32 [n_leaves][6] face-neighbour links, or NULL (dot_set_links) */
 } dot_tree_info_t;
 
 /*
@@ -153,8 +154,29 @@ int dot_build(const dot_tree_desc *desc, int32_t storage, const dot_allocator *a
 int dot_free(dot_tree_t tree);
 
 /* dot_tree_info -- sizes and device pointers of the tree's planes.  Pointers
- * stay valid until the next dot_refine or dot_free on the tree. */
+ * stay valid until the next dot_refine or dot_free on the tree (links: also
+ * dot_set_links). */
 int dot_tree_info(dot_tree_t tree, dot_tree_info_t *out);
+
+/*
+ * dot_set_links -- keep (enable != 0) or drop (enable = 0) the tree's
+ *  face-neighbour links.  They are an acceleration structure of the leaf walk,
+ *  not part of the method: six uint32 per leaf (24 B of device memory per
+ *  leaf) naming, for each face, the internal node of the same depth or the
+ *  leaf of the same or a shallower depth across it (or the outside of the
+ *  root cube).  With them a ray finds its next leaf from one link read issued
+ *  together with the current leaf's data, descending only into a finer
+ *  neighbour, instead of re-descending the child array from the deepest
+ *  common ancestor.  The leaves visited and the segment lengths, hence every
+ *  rendered value, gradient and signal, are the same either way.
+ *  Links are built by dot_build and rebuilt by dot_refine while enabled; a
+ *  tree of more than 2^27 - 1 leaves, or a root leaf, walks without them.
+ *  Synchronises `stream`.  Errors: DOT_EINVAL on a NULL tree; DOT_ENOMEM /
+ *  DOT_EHIP while building (the tree then walks without links).  dot_refine
+ *  returns these codes too when the refined tree's links cannot be built; the
+ *  refinement itself is then complete.
+ */
+int dot_set_links(dot_tree_t tree, int32_t enable, void *stream);
 
 /*
  * dot_render -- forward volume rendering (Sec. 3 "Preliminaries", Eq. 1-2).
@@ -402,8 +424,8 @@ int dot_export(dot_tree_t tree, int32_t *child, float *sigma, float *sh, uint8_t
  * dot_render_stats -- work counters of one forward pass over `rays` (no colour
  *  output): counts[0] rays, [1] segments composited (delta > 0), [2] segments
  *  whose SH coefficients were fetched (sigma^ delta > 0), [3] child-array
- *  reads during traversal.  Synchronous.  Used to turn kernel time into
- *  algorithmic bytes per second.
+ *  and neighbour-link reads (4 B each) during traversal.  Synchronous.  Used
+ *  to turn kernel time into algorithmic bytes per second.
  */
 int dot_render_stats(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                      int64_t counts[4], void *stream);

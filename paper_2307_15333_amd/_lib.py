@@ -56,7 +56,8 @@ class dot_tree_info_t(C.Structure):
                 ("storage", C.c_int32), ("max_depth", C.c_int32), ("sh_stride", C.c_int32),
                 ("child", C.c_void_p), ("sigma", C.c_void_p), ("sh", C.c_void_p),
                 ("leaf_depth", C.c_void_p), ("bbox_min", C.c_float * 3), ("bbox_size", C.c_float),
-                ("palette", C.c_void_p), ("palette_bits", C.c_int32), ("reserved", C.c_int32)]
+                ("palette", C.c_void_p), ("palette_bits", C.c_int32), ("reserved", C.c_int32),
+                ("links", C.c_void_p)]
 
 
 class dot_refine_params(C.Structure):
@@ -117,6 +118,7 @@ SIGNATURES = {
     "dot_mse_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     "dot_quantize_sh": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "dot_set_links": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "dot_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_render_stats": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                    C.POINTER(C.c_int64), C.c_void_p]),

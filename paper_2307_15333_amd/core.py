@@ -229,7 +229,7 @@ class Octree:
         op = render_opts(bg, t_stop)
         out = (C.c_int64 * 4)()
         L.check(self.lib.dot_render_stats(self.handle, C.byref(rays.struct), C.byref(op), out, _stream()))
-        return dict(rays=out[0], segments=out[1], sh_fetches=out[2], child_reads=out[3])
+        return dict(rays=out[0], segments=out[1], sh_fetches=out[2], index_reads=out[3])
 
     def refine(self, signal, prune_tau=1e-3, sample_frac=0.05, max_depth=10, prune_le=True,
                recursive=False, reinit=False):
@@ -284,6 +284,18 @@ class Octree:
     def quantize_sh(self, bits=16):
         """Median-cut palette compression of the SH rows (in place; storage becomes 'pal16')."""
         L.check(self.lib.dot_quantize_sh(self.handle, int(bits), _stream()))
+
+    def set_links(self, enable=True):
+        """Keep or drop the face-neighbour links of the leaf walk (rendered values do not depend on them)."""
+        L.check(self.lib.dot_set_links(self.handle, 1 if enable else 0, _stream()))
+
+    def links_view(self):
+        """The face-neighbour links as an int32 view [L, 6] (uint32 bits), or None when the tree has none."""
+        i = self.info()
+        if not i.links:
+            return None
+        Ln = int(i.n_leaves)
+        return self.alloc.tensor(i.links, Ln * 24).view(torch.int32).view(Ln, 6)
 
     def palette_views(self):
         """(index [L] int16 view of the uint16 indices, palette [2^bits, 3, K] FP16) of a 'pal16' tree."""

@@ -172,6 +172,8 @@ static void release(dot_tree* t) {
     t->alloc.put(t->sh);
     t->alloc.put(t->leaf_depth);
     t->alloc.put(t->palette);
+    t->alloc.put(t->links);
+    t->links = nullptr;
     t->child = nullptr;
     t->sigma = nullptr;
     t->sh = nullptr;
@@ -312,6 +314,7 @@ int dot_build(const dot_tree_desc* desc, int32_t storage, const dot_allocator* a
     } else {
         rc = upload_plane(t->alloc, storage, desc->sigma, t->sigma, t->n_leaves, 1, 1, s);
         if (!rc) rc = upload_plane(t->alloc, storage, desc->sh, t->sh, t->n_leaves, nv, t->sh_stride, s);
+        if (!rc) rc = update_links(*t, s);
     }
     if (rc) {
         release(t);
@@ -346,7 +349,15 @@ int dot_tree_info(dot_tree_t t, dot_tree_info_t* out) {
     out->palette = t->palette;
     out->palette_bits = t->palette_bits;
     out->reserved = 0;
+    out->links = t->links;
     return DOT_OK;
+}
+
+int dot_set_links(dot_tree_t t, int32_t enable, void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_set_links: tree is NULL");
+    t->links_on = enable != 0;
+    if (t->links_on && t->links) return DOT_OK;
+    return update_links(*t, static_cast<hipStream_t>(stream));
 }
 
 int dot_render(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, float* rgb_out, int32_t* nseg_out,

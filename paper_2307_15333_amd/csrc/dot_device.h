@@ -226,14 +226,21 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 //
 // Positions live on an integer lattice of 2^LAT cells per axis.  The current
 // cell (ix, iy, iz) is the finest cell containing the ray just past the
-// current parameter s.  The leaf holding it is found by descending the child
-// array from the deepest ancestor shared with the previous leaf (kept in an
-// LDS stack, one column per lane).  The leaf's exit parameter is the nearest
-// of its three exit planes; the axis (or axes, at an edge or corner) that
-// attains it steps to the neighbouring cell exactly, and the others take the
-// cell of the exit point, clamped to the current leaf's span.
+// current parameter s.  The leaf's exit parameter is the nearest of its three
+// exit planes; the axis (or axes, at an edge or corner) that attains it steps
+// to the neighbouring cell exactly, and the others take the cell of the exit
+// point, clamped to the current leaf's span.  The leaf holding the new cell is
+// found
+//  - with face-neighbour links (tv.links): when one axis attains the exit,
+//    from the link of that face, read together with the leaf's data: a leaf
+//    there is the next leaf, an internal node of the same depth is descended
+//    by the cell's bits; an exit through an edge or corner descends from the
+//    root;
+//  - without links: by descending the child array from the deepest ancestor
+//    shared with the previous leaf, kept in an LDS stack (one column per lane)
+//    and found from the highest differing bit of the old and new cell.
 // `seg(leaf, delta)` is called for every segment with delta > 0 and returns
-// false to stop the ray.  `desc` counts child-array reads.
+// false to stop the ray.  `desc` counts child-array and link reads.
 // ---------------------------------------------------------------------------
 template <class Seg>
 __device__ __forceinline__ void traverse(const TreeView& tv, const Ray& r, int* __restrict__ stk,
@@ -266,17 +273,16 @@ __device__ __forceinline__ void traverse(const TreeView& tv, const Ray& r, int* 
 #pragma unroll
     for (int a = 0; a < 3; ++a) c[a] = min(max((int)floor(O[a]), 0), LAT_N - 1);
 
+    const bool linked = tv.links != nullptr;
     double s = 0.0;
-    int k0 = 0;
-    if (tv.n_internal > 0) stk[0] = 0;
+    int nd = 0, k = 0;       // where the next descent starts: node and its depth
+    int leaf = -1, ld = 0;   // the leaf holding cell c once known, and its depth
+    if (tv.n_internal > 0 && !linked) stk[0] = 0;
     for (int step = 0; step < tv.max_steps; ++step) {
-        int leaf, ld;
         if (tv.n_internal == 0) {
             leaf = 0;
             ld = 0;
-        } else {
-            int k = k0;
-            int nd = stk[k * BLOCK];
+        } else if (leaf < 0) {
             while (true) {
                 int sh = LAT - 1 - k;
                 int oct = ((c[0] >> sh) & 1) | (((c[1] >> sh) & 1) << 1) | (((c[2] >> sh) & 1) << 2);
@@ -289,7 +295,7 @@ __device__ __forceinline__ void traverse(const TreeView& tv, const Ray& r, int* 
                 }
                 ++k;
                 nd = e;
-                stk[k * BLOCK] = e;
+                if (!linked) stk[k * BLOCK] = e;
             }
         }
         const int cs = 1 << (LAT - ld);
@@ -309,6 +315,15 @@ __device__ __forceinline__ void traverse(const TreeView& tv, const Ray& r, int* 
         const bool last = tm >= s1;
         const double e = fmin(fmax(tm, s), s1);
         const float delta = (float)(e - s);
+        // the link across the exit face is requested before the leaf's data so
+        // that both arrive in one memory round trip
+        const int hits = (te[0] == tm) + (te[1] == tm) + (te[2] == tm);
+        uint32_t link = LINK_OUT;
+        if (linked && !last && hits == 1) {
+            const int ax = te[0] == tm ? 0 : (te[1] == tm ? 1 : 2);
+            link = tv.links[(int64_t)leaf * 6 + 2 * ax + (D[ax] > 0.0 ? 1 : 0)];
+            ++desc;
+        }
         if (delta > 0.f) {
             if (!seg(leaf, delta)) return;
         }
@@ -327,9 +342,31 @@ __device__ __forceinline__ void traverse(const TreeView& tv, const Ray& r, int* 
         }
         if (out) return;
         if (tv.n_internal > 0) {
-            unsigned diff = (unsigned)((c[0] ^ n[0]) | (c[1] ^ n[1]) | (c[2] ^ n[2]));
-            int cp = __clz(diff) - (32 - LAT);  // depth of the deepest shared ancestor
-            k0 = min(cp, ld - 1);
+            if (linked) {
+                if (hits != 1) {
+                    nd = 0;              // edge or corner: from the root
+                    k = 0;
+                    leaf = -1;
+                } else if (link & LINK_LEAF) {
+                    // LINK_OUT is not reached (an interior face has a
+                    // neighbour); ids are checked so a bad link cannot
+                    // read outside the planes
+                    if (link == LINK_OUT || (int64_t)(link & LINK_ID_MASK) >= tv.n_leaves) return;
+                    leaf = (int)(link & LINK_ID_MASK);
+                    ld -= (int)((link >> LINK_ID_BITS) & 15u);
+                } else {
+                    if ((int64_t)link >= tv.n_internal) return;
+                    nd = (int)link;      // same depth as the leaf just left
+                    k = ld;
+                    leaf = -1;
+                }
+            } else {
+                unsigned diff = (unsigned)((c[0] ^ n[0]) | (c[1] ^ n[1]) | (c[2] ^ n[2]));
+                int cp = __clz(diff) - (32 - LAT);  // depth of the deepest shared ancestor
+                k = min(cp, ld - 1);
+                nd = stk[k * BLOCK];
+                leaf = -1;
+            }
         }
         c[0] = n[0];
         c[1] = n[1];

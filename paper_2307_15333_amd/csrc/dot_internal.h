@@ -24,6 +24,20 @@ inline int sh_stride_for(int degree, int storage) {
 }
 inline int storage_bytes(int storage) { return storage == DOT_F32 ? 4 : 2; }
 
+// Face-neighbour links of the leaves.  links[6 * leaf + 2 * axis + (dir > 0)]
+// names what lies across that face of the leaf, at the leaf's depth or above:
+//   LINK_OUT                 the face is on the root cube's boundary;
+//   bit 31 clear             an internal node of the same depth as the leaf;
+//   bit 31 set               a leaf: bits 0-26 its id, bits 27-30 how many
+//                            levels shallower than this leaf it is (0..15).
+// A leaf's depth is at least 1 when the tree has internal nodes, so the depth
+// difference fits in 4 bits; leaf ids need n_leaves < 2^27 - 1.
+constexpr uint32_t LINK_OUT = 0xffffffffu;
+constexpr uint32_t LINK_LEAF = 0x80000000u;
+constexpr int LINK_ID_BITS = 27;
+constexpr uint32_t LINK_ID_MASK = (1u << LINK_ID_BITS) - 1u;
+constexpr int64_t LINK_MAX_LEAVES = (int64_t)LINK_ID_MASK;
+
 // Everything a kernel needs to read a tree (passed by value).
 struct TreeView {
     const int32_t* child;
@@ -36,6 +50,7 @@ struct TreeView {
     int max_steps;    // safety bound on traversal steps per ray
     int sh_stride;    // elements per SH row (of the palette for DOT_PAL16)
     const void* palette;   // DOT_PAL16: FP16 palette rows; `sh` holds uint16 indices
+    const uint32_t* links; // face-neighbour links [n_leaves][6], or null (ancestor-stack walk)
 };
 
 struct Alloc {
@@ -59,6 +74,8 @@ struct dot_tree {
     uint8_t* leaf_depth = nullptr;  // device
     void* palette = nullptr;        // device, DOT_PAL16 only
     int32_t palette_bits = 0;
+    uint32_t* links = nullptr;      // device [n_leaves][6], null when off or not built
+    bool links_on = true;           // keep face-neighbour links (rebuilt after refinement)
 
     dot::TreeView view() const {
         dot::TreeView v;
@@ -73,6 +90,7 @@ struct dot_tree {
         v.max_steps = 3 * (1 << md) + 64;
         v.sh_stride = sh_stride;
         v.palette = palette;
+        v.links = links;
         return v;
     }
 };
@@ -187,5 +205,8 @@ int quantize_sh(dot_tree& t, int bits, hipStream_t s);
 hipError_t launch_decode_palette(const dot_tree& t, float* dst, int64_t rows, int64_t row0, hipStream_t s);
 int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, dot_refine_stats* st,
                 hipStream_t s);
+// (re)build or drop t.links after the topology changed: built when t.links_on,
+// the tree has internal nodes and n_leaves <= LINK_MAX_LEAVES; synchronises s
+int update_links(dot_tree& t, hipStream_t s);
 
 }  // namespace dot

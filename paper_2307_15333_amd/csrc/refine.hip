@@ -533,7 +533,9 @@ int refine_tree(dot_tree& t, const float* signal, const dot_refine_params& p, do
         st_out->merged = (int64_t)h_tot[2];
         st_out->subdivided = (int64_t)h_tot[3];
     }
-    return DOT_OK;
+    // the old links described the old topology; without new ones the tree is
+    // still complete and walks by re-descent
+    return update_links(t, s);
 }
 
 }  // namespace dot

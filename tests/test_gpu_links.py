@@ -1,0 +1,208 @@
+"""Face-neighbour links of the leaf walk.
+
+The links are an acceleration structure, not part of the method, so they are
+pinned by two things of their own: a brute-force neighbour search on the CPU
+over the exported tree, and renders, segment counts, signals and training
+records that are bit-identical with and without links (the walk must visit the
+same leaves with the same segment lengths either way).  Edge and corner exits,
+which step by descending from the root, are exercised by the axis-aligned and
+diagonal rays of the explicit-ray set.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2307_15333_amd import synth
+from tests.test_gpu_render import _edge_rays
+
+pytestmark = pytest.mark.gpu
+
+OUT = 0xFFFFFFFF
+LEAF = 0x80000000
+ID_BITS = 27
+
+
+def _core():
+    from paper_2307_15333_amd import core
+    return core
+
+
+def leaf_cells(child, n_leaves):
+    """(depth [L], ijk [L, 3] at the leaf's own depth) by level-wise expansion."""
+    depth = np.zeros(n_leaves, np.int64)
+    ijk = np.zeros((n_leaves, 3), np.int64)
+    nodes = np.array([0], np.int64)
+    pos = np.zeros((1, 3), np.int64)
+    d = 0
+    while nodes.size:
+        e = child[nodes].reshape(-1).astype(np.int64)            # [n * 8], octant order
+        o = np.tile(np.arange(8), nodes.size)
+        p = np.repeat(pos, 8, axis=0) * 2 + np.stack([o & 1, (o >> 1) & 1, (o >> 2) & 1], 1)
+        lf = e < 0
+        depth[-1 - e[lf]] = d + 1
+        ijk[-1 - e[lf]] = p[lf]
+        nodes, pos, d = e[~lf], p[~lf], d + 1
+    return depth, ijk
+
+
+def brute_links(child, depth, ijk, leaves):
+    """Expected links of `leaves`: descend from the root to the neighbour cell
+    at the leaf's depth, stopping at a leaf (coarser or equal) or at that depth."""
+    res = np.full((leaves.size, 6), OUT, np.uint64)
+    for f in range(6):
+        a, up = f >> 1, f & 1
+        d = depth[leaves]
+        c = ijk[leaves].copy()
+        c[:, a] += 1 if up else -1
+        live = (c[:, a] >= 0) & (c[:, a] < (1 << d))
+        idx = np.nonzero(live)[0]
+        node = np.zeros(idx.size, np.int64)
+        k = 0
+        while idx.size:
+            sh = d[idx] - 1 - k
+            cc = c[idx]
+            o = ((cc[:, 0] >> sh) & 1) | (((cc[:, 1] >> sh) & 1) << 1) | (((cc[:, 2] >> sh) & 1) << 2)
+            e = child[node, o].astype(np.int64)
+            lf = e < 0
+            res[idx[lf], f] = LEAF | ((d[idx[lf]] - (k + 1)) << ID_BITS) | (-1 - e[lf])
+            at = (~lf) & (k + 1 == d[idx])
+            res[idx[at], f] = e[at]
+            keep = (~lf) & (~at)
+            idx, node, k = idx[keep], e[keep], k + 1
+    return res
+
+
+def check_links(tree, sample=None, seed=0):
+    ex = tree.export()
+    L = tree.n_leaves
+    view = tree.links_view()
+    assert view is not None
+    got = view.cpu().numpy().view(np.uint32).astype(np.uint64)
+    depth, ijk = leaf_cells(ex["child"], L)
+    np.testing.assert_array_equal(depth, ex["depth"].astype(np.int64))
+    leaves = np.arange(L) if sample is None or sample >= L else \
+        np.sort(np.random.default_rng(seed).choice(L, sample, replace=False))
+    exp = brute_links(ex["child"], depth, ijk, leaves)
+    np.testing.assert_array_equal(got[leaves], exp)
+    return got
+
+
+def test_links_match_brute_force():
+    core = _core()
+    for s in (synth.sphere_scene(), synth.random_tree_scene(6, 1, seed=4, p_split=0.42),
+              synth.uniform_scene(3, 0, 2.0)):
+        tree = core.Octree.from_scene(s)
+        got = check_links(tree)
+        n_out = int((got == OUT).sum())
+        print(f"{s.n_leaves} leaves: {n_out} boundary faces, "
+              f"{int(((got & LEAF) != 0).sum()) - n_out} leaf links, {int(((got & LEAF) == 0).sum())} node links")
+        tree.close()
+
+
+def test_links_rebuilt_by_refine():
+    core = _core()
+    s = synth.sphere_scene()
+    tree = core.Octree.from_scene(s)
+    rng = np.random.default_rng(3)
+    sig = rng.uniform(0.0, 1.0, s.n_leaves).astype(np.float32)
+    sig[rng.random(s.n_leaves) < 0.5] = 1e-4
+    st = tree.refine(torch.as_tensor(sig, device="cuda"), prune_tau=1e-3, sample_frac=0.1, max_depth=7)
+    assert st["merged"] > 0 and st["subdivided"] > 0
+    check_links(tree)
+    tree.close()
+
+
+def test_links_toggle_and_root_leaf():
+    core = _core()
+    tree = core.Octree.from_scene(synth.sphere_scene())
+    assert tree.links_view() is not None
+    tree.set_links(False)
+    assert tree.links_view() is None
+    tree.set_links(True)
+    check_links(tree)
+    tree.close()
+    root = core.Octree.from_scene(synth.uniform_scene(0, 1, 3.0, sh_dc=0.7))
+    assert root.links_view() is None          # a root leaf has no faces inside the cube
+    root.close()
+
+
+def _pair(tree, fn):
+    tree.set_links(True)
+    a = fn()
+    tree.set_links(False)
+    b = fn()
+    tree.set_links(True)
+    return a, b
+
+
+def _render_all(tree, rays, **kw):
+    sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
+    rgb, ns = tree.render(rays, nseg=True, signal=sig, **kw)
+    torch.cuda.synchronize()
+    return rgb.cpu().numpy(), ns.cpu().numpy(), sig.cpu().numpy()
+
+
+def _assert_same(a, b):
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_renders_identical_with_and_without_links(storage):
+    core = _core()
+    o, d = _edge_rays()
+    for s in (synth.sphere_scene(), synth.random_tree_scene(6, 3, seed=0, p_split=0.42, sigma_max=20.0),
+              synth.uniform_scene(4, 2, 6.0, seed=3)):
+        tree = core.Octree.from_scene(s, storage)
+        for rays in (core.Rays.cameras(synth.sphere_camera()), core.Rays.explicit(o, d)):
+            for t_stop in (1e-4, 0.0):
+                _assert_same(*_pair(tree, lambda: _render_all(tree, rays, t_stop=t_stop)))
+        tree.close()
+
+
+def test_training_forward_identical_with_and_without_links():
+    core = _core()
+    s = synth.sphere_scene()
+    tree = core.Octree.from_scene(s)
+    views = synth.training_views(n=5)
+    ci, pi = synth.pixel_batch(5, 64, 64, 4000, seed=2)
+    rays = core.Rays.pixels(views, ci, pi)
+    rec = torch.empty(tree.records_bytes(rays.n_rays, 4), dtype=torch.uint8, device="cuda")
+
+    n = rays.n_rays
+    up = lambda b: (b + 255) // 256 * 256
+
+    def fwd():
+        sig = torch.zeros(tree.n_leaves, device="cuda")
+        rec.zero_()
+        rgb, ns, cnt = tree.render_train(rays, signal=sig, records=rec)
+        torch.cuda.synchronize()
+        r = rec.cpu().numpy()
+        # buffer: overflow count, per-ray record counts, overflow ray list (in
+        # arrival order: compared as a set), then the slot-major records
+        n_over = int(r[:4].view(np.uint32)[0])
+        counts = r[256:256 + 4 * n].view(np.int32)
+        o0 = 256 + up(4 * n)
+        olist = np.sort(r[o0:o0 + 4 * n_over].view(np.int32))
+        recs = r[o0 + up(4 * n):]
+        return (rgb.cpu().numpy(), ns.cpu().numpy(), cnt.cpu().numpy(), sig.cpu().numpy(), np.array([n_over]),
+                counts, olist, recs)
+
+    a, b = _pair(tree, fwd)
+    assert a[4][0] > 0          # some rays overflow the 4-record capacity
+    _assert_same(a, b)
+    tree.close()
+
+
+def test_torus_box_full_size_links():
+    """The 3.54M-leaf octree: sampled links against brute force, and the 8 x
+    800x800 render (FP32 and FP16) bit-identical with and without links."""
+    core = _core()
+    s = synth.torus_box_scene()
+    rays = core.Rays.cameras(synth.ring_cameras())
+    for storage in ("f32", "f16"):
+        tree = core.Octree.from_scene(s, storage)
+        if storage == "f32":
+            check_links(tree, sample=200_000)
+        _assert_same(*_pair(tree, lambda: _render_all(tree, rays)))
+        tree.close()
