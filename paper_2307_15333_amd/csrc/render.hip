@@ -328,10 +328,18 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
     if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) return;
     const float d[3] = {(float)r.dx, (float)r.dy, (float)r.dz};
     float S = 0.f, T = 1.f, P[3] = {0.f, 0.f, 0.f};
+    // record i + 1 is requested before record i's slot atomic and row store,
+    // so its load overlaps them instead of following them
+    float4 A = a.rec.a[rid];
+    float2 B = a.rec.b[rid];
     for (int i = 0; i < nrec; ++i) {
-        const int64_t j = (int64_t)i * a.rec.n + rid;
-        const float4 A = a.rec.a[j];
-        const float2 B = a.rec.b[j];
+        float4 An = A;
+        float2 Bn = B;
+        if (i + 1 < nrec) {
+            const int64_t jn = (int64_t)(i + 1) * a.rec.n + rid;
+            An = a.rec.a[jn];
+            Bn = a.rec.b[jn];
+        }
         const int leaf = __float_as_int(A.x);
         if ((uint64_t)(uint32_t)leaf >= (uint64_t)L) break;   // records of another tree: stop, stay in bounds
         const float delta = A.y, tau = A.z;
@@ -363,6 +371,8 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
         }
         S = Sn;
         T = Tn;
+        A = An;
+        B = Bn;
     }
 }
 
