@@ -454,11 +454,13 @@ __device__ __forceinline__ bool bucket_sum(int64_t l, const uint32_t* __restrict
     return true;
 }
 
-// Bucket reductions: one thread per leaf sums its bucket into registers, the
-// block stages the SH sums of its 256 leaves in LDS, then all threads walk the
-// block's contiguous range of the [L][3K] arrays so that loads and stores are
-// coalesced (a thread-per-leaf row of 3K floats would touch a new cache line
-// per lane and instruction).
+// Bucket reductions: one thread per leaf sums its bucket into registers, then
+// the block stages the SH sums of its 256 leaves in LDS one channel at a time
+// (K floats per leaf, padded to K + 1 against bank conflicts; 17 KB at degree
+// 3, so several blocks stay resident per CU) and all threads walk that
+// channel's columns of the block's leaves, so loads and stores are coalesced
+// in K-float runs (a thread-per-leaf row of 3K floats would touch a new cache
+// line per lane and instruction).
 constexpr int RED_BLOCK = 256;
 
 template <int DEG>
@@ -467,22 +469,28 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const 
                                                                const uint32_t* __restrict__ cursor,
                                                                const float* __restrict__ rows,
                                                                float* __restrict__ gsig, float* __restrict__ gsh) {
-    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
-    __shared__ float stage[RED_BLOCK * NV];
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int NV = 3 * K;
+    constexpr int KP = K + 1;
+    __shared__ float stage[RED_BLOCK * KP];
     const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
     const int64_t l = l0 + threadIdx.x;
     float gs = 0.f, acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.f;
     if (l < L && bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc)) gsig[l] += gs;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) stage[threadIdx.x * NV + j] = acc[j];
-    __syncthreads();
     const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
-    float* o = gsh + l0 * NV;
-    for (int i = threadIdx.x; i < nl * NV; i += RED_BLOCK) {
-        const float v = stage[i];
-        if (v != 0.f) o[i] += v;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        if (ch) __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) stage[threadIdx.x * KP + k] = acc[ch * K + k];
+        __syncthreads();
+        for (int i = threadIdx.x; i < nl * K; i += RED_BLOCK) {
+            const int r = i / K, k = i - r * K;
+            const float v = stage[r * KP + k];
+            if (v != 0.f) gsh[(l0 + r) * NV + ch * K + k] += v;
+        }
     }
 }
 
@@ -496,8 +504,10 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const
                                                                 float* __restrict__ sigma, float* __restrict__ sh,
                                                                 int stride, float* __restrict__ vs,
                                                                 float* __restrict__ vh, dot_rmsprop_params p) {
-    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
-    __shared__ float stage[RED_BLOCK * NV];
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int NV = 3 * K;
+    constexpr int KP = K + 1;
+    __shared__ float stage[RED_BLOCK * KP];
     const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
     const int64_t l = l0 + threadIdx.x;
     float gs = 0.f, acc[NV];
@@ -510,18 +520,23 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const
         sigma[l] = th;
         vs[l] = v;
     }
-#pragma unroll
-    for (int j = 0; j < NV; ++j) stage[threadIdx.x * NV + j] = acc[j];
-    __syncthreads();
     const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
-    for (int i = threadIdx.x; i < nl * NV; i += RED_BLOCK) {
-        const int64_t r = l0 + i / NV;
-        const int c = i % NV;
-        float* t = sh + r * stride + c;
-        float th = *t, v = vh[l0 * NV + i];
-        rmsprop_update(th, v, stage[i], p.lr_sh, p.alpha, p.eps);
-        *t = th;
-        vh[l0 * NV + i] = v;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        if (ch) __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) stage[threadIdx.x * KP + k] = acc[ch * K + k];
+        __syncthreads();
+        for (int i = threadIdx.x; i < nl * K; i += RED_BLOCK) {
+            const int r = i / K, k = i - r * K;
+            const int64_t col = (int64_t)ch * K + k;
+            float* t = sh + (l0 + r) * stride + col;
+            float* vp = vh + (l0 + r) * NV + col;
+            float th = *t, v = *vp;
+            rmsprop_update(th, v, stage[r * KP + k], p.lr_sh, p.alpha, p.eps);
+            *t = th;
+            *vp = v;
+        }
     }
 }
 

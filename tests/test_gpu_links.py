@@ -99,15 +99,32 @@ def test_links_match_brute_force():
         tree.close()
 
 
-def test_links_rebuilt_by_refine():
+@pytest.mark.parametrize("recursive", [False, True])
+def test_links_rebuilt_by_refine(recursive):
     core = _core()
     s = synth.sphere_scene()
     tree = core.Octree.from_scene(s)
     rng = np.random.default_rng(3)
-    sig = rng.uniform(0.0, 1.0, s.n_leaves).astype(np.float32)
-    sig[rng.random(s.n_leaves) < 0.5] = 1e-4
-    st = tree.refine(torch.as_tensor(sig, device="cuda"), prune_tau=1e-3, sample_frac=0.1, max_depth=7)
-    assert st["merged"] > 0 and st["subdivided"] > 0
+    for it in range(2):                       # the second pass refines an already refined tree
+        L = tree.n_leaves
+        sig = rng.uniform(0.0, 1.0, L).astype(np.float32)
+        sig[rng.random(L) < 0.5] = 1e-4
+        st = tree.refine(torch.as_tensor(sig, device="cuda"), prune_tau=1e-3, sample_frac=0.1, max_depth=7,
+                         recursive=recursive)
+        assert st["merged"] > 0 and st["subdivided"] > 0
+        check_links(tree)
+    tree.close()
+
+
+def test_links_stay_off_through_refine():
+    core = _core()
+    s = synth.sphere_scene()
+    tree = core.Octree.from_scene(s)
+    tree.set_links(False)
+    sig = torch.full((s.n_leaves,), 0.5, device="cuda")
+    tree.refine(sig, prune_tau=1e-3, sample_frac=0.05, max_depth=7)
+    assert tree.links_view() is None
+    tree.set_links(True)
     check_links(tree)
     tree.close()
 

@@ -132,6 +132,19 @@ def test_rmsprop_step_matches_oracle():
     tree.close()
 
 
+def assert_square_average(v, v_ref, g_ref, alpha, gtol=1e-5):
+    """RMSProp square average v = alpha v0 + (1 - alpha) g^2 against the FP64
+    reference.  The FP32 gradient is summed in bucket order, so its error is
+    bounded relative to the largest gradient (gtol, the adjoint tests' bound),
+    not to each element: a gradient formed by cancellation carries an absolute
+    error dg <= gtol max|g|, hence |dv| <= (1 - alpha)(2 |g| dg + dg^2), plus a
+    few FP32 roundings of v itself."""
+    dg = gtol * np.abs(g_ref).max()
+    bound = 1e-5 * np.abs(v_ref) + (1.0 - alpha) * (2.0 * np.abs(g_ref) * dg + dg * dg) + 1e-30
+    err = np.abs(np.asarray(v, np.float64) - v_ref)
+    assert np.all(err <= bound), float((err / bound).max())
+
+
 @pytest.mark.parametrize("degree", [0, 3])
 def test_fused_backward_rmsprop_matches_oracle(degree):
     """Adjoint + RMSProp in one call against the oracle's gradient followed by
@@ -159,8 +172,8 @@ def test_fused_backward_rmsprop_matches_oracle(degree):
     wh, vh = A.rmsprop(s.sh.astype(np.float64), gh, np.zeros_like(gh), 0.01, 0.99, 1e-4)
     np.testing.assert_allclose(ex["sigma"], ws, rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(ex["sh"], wh, rtol=1e-6, atol=1e-6)
-    np.testing.assert_allclose(st["v_sigma"].cpu().numpy(), vs, rtol=1e-4, atol=1e-18)
-    np.testing.assert_allclose(st["v_sh"].cpu().numpy(), vh, rtol=1e-4, atol=1e-18)
+    assert_square_average(st["v_sigma"].cpu().numpy(), vs, gs, 0.99)
+    assert_square_average(st["v_sh"].cpu().numpy(), vh, gh, 0.99)
     # an empty batch: g = 0 everywhere, values unchanged, averages decay by alpha
     v1 = st["v_sigma"].clone()
     empty = core.Rays.pixels(views, np.zeros(0, np.int32), np.zeros(0, np.int32))
