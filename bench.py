@@ -393,7 +393,7 @@ def serving(torch, core, synth, c2_scene, args):
     trees = [core.Octree.from_scene(x, "f16") for x in (s1a, s1b, c2_scene, s2b)]
     warm = 2.0
     reqs = serve.poisson_requests(4, rate=200.0, duration=warm + args.serve_seconds, seed=4)
-    srv = serve.Server(trees, out_budget_bytes=2 << 30, max_tiles=16384)
+    srv = serve.Server(trees, out_budget_bytes=2 << 30, max_tiles=65536)
     st = srv.run(reqs, warmup=warm)
     for t in trees:
         t.close()

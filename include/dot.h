@@ -454,7 +454,10 @@ size_t dot_render_jobs_workspace(int32_t n_jobs);
 
 /*
  * dot_render_jobs -- one persistent launch over all tiles of `jobs` (host
- *  array, read during the call).  `workspace` is a DEVICE buffer of at least
+ *  array, read during the call) per leaf storage type present among them
+ *  (usually one), each with the registers of its own type.  Tiles are handed
+ *  out in 8 contiguous chunks, one per XCD, with stealing between chunks.
+ *  `workspace` is a DEVICE buffer of at least
  *  dot_render_jobs_workspace(n_jobs) bytes owned by the caller; the call
  *  writes the job table into it on `stream`, so it may be reused by the next
  *  call on the same stream, but not concurrently on another stream.

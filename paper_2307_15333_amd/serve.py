@@ -16,6 +16,10 @@ iteration the server
   4. retires launches whose completion event has fired; a request completes
      with the launch that rendered its last tile, and frees its slot and budget.
 
+While work is queued or running the loop polls (no sleep), so completions and
+arrivals are seen within one event query; when idle it sleeps until `spin_s`
+before the next arrival.
+
 Latency = completion time - arrival time (host clock, event-polled).  The
 image a request receives is independent of the batch it was packed into: every
 pixel runs the same per-ray code on the same tree and camera.
@@ -62,8 +66,8 @@ class Request:
 
 
 class Server:
-    def __init__(self, trees, out_budget_bytes=2 << 30, max_active=64, max_tiles=8192, max_inflight=2,
-                 device="cuda"):
+    def __init__(self, trees, out_budget_bytes=2 << 30, max_active=64, max_tiles=65536, max_inflight=2,
+                 device="cuda", spin_s=3e-4):
         self.trees = trees
         self.lib = L.load()
         self.device = torch.device(device)
@@ -71,6 +75,7 @@ class Server:
         self.max_active = int(max_active)
         self.max_tiles = int(max_tiles)
         self.max_inflight = int(max_inflight)
+        self.spin_s = float(spin_s)
         self.used = 0
         self.max_used = 0
         self.ws_bytes = 0
@@ -174,13 +179,14 @@ class Server:
                         r.cam_dev = None
                     completed.append(r)
                 progressed = True
-            if not progressed:
-                if pending and not waiting and not active and not inflight:
-                    dt = pending[0].arrival - (time.perf_counter() - t0)
-                    if dt > 0:
-                        time.sleep(min(dt, 0.002))
-                else:
-                    time.sleep(0.00005)
+            if not progressed and pending and not waiting and not active and not inflight:
+                # idle: sleep until shortly before the next arrival (a sleep
+                # overshoots by tens of microseconds), then poll
+                dt = pending[0].arrival - (time.perf_counter() - t0)
+                if dt > self.spin_s:
+                    time.sleep(min(dt - self.spin_s, 0.002))
+            # with work queued or running the loop polls without sleeping, so a
+            # completion or an arrival is seen within one event query
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         meas = [r for r in completed if r.arrival >= warmup]
