@@ -124,3 +124,31 @@ def test_job_validation(trees):
     assert e.value.code == L.DOT_EINVAL and "tile range" in str(e.value)
     jobs = (L.dot_render_job * 1)()
     assert srv.lib.dot_render_jobs(jobs, 1, C.c_void_p(srv._workspace(1).data_ptr()), 16, None) == L.DOT_EINVAL
+
+
+def test_batch_mixing_storage_types():
+    """One batch over trees of all four storage types (one launch per type,
+    tiles of one image split and interleaved with the others): each image
+    equals dot_render's, and a one-tile batch (fewer workgroups than chunks)
+    completes too."""
+    core, serve = _mods()
+    s = synth.sphere_scene()
+    ts = [core.Octree.from_scene(s, st) for st in ("f32", "f16", "bf16", "f32")]
+    ts[3].quantize_sh(8)                                         # palette leaves
+    srv = serve.Server(ts)
+    reqs = [_req(serve, i, i, w, h, 70.0 * i, 15.0 - 10.0 * i)
+            for i, (w, h) in enumerate(((96, 80), (64, 64), (120, 72), (80, 96)))]
+    for r in reqs:
+        srv._admit(r, 0.0)
+    a, b, c, d = reqs
+    ha = a.n_tiles // 2
+    srv.launch([(a, ha, a.n_tiles - ha), (b, 0, b.n_tiles), (c, 0, c.n_tiles), (a, 0, ha), (d, 0, d.n_tiles)])
+    tiny = _req(serve, 9, 1, 8, 8, 5.0, 5.0)
+    srv._admit(tiny, 0.0)
+    srv.launch([(tiny, 0, 1)])
+    torch.cuda.synchronize()
+    for r in reqs + [tiny]:
+        ref = ts[r.tree].render(core.Rays.cameras(np.asarray(r.cam).reshape(1))).reshape(r.height, r.width, 3)
+        np.testing.assert_allclose(r.out.cpu().numpy(), ref.cpu().numpy(), atol=1e-6, rtol=0)
+    for t in ts:
+        t.close()
