@@ -316,7 +316,7 @@ int dot_adam_step(dot_tree_t tree, const float *grad_sigma, const float *grad_sh
 
 typedef struct {
     float lr_sigma, lr_sh;     /* learning rates (the paper: 0.1 for sigma, 0.01 for SH, Sec. 4.1) */
-    float alpha, eps;          /* square-average decay and denominator term */
+    float alpha, eps;          /* square-average decay in [0, 1) and denominator term (> 0, finite) */
 } dot_rmsprop_params;
 
 /*
@@ -325,7 +325,7 @@ typedef struct {
  *  theta -= lr g / (sqrt(v) + eps).  grad_*: DEVICE float, dense layouts as in
  *  dot_render_backward; v_*: DEVICE float square averages of the same shapes,
  *  zero-initialised by the caller.  FP32 storage only (DOT_EUNSUPPORTED
- *  otherwise).
+ *  otherwise); DOT_EINVAL for alpha outside [0, 1) or eps not positive.
  */
 int dot_rmsprop_step(dot_tree_t tree, const float *grad_sigma, const float *grad_sh, float *v_sigma,
                      float *v_sh, const dot_rmsprop_params *params, void *stream);

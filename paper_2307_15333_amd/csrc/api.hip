@@ -478,6 +478,8 @@ int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_re
         return fail(DOT_EUNSUPPORTED, "dot_render_backward_rmsprop: only FP32 leaf storage is trainable");
     if (!(params->alpha >= 0.f && params->alpha < 1.f))
         return fail(DOT_EINVAL, "dot_render_backward_rmsprop: alpha must be in [0, 1)");
+    if (!(params->eps > 0.f && params->eps < __builtin_huge_valf()))
+        return fail(DOT_EINVAL, "dot_render_backward_rmsprop: eps must be positive and finite");
     if (!v_sigma || !v_sh) return fail(DOT_EINVAL, "dot_render_backward_rmsprop: square-average buffers are required");
     RayBatch rb;
     int rc = make_batch(rays, rb, "dot_render_backward_rmsprop");
@@ -548,6 +550,8 @@ int dot_rmsprop_step(dot_tree_t t, const float* grad_sigma, const float* grad_sh
     if (!grad_sigma || !grad_sh || !v_sigma || !v_sh)
         return fail(DOT_EINVAL, "dot_rmsprop_step: gradient and square-average buffers are required");
     if (!(p->alpha >= 0.f && p->alpha < 1.f)) return fail(DOT_EINVAL, "dot_rmsprop_step: alpha must be in [0, 1)");
+    if (!(p->eps > 0.f && p->eps < __builtin_huge_valf()))
+        return fail(DOT_EINVAL, "dot_rmsprop_step: eps must be positive and finite");
     hipError_t e = launch_rmsprop(*t, grad_sigma, grad_sh, v_sigma, v_sh, *p, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_rmsprop_step: launch");
     return DOT_OK;

@@ -189,13 +189,22 @@ def test_rmsprop_rejects_bad_arguments():
     from paper_2307_15333_amd import _lib as L
     core = _core()
     s = synth.random_tree_scene(3, 1, seed=1)
-    for storage, kw, code in (("bf16", {}, L.DOT_EUNSUPPORTED), ("f32", {"alpha": 1.0}, L.DOT_EINVAL)):
+    for storage, kw, code in (("bf16", {}, L.DOT_EUNSUPPORTED), ("f32", {"alpha": 1.0}, L.DOT_EINVAL),
+                              ("f32", {"eps": 0.0}, L.DOT_EINVAL), ("f32", {"eps": float("inf")}, L.DOT_EINVAL)):
         tree = core.Octree.from_scene(s, storage)
         st = tree.rmsprop_state()
         with pytest.raises(L.DotError) as e:
             tree.rmsprop_step(torch.zeros(tree.n_leaves, device="cuda"),
                               torch.zeros((tree.n_leaves, 3, tree.K), device="cuda"), st, **kw)
         assert e.value.code == code
+        if storage == "f32":
+            # the fused adjoint + RMSProp checks the same parameters
+            views = synth.random_sphere_cameras(1, 3.5, 8, 8, seed=1)
+            empty = core.Rays.pixels(views, np.zeros(0, np.int32), np.zeros(0, np.int32))
+            z = torch.zeros((0, 3), device="cuda")
+            with pytest.raises(L.DotError) as e:
+                tree.backward_rmsprop(empty, z, torch.zeros(0, dtype=torch.int32, device="cuda"), z, st, **kw)
+            assert e.value.code == code
         tree.close()
 
 
