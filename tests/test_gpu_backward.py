@@ -225,3 +225,39 @@ def test_backward_replaying_forward_records(scene_kind, max_segments):
         tree.render_train(rays, records=rec[:1000])
     tree.close()
     t2.close()
+
+
+def test_backward_torus_box_full_size():
+    """The adjoint at the size the training loop runs it: the 3.54M-leaf
+    torus+box octree, a tile-ordered batch of 2^16 random pixels of 100 views
+    at 800x800 (dot_pixel_batch), the training forward with segment records and
+    the adjoint replaying them (rays past the record capacity re-traversed),
+    against the oracle's analytic gradient on the same rays (t_stop = 0)."""
+    core = _core()
+    s = synth.torus_box_scene()
+    views = synth.sphere_views(100)
+    W, H = int(views[0]["width"]), int(views[0]["height"])
+    ids = np.sort(np.random.default_rng(81).choice(len(views) * W * H, 1 << 16, replace=False)).astype(np.int64)
+    cam, pix, _, _ = core.pixel_batch(torch.as_tensor(ids, device="cuda"), W, H, len(views))
+    ci, pi = cam.cpu().numpy(), pix.cpu().numpy()
+    rays = core.Rays.pixels(views, ci, pi)
+    tree = core.Octree.from_scene(s)
+    # 48 records per ray: without early termination some rays cross more leaves
+    rec = torch.empty(core.Octree.records_bytes(ci.shape[0], 48), dtype=torch.uint8, device="cuda")
+    rgb, ns, cnt = tree.render_train(rays, t_stop=0.0, records=rec)
+    g = np.random.default_rng(82).normal(size=(ci.shape[0], 3)) * 1e-3
+    Ln, K = tree.n_leaves, tree.K
+    gs = torch.zeros(Ln, device="cuda")
+    gh = torch.zeros((Ln, 3, K), device="cuda")
+    tree.backward(rays, rgb, ns, torch.as_tensor(g, dtype=torch.float32, device="cuda"), gs, gh, t_stop=0.0,
+                  leaf_count=cnt, records=rec)
+    over = int(rec[:4].cpu().numpy().view(np.uint32)[0])
+    torch.cuda.synchronize()
+    o, d = O.camera_rays(views, ci, pi)
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    rs, rh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64), t_stop=0.0)
+    es, eh = _rel(gs.cpu().numpy(), rs), _rel(gh.cpu().numpy(), rh)
+    print(f"torus+box 2^16 rays: {over} rays re-traversed; grad_sigma rel {es:.3e}, grad_sh rel {eh:.3e}")
+    assert over > 0
+    assert es <= GTOL and eh <= GTOL
+    tree.close()
