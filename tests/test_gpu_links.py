@@ -164,13 +164,16 @@ def _assert_same(a, b):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "pal16"])
 def test_renders_identical_with_and_without_links(storage):
     core = _core()
     o, d = _edge_rays()
     for s in (synth.sphere_scene(), synth.random_tree_scene(6, 3, seed=0, p_split=0.42, sigma_max=20.0),
               synth.uniform_scene(4, 2, 6.0, seed=3)):
-        tree = core.Octree.from_scene(s, storage)
+        tree = core.Octree.from_scene(s, "f32" if storage == "pal16" else storage)
+        if storage == "pal16":
+            tree.quantize_sh(6)              # the palette keeps the tree's links
+            assert tree.links_view() is not None
         for rays in (core.Rays.cameras(synth.sphere_camera()), core.Rays.explicit(o, d)):
             for t_stop in (1e-4, 0.0):
                 _assert_same(*_pair(tree, lambda: _render_all(tree, rays, t_stop=t_stop)))
