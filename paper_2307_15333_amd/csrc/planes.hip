@@ -186,10 +186,16 @@ hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s) {
 // kernel of the same stream).
 __global__ void zero_f64_kernel(double* p) { *p = 0.0; }
 
-__global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
+// Each workgroup ends with one FP64 atomic on the single loss value, and those
+// atomics queue on one address, so the grid is kept to at most MSE_BLOCKS
+// large workgroups (a 2^20-ray batch: 256 atomics instead of 4096).
+constexpr int MSE_THREADS = 1024;
+constexpr int MSE_BLOCKS = 256;
+
+__global__ __launch_bounds__(MSE_THREADS) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
                                                   const int64_t* __restrict__ idx, int64_t n, double gscale,
                                                   float* __restrict__ grad, double* __restrict__ loss, double lscale) {
-    __shared__ double part[256 / WAVE];
+    __shared__ double part[MSE_THREADS / WAVE];
     double acc = 0.0;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t t = idx ? idx[r] : r;
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ pred
     __syncthreads();
     if (threadIdx.x == 0) {
         double b = 0.0;
-        for (int w = 0; w < 256 / WAVE; ++w) b += part[w];
+        for (int w = 0; w < MSE_THREADS / WAVE; ++w) b += part[w];
         atomicAdd(loss, b * lscale);
     }
 }
@@ -219,11 +225,11 @@ hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx
         if (e != hipSuccess) return e;
     }
     if (n == 0) return hipSuccess;
-    int64_t g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
+    int64_t g = (n + MSE_THREADS - 1) / MSE_THREADS;
+    if (g > MSE_BLOCKS) g = MSE_BLOCKS;
     const double gscale = 2.0 / (3.0 * (double)n);
-    hipLaunchKernelGGL(mse_kernel, dim3((unsigned)g), dim3(256), 0, s, pred, target, idx, n, gscale, grad, loss,
-                       1.0 / (3.0 * (double)n));
+    hipLaunchKernelGGL(mse_kernel, dim3((unsigned)g), dim3(MSE_THREADS), 0, s, pred, target, idx, n, gscale, grad,
+                       loss, 1.0 / (3.0 * (double)n));
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // Exclusive prefix scan of uint32 arrays: per-tile sums, a single-workgroup
-// scan of the tile sums, then a per-tile rescan with the tile's offset.
+// scan of the tile sums, then a per-tile rescan with the tile's offset; arrays
+// of up to 16 tiles are scanned by one workgroup in one launch.
 #include <hip/hip_runtime.h>
 
 #include "dot_internal.h"
@@ -84,12 +85,46 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const u
     }
 }
 
+// small arrays: one workgroup walks the tiles in order, carrying the running
+// total (one launch instead of three)
+constexpr int64_t SCAN_SINGLE_MAX = 16 * SCAN_TILE;
+
+__global__ void k_scan_single(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ out,
+                              uint32_t* __restrict__ tot) {
+    uint32_t carry = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+        const int64_t base = t0 + (int64_t)threadIdx.x * SCAN_ITEMS;
+        uint32_t v[SCAN_ITEMS];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            int64_t i = base + j;
+            v[j] = i < n ? in[i] : 0u;
+            acc += v[j];
+        }
+        uint32_t total;
+        uint32_t off = block_exclusive_scan(acc, total) + carry;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            int64_t i = base + j;
+            if (i < n) out[i] = off;
+            off += v[j];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) *tot = carry;
+}
+
 }  // namespace
 
 int64_t scan_scratch_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s) {
     if (n == 0) return hipSuccess;
+    if (n <= SCAN_SINGLE_MAX) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(TPB), 0, s, in, n, out, tot);
+        return hipGetLastError();
+    }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum);
     hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(TPB), 0, s, bsum, nb, tot);
