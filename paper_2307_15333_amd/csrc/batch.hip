@@ -75,7 +75,7 @@ __global__ void k_pb_scatter(const int64_t* __restrict__ ids, int64_t n, PixelGe
 // Few bins: every workgroup counts (and ranks) its chunk of rays in LDS, so a
 // bin takes one global atomic per workgroup instead of one per ray.
 constexpr int LDS_BINS = 4096;
-constexpr int ITEMS = 16;               // rays per thread
+constexpr int ITEMS = 4;                // rays per thread
 constexpr int CHUNK = 256 * ITEMS;      // rays per workgroup
 
 __global__ __launch_bounds__(256) void k_pb_count_lds(const int64_t* __restrict__ ids, int64_t n, PixelGeo g,
