@@ -201,18 +201,22 @@ int dot_render(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opt
 
 /*
  * dot_render_train -- the forward pass of a training step: dot_render with
- *  nseg_out required, plus leaf_count_out: DEVICE uint32 [n_leaves],
+ *  nseg_out required, plus leaf_count_out: DEVICE uint32 [2][n_leaves],
  *  overwritten with, per leaf, the number of this batch's segments whose
- *  leaf has sigma > 0 -- the segments whose gradient rows the adjoint emits.
- *  Given to dot_render_backward / dot_render_backward_rmsprop with the same
- *  tree, rays and opts, it lets the adjoint skip its own counting traversal.
+ *  leaf has sigma > 0 -- the segments whose gradient rows the adjoint emits --
+ *  split into [0][l] the segments recorded (below) and [1][l] the others
+ *  (all of them when records is NULL).  Given to dot_render_backward /
+ *  dot_render_backward_rmsprop with the same tree, rays and opts, it lets the
+ *  adjoint skip its own counting traversal.
  *  records: DEVICE buffer or NULL.  When given, the forward also records each
  *  ray's first `max_segments` segments whose leaf has sigma > 0 (leaf, delta,
- *  optical depth and colour; 24 bytes each), max_segments being the largest
- *  count for which dot_render_train_records_bytes(n_rays, max_segments) fits
- *  in records_bytes (at most 1024).  The adjoint then replays them instead of
- *  traversing the tree and fetching the leaves again, and re-traverses only
- *  the rays that had more.  The layout is private to the library; the buffer
+ *  optical depth, colour and the slot its gradient row will take in the
+ *  leaf's bucket, reserved here; 28 bytes each), max_segments being the
+ *  largest count for which dot_render_train_records_bytes(n_rays,
+ *  max_segments) fits in records_bytes (at most 1024).  The adjoint then
+ *  replays them instead of traversing the tree and fetching the leaves again,
+ *  without atomics, and re-traverses only the rays that had more, for their
+ *  remaining segments.  The layout is private to the library; the buffer
  *  stays the caller's.
  *  FP32 storage only (DOT_EUNSUPPORTED otherwise); DOT_EINVAL on a records
  *  buffer too small for one segment per ray.
@@ -248,11 +252,12 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  once to size it; beyond 8 GiB of
  *  scratch, or if it cannot be allocated, the terms go straight to the
  *  arrays with FP32 atomics.  Summation order, hence the last bits, depends
- *  on scheduling.  leaf_count: NULL, or the counts dot_render_train wrote
- *  for the same tree, rays and opts (the counting traversal is then skipped;
- *  counts from another batch give wrong gradients, never an access outside
- *  the buffers).  records: NULL, or the records that same dot_render_train
- *  call wrote (requires leaf_count; `records_bytes` as given to it).
+ *  on scheduling.  leaf_count: NULL, or the [2][n_leaves] counts
+ *  dot_render_train wrote for the same tree, rays and opts (the counting
+ *  traversal is then skipped; counts or records from another batch give wrong
+ *  gradients, never an access outside the buffers).  records: NULL, or the
+ *  records that same dot_render_train call wrote (requires leaf_count;
+ *  `records_bytes` as given to it).
  */
 int dot_render_backward(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                         const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,

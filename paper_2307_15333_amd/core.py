@@ -195,12 +195,13 @@ class Octree:
 
     def render_train(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max", leaf_count=None,
                      records=None):
-        """Training forward: (rgb, nseg, leaf_count) -- leaf_count feeds the adjoint's buckets; `records`
-        (uint8 device buffer of records_bytes(n) bytes, or None) receives the segments the adjoint replays."""
+        """Training forward: (rgb, nseg, leaf_count) -- leaf_count ([2, L]: recorded and other segments per
+        leaf) feeds the adjoint's buckets; `records` (uint8 device buffer of records_bytes(n) bytes, or None)
+        receives the segments the adjoint replays."""
         rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device=self.device)
         ns = torch.empty(rays.n_rays, dtype=torch.int32, device=self.device)
-        if leaf_count is None or leaf_count.numel() < self.n_leaves:
-            leaf_count = torch.empty(self.n_leaves, dtype=torch.int32, device=self.device)
+        if leaf_count is None or leaf_count.numel() < 2 * self.n_leaves:
+            leaf_count = torch.empty((2, self.n_leaves), dtype=torch.int32, device=self.device)
         op = render_opts(bg, t_stop, signal_mode)
         L.check(self.lib.dot_render_train(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb), _ptr(ns),
                                           _ptr(signal), _ptr(leaf_count), _ptr(records),

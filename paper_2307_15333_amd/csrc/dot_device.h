@@ -390,8 +390,17 @@ struct FwdSeg {
     int fetched = 0;
     int64_t rid = 0;    // COUNT: the ray's index in the batch (record column)
     int nrec = 0;       // COUNT: composited segments recorded so far
+    // COUNT: the last record's bucket slot is stored with the next record (or
+    // at the end of the ray), so the forward never waits for the atomic
+    int64_t pend_j = -1;
+    uint32_t pend_slot = 0;
 
     __device__ FwdSeg(const TreeView& tv_, const FwdArgs& a_) : tv(tv_), a(a_) {}
+
+    __device__ __forceinline__ void flush_slot() {
+        if constexpr (COUNT)
+            if (pend_j >= 0) a.rec.slot[pend_j] = pend_slot;
+    }
 
     __device__ __forceinline__ bool operator()(int leaf, float delta) {
         // sigma and the SH row are requested together (one memory round trip);
@@ -425,9 +434,6 @@ struct FwdSeg {
         float tau = sg * delta;
         ++n;
         fetched += tau > 0.f;
-        // a training forward counts, per leaf, the segments its adjoint will emit
-        if constexpr (COUNT)
-            if (sg > 0.f) atomicAdd(&a.leaf_count[leaf], 1u);
         {
             float Sn = S + tau;
             float Tn = __expf(-Sn);
@@ -451,15 +457,23 @@ struct FwdSeg {
                 cv[ch] = sigmoidf_(x);
                 C[ch] = fmaf(w, cv[ch], C[ch]);
             }
-            // the record the adjoint replays: leaf, delta, tau and the colour
+            // a training forward counts, per leaf, the segments whose gradient
+            // rows its adjoint emits; a recorded segment (leaf, delta, tau and
+            // the colour) also reserves its row's bucket slot here
             if constexpr (COUNT) {
-                if (sg > 0.f && a.rec.a) {
-                    if (nrec < a.rec.cap) {
+                if (sg > 0.f) {
+                    if (a.rec.a && nrec < a.rec.cap) {
+                        const uint32_t slot = atomicAdd(&a.leaf_count[leaf], 1u);
                         const int64_t j = (int64_t)nrec * a.rec.n + rid;
                         a.rec.a[j] = make_float4(__int_as_float(leaf), delta, tau, cv[0]);
                         a.rec.b[j] = make_float2(cv[1], cv[2]);
+                        flush_slot();
+                        pend_j = j;
+                        pend_slot = slot;
+                    } else {
+                        atomicAdd(&a.leaf_rest[leaf], 1u);
                     }
-                    ++nrec;
+                    if (a.rec.a) ++nrec;
                 }
             }
             if (a.signal) {

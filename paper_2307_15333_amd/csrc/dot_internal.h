@@ -125,13 +125,20 @@ struct RayBatch {
 
 // Segment records of a training forward, replayed by the adjoint instead of a
 // second traversal: per ray up to `cap` composited segments (sigma > 0), slot
-// major ([slot][ray]) so one step's writes and reads are coalesced.  A ray
-// with more records keeps only its count and is replayed by traversal.  The
-// buffer's size sets `cap`.
+// major ([slot][ray]) so one step's writes and reads are coalesced, each with
+// the bucket slot the forward reserved for its gradient row.  A ray with more
+// segments is listed; the adjoint replays its first `cap` and re-traverses it
+// for the rest.  The buffer's size sets `cap`.
+//
+// Per-leaf counts of a training forward (uint32 [2][L]): [0][l] the recorded
+// segments of leaf l (their rows take bucket slots 0 .. [0][l] - 1, reserved
+// by the forward), [1][l] the other segments with sigma > 0 (slots after
+// those, taken in the adjoint).  Bucket l holds [0][l] + [1][l] rows.
 constexpr int SEG_CAP_MAX = 1024;
 struct SegRecords {
     float4* a = nullptr;          // [cap][n]: leaf id bits, delta, tau, c0
     float2* b = nullptr;          // [cap][n]: c1, c2
+    uint32_t* slot = nullptr;     // [cap][n]: bucket slot of the record's row
     int32_t* count = nullptr;     // [n]: records of the ray
     uint32_t* overflow = nullptr; // [1]: rays with more than `cap` records
     int32_t* olist = nullptr;     // [n]: ids of those rays (first `overflow` entries)
@@ -150,7 +157,8 @@ struct FwdArgs {
     float bg[3];
     float thr;          // -ln(t_stop), +inf when disabled
     unsigned long long* stats;  // may be null
-    uint32_t* leaf_count;       // may be null: per leaf, the segments with sigma > 0 (for the adjoint)
+    uint32_t* leaf_count;       // may be null: [2][L] per-leaf segment counts (recorded, other) for the adjoint
+    uint32_t* leaf_rest;        // leaf_count + L
     SegRecords rec;             // training forward: segment records (a == null: none)
 };
 
@@ -161,7 +169,7 @@ struct BwdArgs {
     float* grad_sigma;
     float* grad_sh;
     float thr;
-    // per-leaf contributing-segment counts from the forward pass, or null (counted here)
+    // per-leaf segment counts [2][L] from the training forward, or null (counted here)
     const uint32_t* leaf_count;
     // the forward's segment records (a == null: replay by traversal)
     SegRecords rec;

@@ -27,6 +27,7 @@ __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(TreeView tv, RayBatch
     traverse(tv, r, &stack_lds[tid], seg, desc);
     if constexpr (MODE == 2) {
         if (a.rec.a) {
+            seg.flush_slot();
             a.rec.count[rid] = seg.nrec;
             if (seg.nrec > a.rec.cap) a.rec.olist[atomicAdd(a.rec.overflow, 1u)] = (int32_t)rid;
         }
@@ -133,8 +134,11 @@ __global__ __launch_bounds__(BLOCK) void render_bwd_kernel(TreeView tv, RayBatch
 // segment's 1 + 3K gradient terms with float atomics serialises on the hot
 // leaves.  Instead: (1) count the contributing segments of every leaf, (2)
 // scan the counts into bucket offsets, (3) write each segment's gradient row
-// into its leaf's bucket (one integer atomic per segment picks the slot), and
-// (4) reduce every bucket into the gradient arrays.  The SH gradient of a
+// into its leaf's bucket, and (4) reduce every bucket into the gradient
+// arrays.  A bucket has two regions: the rows of the segments a training
+// forward recorded, at the slots the forward reserved (replayed without
+// atomics), then the rows of the other segments, whose slots an integer
+// atomic on the leaf's cursor picks as they are emitted.  The SH gradient of a
 // segment is the outer product a_ch Y_k(d) with a_ch = g_ch w c_ch (1 - c_ch),
 // so a row stores dsigma, a[3] and the ray direction (8 floats; 4 at degree 0,
 // where Y is constant) and the reduction re-evaluates Y(d) -- 32 B per segment
@@ -158,13 +162,18 @@ template <int DEG>
 constexpr int bwd_row_floats() { return DEG == 0 ? 4 : 8; }
 inline int bwd_row_floats_rt(int deg) { return deg == 0 ? 4 : 8; }
 
+// Emits the rows of the segments in the second region of their buckets:
+// slot = base0[leaf] (recorded rows, or none) + the cursor's count.  The first
+// `skip` contributing segments of the ray (the recorded ones) only advance the
+// prefix sums.
 template <int DT, int DEG>
 struct BwdEmit {
     static constexpr int K = (DEG + 1) * (DEG + 1);
     static constexpr int RS = bwd_row_floats<DEG>();
     const TreeView& tv;
     const uint32_t* offset;
-    const uint32_t* count;
+    const uint32_t* base0;    // [L] rows of the recorded region, or null
+    const uint32_t* count;    // [L] rows of the second region
     uint32_t* cursor;
     float* rows;
     float Y[K];
@@ -173,14 +182,33 @@ struct BwdEmit {
     float C[3], g[3];
     float P[3] = {0.f, 0.f, 0.f};
     int n = 0, limit = 0;
+    int skip = 0;             // contributing segments not to emit
 
-    __device__ BwdEmit(const TreeView& tv_, const uint32_t* o, const uint32_t* n_, uint32_t* c, float* r)
-        : tv(tv_), offset(o), count(n_), cursor(c), rows(r) {}
+    __device__ BwdEmit(const TreeView& tv_, const uint32_t* o, const uint32_t* b0, const uint32_t* n_, uint32_t* c,
+                       float* r)
+        : tv(tv_), offset(o), base0(b0), count(n_), cursor(c), rows(r) {}
 
     __device__ __forceinline__ bool operator()(int leaf, float delta) {
         ++n;
         float sraw = load_sigma<DT>(tv.sigma, leaf);
-        if (sraw > 0.f) {
+        if (sraw > 0.f && skip > 0) {
+            // a recorded segment: its row comes from the replay
+            --skip;
+            const float Sn = S + sraw * delta;
+            const float Tn = __expf(-Sn);
+            const float w = fmaxf(T - Tn, 0.f);
+            float row[3 * K];
+            load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float x = 0.f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) x = fmaf(row[ch * K + k], Y[k], x);
+                P[ch] = fmaf(w, sigmoidf_(x), P[ch]);
+            }
+            S = Sn;
+            T = Tn;
+        } else if (sraw > 0.f) {
             float tau = sraw * delta;
             float Sn = S + tau;
             float Tn = __expf(-Sn);
@@ -211,11 +239,12 @@ struct BwdEmit {
                 out[6] = d[2];
                 out[7] = 0.f;
             }
-            // the bucket holds exactly the segments the counting pass found; a
-            // slot past it is never written (the reduction reads written rows only)
+            // the region holds exactly the segments the counting found; a slot
+            // past it is never written (the reduction reads written rows only)
             uint32_t k = atomicAdd(&cursor[leaf], 1u);
             if (k < count[leaf]) {
-                float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)offset[leaf] + k) * RS);
+                const uint32_t b = base0 ? base0[leaf] : 0u;
+                float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)offset[leaf] + b + k) * RS);
 #pragma unroll
                 for (int j = 0; j < RS / 4; ++j)
                     dst[j] = make_float4(out[4 * j], out[4 * j + 1], out[4 * j + 2], out[4 * j + 3]);
@@ -247,7 +276,8 @@ __global__ __launch_bounds__(BLOCK) void bwd_count_kernel(TreeView tv, RayBatch 
 
 template <int DT, int DEG>
 __global__ __launch_bounds__(BLOCK) void bwd_emit_kernel(TreeView tv, RayBatch rb, BwdArgs a, const uint32_t* offset,
-                                                         const uint32_t* count, uint32_t* cursor, float* rows) {
+                                                         const uint32_t* base0, const uint32_t* count, uint32_t* cursor,
+                                                         float* rows) {
     __shared__ int stack_lds[LAT * BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
@@ -256,7 +286,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_kernel(TreeView tv, RayBatch r
     Ray r;
     int64_t rid;
     if (!make_ray(rb, tile, lane, r, rid)) return;
-    BwdEmit<DT, DEG> seg(tv, offset, count, cursor, rows);
+    BwdEmit<DT, DEG> seg(tv, offset, base0, count, cursor, rows);
     seg.limit = a.nseg[rid];
     if (seg.limit <= 0) return;
 #pragma unroll
@@ -273,12 +303,14 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_kernel(TreeView tv, RayBatch r
     traverse(tv, r, &stack_lds[tid], seg, desc);
 }
 
-// Re-traversal of the rays whose records overflowed (their ids listed by the
-// forward): one ray per lane, in list order.
+// Re-traversal of the rays with more segments than the records hold (their
+// ids listed by the forward), one ray per lane: the recorded first `cap`
+// contributing segments only advance the prefix sums, the rest are emitted.
 template <int DT, int DEG>
 __global__ __launch_bounds__(BLOCK) void bwd_emit_list_kernel(TreeView tv, RayBatch rb, BwdArgs a, const int32_t* list,
                                                               int64_t nlist, const uint32_t* offset,
-                                                              const uint32_t* count, uint32_t* cursor, float* rows) {
+                                                              const uint32_t* base0, const uint32_t* count,
+                                                              uint32_t* cursor, float* rows) {
     __shared__ int stack_lds[LAT * BLOCK];
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * BLOCK + tid;
@@ -286,8 +318,9 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_list_kernel(TreeView tv, RayBa
     const int64_t rid = list[i];
     if (rid < 0 || rid >= rb.n_rays) return;
     Ray r = ray_of(rb, rid);
-    BwdEmit<DT, DEG> seg(tv, offset, count, cursor, rows);
+    BwdEmit<DT, DEG> seg(tv, offset, base0, count, cursor, rows);
     seg.limit = a.nseg[rid];
+    seg.skip = a.rec.cap;
     if (seg.limit <= 0) return;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -303,12 +336,16 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_list_kernel(TreeView tv, RayBa
     traverse(tv, r, &stack_lds[tid], seg, desc);
 }
 
-// Replay of the forward's segment records (rays with at most `cap` of them):
-// the same per-segment arithmetic as BwdEmit, without the traversal and the
-// leaf fetches.  Same ray-to-lane mapping as the traversal kernels.
+// Replay of the forward's segment records (of every ray, the first `cap` of
+// a ray with more): the same per-segment arithmetic as BwdEmit, without the
+// traversal and the leaf fetches, each row stored at the slot the forward
+// reserved.  Every record's row is written (zero for a ray with g = 0), since
+// the recorded region of a bucket has no cursor.  The next record and its
+// leaf's bucket offset are requested one record ahead, so the stores do not
+// wait on them.  Same ray-to-lane mapping as the traversal kernels.
 template <int DEG>
 __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArgs a, int64_t L, const uint32_t* offset,
-                                                             const uint32_t* count, uint32_t* cursor, float* rows) {
+                                                             const uint32_t* base0, float* rows) {
     constexpr int RS = bwd_row_floats<DEG>();
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
@@ -317,33 +354,56 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
     Ray r;
     int64_t rid;
     if (!make_ray(rb, tile, lane, r, rid)) return;
-    const int nrec = a.rec.count[rid];
-    if (nrec <= 0 || nrec > a.rec.cap) return;
+    int nrec = a.rec.count[rid];
+    if (nrec <= 0) return;
+    if (nrec > a.rec.cap) nrec = a.rec.cap;
     float g[3], C[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         C[ch] = a.rgb_fwd[3 * rid + ch];
         g[ch] = a.grad_rgb[3 * rid + ch];
     }
-    if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) return;
     const float d[3] = {(float)r.dx, (float)r.dy, (float)r.dz};
     float S = 0.f, T = 1.f, P[3] = {0.f, 0.f, 0.f};
-    // record i + 1 is requested before record i's slot atomic and row store,
-    // so its load overlaps them instead of following them
-    float4 A = a.rec.a[rid];
-    float2 B = a.rec.b[rid];
-    for (int i = 0; i < nrec; ++i) {
-        float4 An = A;
-        float2 Bn = B;
+    auto load_rec = [&](int i, float4& A_, float2& B_, uint32_t& s_) {
+        const int64_t j = (int64_t)i * a.rec.n + rid;
+        A_ = a.rec.a[j];
+        B_ = a.rec.b[j];
+        s_ = a.rec.slot[j];
+    };
+    // record i (with its bucket offset and recorded-region size), record i + 1
+    float4 A0, A1;
+    float2 B0, B1;
+    uint32_t s0 = 0, s1 = 0;
+    load_rec(0, A0, B0, s0);
+    A1 = A0;
+    B1 = B0;
+    if (nrec > 1) load_rec(1, A1, B1, s1);
+    int leaf0 = __float_as_int(A0.x);
+    bool ok0 = (uint64_t)(uint32_t)leaf0 < (uint64_t)L;   // records of another tree: stop, stay in bounds
+    uint32_t off0 = 0, lim0 = 0;
+    if (ok0) {
+        off0 = offset[leaf0];
+        lim0 = base0[leaf0];
+    }
+    for (int i = 0; i < nrec && ok0; ++i) {
+        // record i + 1's bucket data and record i + 2 are requested first
+        bool ok1 = false;
+        uint32_t off1 = 0, lim1 = 0;
+        float4 A2 = A1;
+        float2 B2 = B1;
+        uint32_t s2 = s1;
         if (i + 1 < nrec) {
-            const int64_t jn = (int64_t)(i + 1) * a.rec.n + rid;
-            An = a.rec.a[jn];
-            Bn = a.rec.b[jn];
+            const int leaf1 = __float_as_int(A1.x);
+            ok1 = (uint64_t)(uint32_t)leaf1 < (uint64_t)L;
+            if (ok1) {
+                off1 = offset[leaf1];
+                lim1 = base0[leaf1];
+            }
+            if (i + 2 < nrec) load_rec(i + 2, A2, B2, s2);
         }
-        const int leaf = __float_as_int(A.x);
-        if ((uint64_t)(uint32_t)leaf >= (uint64_t)L) break;   // records of another tree: stop, stay in bounds
-        const float delta = A.y, tau = A.z;
-        const float c[3] = {A.w, B.x, B.y};
+        const float delta = A0.y, tau = A0.z;
+        const float c[3] = {A0.w, B0.x, B0.y};
         const float Sn = S + tau;
         const float Tn = __expf(-Sn);
         const float w = fmaxf(T - Tn, 0.f);
@@ -363,23 +423,30 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
             out[6] = d[2];
             out[7] = 0.f;
         }
-        const uint32_t k = atomicAdd(&cursor[leaf], 1u);
-        if (k < count[leaf]) {
-            float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)offset[leaf] + k) * RS);
+        if (s0 < lim0) {
+            float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)off0 + s0) * RS);
 #pragma unroll
             for (int q = 0; q < RS / 4; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
         }
         S = Sn;
         T = Tn;
-        A = An;
-        B = Bn;
+        A0 = A1;
+        B0 = B1;
+        s0 = s1;
+        ok0 = ok1;
+        off0 = off1;
+        lim0 = lim1;
+        A1 = A2;
+        B1 = B2;
+        s1 = s2;
     }
 }
 
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t seg_records_bytes(int64_t n, int cap) {
-    return 256 + 2 * up256((size_t)n * 4) + up256((size_t)cap * n * 16) + up256((size_t)cap * n * 8);
+    return 256 + 2 * up256((size_t)n * 4) + up256((size_t)cap * n * 16) + up256((size_t)cap * n * 8) +
+           up256((size_t)cap * n * 4);
 }
 
 SegRecords seg_records_view(void* base, int64_t n, size_t bytes) {
@@ -403,19 +470,30 @@ SegRecords seg_records_view(void* base, int64_t n, size_t bytes) {
     r.a = reinterpret_cast<float4*>(p);
     p += up256((size_t)cap * n * 16);
     r.b = reinterpret_cast<float2*>(p);
+    p += up256((size_t)cap * n * 8);
+    r.slot = reinterpret_cast<uint32_t*>(p);
     r.n = n;
     r.cap = cap;
     return r;
 }
 
+// Rows of leaf l's bucket: the recorded region (base0, or none), then the rows
+// the second region's cursor handed out (never more than it holds).
+__device__ __forceinline__ uint32_t bucket_rows(int64_t l, const uint32_t* __restrict__ base0,
+                                                const uint32_t* __restrict__ count,
+                                                const uint32_t* __restrict__ cursor) {
+    return (base0 ? base0[l] : 0u) + min(count[l], cursor[l]);
+}
+
 // Sum of one leaf's bucket: dsigma and, per channel, sum_rows a_ch Y_k(d_row).
 template <int DEG>
 __device__ __forceinline__ bool bucket_sum(int64_t l, const uint32_t* __restrict__ offset,
-                                           const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor,
-                                           const float* __restrict__ rows, float& gs, float* acc) {
+                                           const uint32_t* __restrict__ base0, const uint32_t* __restrict__ count,
+                                           const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
+                                           float& gs, float* acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int RS = bwd_row_floats<DEG>();
-    const uint32_t m = min(count[l], cursor[l]);
+    const uint32_t m = bucket_rows(l, base0, count, cursor);
     gs = 0.f;
 #pragma unroll
     for (int j = 0; j < 3 * K; ++j) acc[j] = 0.f;
@@ -465,6 +543,7 @@ constexpr int RED_BLOCK = 256;
 
 template <int DEG>
 __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const uint32_t* __restrict__ offset,
+                                                               const uint32_t* __restrict__ base0,
                                                                const uint32_t* __restrict__ count,
                                                                const uint32_t* __restrict__ cursor,
                                                                const float* __restrict__ rows,
@@ -478,7 +557,7 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const 
     float gs = 0.f, acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.f;
-    if (l < L && bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc)) gsig[l] += gs;
+    if (l < L && bucket_sum<DEG>(l, offset, base0, count, cursor, rows, gs, acc)) gsig[l] += gs;
     const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -498,6 +577,7 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const 
 // g = 0: their square averages decay, their values stay).
 template <int DEG>
 __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const uint32_t* __restrict__ offset,
+                                                                const uint32_t* __restrict__ base0,
                                                                 const uint32_t* __restrict__ count,
                                                                 const uint32_t* __restrict__ cursor,
                                                                 const float* __restrict__ rows,
@@ -514,7 +594,7 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.f;
     if (l < L) {
-        bucket_sum<DEG>(l, offset, count, cursor, rows, gs, acc);
+        bucket_sum<DEG>(l, offset, base0, count, cursor, rows, gs, acc);
         float th = sigma[l], v = vs[l];
         rmsprop_update(th, v, gs, p.lr_sigma, p.alpha, p.eps);
         sigma[l] = th;
@@ -546,8 +626,9 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const
 // RMSProp to every leaf, otherwise the sums are added to the gradient arrays.
 template <int DEG, bool FUSED>
 __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
-    int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ count,
-    const uint32_t* __restrict__ cursor, const float* __restrict__ rows, float* __restrict__ gsig,
+    int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ base0,
+    const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
+    float* __restrict__ gsig,
     float* __restrict__ gsh, float* __restrict__ sigma, float* __restrict__ sh, int stride, float* __restrict__ vs,
     float* __restrict__ vh, dot_rmsprop_params p) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -558,7 +639,7 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     for (int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; l < L; l += nw) {
-        const uint32_t m = min(count[l], cursor[l]);
+        const uint32_t m = bucket_rows(l, base0, count, cursor);
         const float4* p4 = reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS);
         float gs = 0.f, acc[NV];
 #pragma unroll
@@ -611,17 +692,18 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
 
 template <int DEG>
 static void launch_reduce_wave(const dot_tree& t, const BwdArgs& a, bool fused, const uint32_t* offset,
-                               const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
+                               const uint32_t* base0, const uint32_t* count, const uint32_t* cursor,
+                               const float* rows, hipStream_t s) {
     const int64_t L = t.n_leaves;
     const unsigned g = (unsigned)std::min<int64_t>((L + RED_BLOCK / WAVE - 1) / (RED_BLOCK / WAVE), 1 << 16);
     const dot_rmsprop_params p = fused ? *a.rms : dot_rmsprop_params{};
     if (fused)
-        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, true>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, count, cursor,
-                           rows, nullptr, nullptr, static_cast<float*>(t.sigma), static_cast<float*>(t.sh),
+        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, true>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0, count,
+                           cursor, rows, nullptr, nullptr, static_cast<float*>(t.sigma), static_cast<float*>(t.sh),
                            t.sh_stride, a.v_sigma, a.v_sh, p);
     else
-        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, false>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, count,
-                           cursor, rows, a.grad_sigma, a.grad_sh, nullptr, nullptr, 0, nullptr, nullptr, p);
+        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, false>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0,
+                           count, cursor, rows, a.grad_sigma, a.grad_sh, nullptr, nullptr, 0, nullptr, nullptr, p);
 }
 
 // buckets holding at least this many rows on average are reduced a wave per leaf
@@ -700,13 +782,20 @@ static hipError_t bwd_atomic(const dot_tree& t, const RayBatch& rb, const BwdArg
 
 template <int DT>
 static void launch_emit(int deg, const TreeView& tv, const RayBatch& rb, const BwdArgs& a, const uint32_t* off,
-                        const uint32_t* cnt, uint32_t* cur, float* rows, dim3 grid, hipStream_t s) {
+                        const uint32_t* b0, const uint32_t* cnt, uint32_t* cur, float* rows, dim3 grid, hipStream_t s) {
     switch (deg) {
-        case 0: hipLaunchKernelGGL((bwd_emit_kernel<DT, 0>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
-        case 1: hipLaunchKernelGGL((bwd_emit_kernel<DT, 1>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
-        case 2: hipLaunchKernelGGL((bwd_emit_kernel<DT, 2>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
-        default: hipLaunchKernelGGL((bwd_emit_kernel<DT, 3>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, cnt, cur, rows); break;
+        case 0: hipLaunchKernelGGL((bwd_emit_kernel<DT, 0>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, b0, cnt, cur, rows); break;
+        case 1: hipLaunchKernelGGL((bwd_emit_kernel<DT, 1>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, b0, cnt, cur, rows); break;
+        case 2: hipLaunchKernelGGL((bwd_emit_kernel<DT, 2>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, b0, cnt, cur, rows); break;
+        default: hipLaunchKernelGGL((bwd_emit_kernel<DT, 3>), grid, dim3(BLOCK), 0, s, tv, rb, a, off, b0, cnt, cur, rows); break;
     }
+}
+
+// c = a + b elementwise (a bucket's two regions)
+__global__ void add_u32_kernel(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint32_t* __restrict__ c,
+                               int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c[i] = a[i] + b[i];
 }
 
 // bucket scratch beyond this many bytes falls back to the atomic adjoint
@@ -739,11 +828,11 @@ static hipError_t bwd_rmsprop_dense(const dot_tree& t, const RayBatch& rb, const
 }
 
 template <int DEG>
-static void launch_bwd_rmsprop(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* count,
-                               const uint32_t* cursor, const float* rows, hipStream_t s) {
+static void launch_bwd_rmsprop(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
+                               const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
     const int64_t L = t.n_leaves;
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
-    hipLaunchKernelGGL(bwd_rmsprop_kernel<DEG>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows,
+    hipLaunchKernelGGL(bwd_rmsprop_kernel<DEG>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows,
                        static_cast<float*>(t.sigma), static_cast<float*>(t.sh), t.sh_stride, a.v_sigma, a.v_sh,
                        *a.rms);
 }
@@ -758,35 +847,42 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     const int64_t L = t.n_leaves;
     const int rs = bwd_row_floats_rt(t.degree);
     TreeView tv = t.view();
-    // the forward's counts when given, else our own (filled by the counting pass)
+    // Bucket regions: with the training forward's counts, base0 = its recorded
+    // counts and count = its other counts; else no recorded region and count =
+    // our own counting pass.  `total` = base0 + count feeds the scan.
+    const uint32_t* base0 = a.leaf_count;
     uint32_t* count_own = a.leaf_count ? nullptr : static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
-    uint32_t* count = a.leaf_count ? const_cast<uint32_t*>(a.leaf_count) : count_own;
+    const uint32_t* count = a.leaf_count ? a.leaf_count + L : count_own;
+    uint32_t* total = a.leaf_count ? static_cast<uint32_t*>(t.alloc.get((size_t)L * 4)) : count_own;
     uint32_t* offset = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
     uint32_t* cursor = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
     uint32_t* bsum = static_cast<uint32_t*>(t.alloc.get((size_t)scan_scratch_elems(L) * 4));
     uint32_t* tot = static_cast<uint32_t*>(t.alloc.get(16));
     auto drop = [&]() {
         t.alloc.put(count_own);
+        if (a.leaf_count) t.alloc.put(total);
         t.alloc.put(offset);
         t.alloc.put(cursor);
         t.alloc.put(bsum);
         t.alloc.put(tot);
     };
-    if (!count || !offset || !cursor || !bsum || !tot) {
+    if (!total || !offset || !cursor || !bsum || !tot) {
         drop();
         return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     unsigned fg = (unsigned)std::min<int64_t>((L + 255) / 256, 65536);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L);
     if (!a.leaf_count) {
-        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count, L);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count_own, L);
         switch (t.storage) {
-            case DOT_F32: hipLaunchKernelGGL(bwd_count_kernel<DOT_F32>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
-            case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
-            default: hipLaunchKernelGGL(bwd_count_kernel<DOT_BF16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count); break;
+            case DOT_F32: hipLaunchKernelGGL(bwd_count_kernel<DOT_F32>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
+            case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
+            default: hipLaunchKernelGGL(bwd_count_kernel<DOT_BF16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
         }
+    } else {
+        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, base0, count, total, L);
     }
-    hipError_t e = scan_u32(count, offset, L, bsum, tot, s);
+    hipError_t e = scan_u32(total, offset, L, bsum, tot, s);
     uint32_t m = 0, overflow = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&m, tot, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && a.rec.a) e = hipMemcpyAsync(&overflow, a.rec.overflow, 4, hipMemcpyDeviceToHost, s);
@@ -802,51 +898,51 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     if (a.rec.a) {
-        // replay the recorded segments; re-traverse only the rays that overflowed
+        // replay the recorded segments; re-traverse only the rays with more
         switch (t.degree) {
-            case 0: hipLaunchKernelGGL(bwd_emit_rec_kernel<0>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
-            case 1: hipLaunchKernelGGL(bwd_emit_rec_kernel<1>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
-            case 2: hipLaunchKernelGGL(bwd_emit_rec_kernel<2>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
-            default: hipLaunchKernelGGL(bwd_emit_rec_kernel<3>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, count, cursor, rows); break;
+            case 0: hipLaunchKernelGGL(bwd_emit_rec_kernel<0>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
+            case 1: hipLaunchKernelGGL(bwd_emit_rec_kernel<1>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
+            case 2: hipLaunchKernelGGL(bwd_emit_rec_kernel<2>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
+            default: hipLaunchKernelGGL(bwd_emit_rec_kernel<3>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
         }
-    }
-    if (!a.rec.a) {
+        if (overflow > 0) {
+            // only FP32 trees record (training storage)
+            const int64_t no = std::min<int64_t>(overflow, rb.n_rays);
+            const dim3 lg((unsigned)((no + BLOCK - 1) / BLOCK));
+            switch (t.degree) {
+                case 0: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 0>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+                case 1: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 1>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+                case 2: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 2>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+                default: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 3>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+            }
+        }
+    } else {
         switch (t.storage) {
-            case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
-            case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
-            default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, count, cursor, rows, grid, s); break;
-        }
-    } else if (overflow > 0) {
-        // only FP32 trees record (training storage)
-        const int64_t no = std::min<int64_t>(overflow, rb.n_rays);
-        const dim3 lg((unsigned)((no + BLOCK - 1) / BLOCK));
-        switch (t.degree) {
-            case 0: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 0>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
-            case 1: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 1>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
-            case 2: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 2>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
-            default: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 3>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, count, cursor, rows); break;
+            case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, a, offset, base0, count, cursor, rows, grid, s); break;
+            case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, base0, count, cursor, rows, grid, s); break;
+            default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, base0, count, cursor, rows, grid, s); break;
         }
     }
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
     if ((uint64_t)m >= (uint64_t)kWaveRowsPerLeaf * (uint64_t)L) {
         switch (t.degree) {
-            case 0: launch_reduce_wave<0>(t, a, fused, offset, count, cursor, rows, s); break;
-            case 1: launch_reduce_wave<1>(t, a, fused, offset, count, cursor, rows, s); break;
-            case 2: launch_reduce_wave<2>(t, a, fused, offset, count, cursor, rows, s); break;
-            default: launch_reduce_wave<3>(t, a, fused, offset, count, cursor, rows, s); break;
+            case 0: launch_reduce_wave<0>(t, a, fused, offset, base0, count, cursor, rows, s); break;
+            case 1: launch_reduce_wave<1>(t, a, fused, offset, base0, count, cursor, rows, s); break;
+            case 2: launch_reduce_wave<2>(t, a, fused, offset, base0, count, cursor, rows, s); break;
+            default: launch_reduce_wave<3>(t, a, fused, offset, base0, count, cursor, rows, s); break;
         }
     } else if (fused) {
         switch (t.degree) {
-            case 0: launch_bwd_rmsprop<0>(t, a, offset, count, cursor, rows, s); break;
-            case 1: launch_bwd_rmsprop<1>(t, a, offset, count, cursor, rows, s); break;
-            case 2: launch_bwd_rmsprop<2>(t, a, offset, count, cursor, rows, s); break;
-            default: launch_bwd_rmsprop<3>(t, a, offset, count, cursor, rows, s); break;
+            case 0: launch_bwd_rmsprop<0>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 1: launch_bwd_rmsprop<1>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 2: launch_bwd_rmsprop<2>(t, a, offset, base0, count, cursor, rows, s); break;
+            default: launch_bwd_rmsprop<3>(t, a, offset, base0, count, cursor, rows, s); break;
         }
     } else switch (t.degree) {
-        case 0: hipLaunchKernelGGL(bwd_reduce_kernel<0>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
-        case 1: hipLaunchKernelGGL(bwd_reduce_kernel<1>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
-        case 2: hipLaunchKernelGGL(bwd_reduce_kernel<2>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
-        default: hipLaunchKernelGGL(bwd_reduce_kernel<3>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 0: hipLaunchKernelGGL(bwd_reduce_kernel<0>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 1: hipLaunchKernelGGL(bwd_reduce_kernel<1>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        case 2: hipLaunchKernelGGL(bwd_reduce_kernel<2>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+        default: hipLaunchKernelGGL(bwd_reduce_kernel<3>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
     }
     e = hipGetLastError();
     t.alloc.put(rows);

@@ -199,12 +199,14 @@ def test_training_forward_identical_with_and_without_links():
         torch.cuda.synchronize()
         r = rec.cpu().numpy()
         # buffer: overflow count, per-ray record counts, overflow ray list (in
-        # arrival order: compared as a set), then the slot-major records
+        # arrival order: compared as a set), the slot-major records, then their
+        # bucket slots (handed out in arrival order: not compared)
         n_over = int(r[:4].view(np.uint32)[0])
         counts = r[256:256 + 4 * n].view(np.int32)
         o0 = 256 + up(4 * n)
         olist = np.sort(r[o0:o0 + 4 * n_over].view(np.int32))
-        recs = r[o0 + up(4 * n):]
+        a0 = o0 + up(4 * n)
+        recs = r[a0:a0 + up(4 * n * 16) + up(4 * n * 8)]
         return (rgb.cpu().numpy(), ns.cpu().numpy(), cnt.cpu().numpy(), sig.cpu().numpy(), np.array([n_over]),
                 counts, olist, recs)
 
