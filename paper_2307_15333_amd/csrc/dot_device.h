@@ -434,6 +434,21 @@ struct FwdSeg {
         float tau = sg * delta;
         ++n;
         fetched += tau > 0.f;
+        // a training forward counts, per leaf, the segments whose gradient rows
+        // its adjoint emits; a segment it records also reserves its row's slot
+        // in the leaf's bucket (issued here, early, and consumed one record later)
+        [[maybe_unused]] uint32_t slot = 0;
+        [[maybe_unused]] bool record = false;
+        if constexpr (COUNT) {
+            if (sg > 0.f) {
+                if (a.rec.a && nrec < a.rec.cap) {
+                    slot = atomicAdd(&a.leaf_count[leaf], 1u);
+                    record = true;
+                } else {
+                    atomicAdd(&a.leaf_rest[leaf], 1u);
+                }
+            }
+        }
         {
             float Sn = S + tau;
             float Tn = __expf(-Sn);
@@ -457,24 +472,18 @@ struct FwdSeg {
                 cv[ch] = sigmoidf_(x);
                 C[ch] = fmaf(w, cv[ch], C[ch]);
             }
-            // a training forward counts, per leaf, the segments whose gradient
-            // rows its adjoint emits; a recorded segment (leaf, delta, tau and
-            // the colour) also reserves its row's bucket slot here
+            // the record the adjoint replays: leaf, delta, tau, the colour and
+            // (stored with the next record) the reserved slot
             if constexpr (COUNT) {
-                if (sg > 0.f) {
-                    if (a.rec.a && nrec < a.rec.cap) {
-                        const uint32_t slot = atomicAdd(&a.leaf_count[leaf], 1u);
-                        const int64_t j = (int64_t)nrec * a.rec.n + rid;
-                        a.rec.a[j] = make_float4(__int_as_float(leaf), delta, tau, cv[0]);
-                        a.rec.b[j] = make_float2(cv[1], cv[2]);
-                        flush_slot();
-                        pend_j = j;
-                        pend_slot = slot;
-                    } else {
-                        atomicAdd(&a.leaf_rest[leaf], 1u);
-                    }
-                    if (a.rec.a) ++nrec;
+                if (record) {
+                    const int64_t j = (int64_t)nrec * a.rec.n + rid;
+                    a.rec.a[j] = make_float4(__int_as_float(leaf), delta, tau, cv[0]);
+                    a.rec.b[j] = make_float2(cv[1], cv[2]);
+                    flush_slot();
+                    pend_j = j;
+                    pend_slot = slot;
                 }
+                if (sg > 0.f && a.rec.a) ++nrec;
             }
             if (a.signal) {
                 if (a.signal_mode == DOT_SIGNAL_MAX) {
