@@ -83,6 +83,8 @@ def main():
                     help="run one secondary measurement alone and print its JSON (for profiling it)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one 1 GiB device copy and one render (counter calibration runs)")
+    ap.add_argument("--profile-dtypes", action="store_true",
+                    help="render the benchmark frame once per leaf storage (FP32, FP16, BF16) for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the renderer would shard by rays "
@@ -126,6 +128,18 @@ def main():
         L.check(lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(opts), C.c_void_p(rgb.data_ptr()),
                                None, C.c_void_p(signal.data_ptr()), core._stream()))
 
+    if args.profile_dtypes:
+        for st in ("f32", "f16", "bf16"):
+            t = tree if st == "f32" else core.Octree.from_scene(scene, st)
+            signal.zero_()
+            for _ in range(2):
+                L.check(lib.dot_render(t.handle, C.byref(rays.struct), C.byref(opts), C.c_void_p(rgb.data_ptr()),
+                                       None, C.c_void_p(signal.data_ptr()), core._stream()))
+            torch.cuda.synchronize()
+            if t is not tree:
+                t.close()
+        log("profile-dtypes: two renders per storage type done")
+        return
     if args.profile_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
