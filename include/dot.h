@@ -313,7 +313,8 @@ typedef struct {
  *  (FP32 storage only).  grad_*: DEVICE float, dense layouts as in
  *  dot_render_backward; m_* / v_*: DEVICE float moments of the same shapes,
  *  zero-initialised by the caller before step 1.
- *  Errors: DOT_EUNSUPPORTED for FP16/BF16 storage.
+ *  Errors: DOT_EUNSUPPORTED for FP16/BF16 storage; DOT_EINVAL for beta1 or
+ *  beta2 outside [0, 1), eps not positive and finite, or step < 1.
  */
 int dot_adam_step(dot_tree_t tree, const float *grad_sigma, const float *grad_sh, float *m_sigma,
                   float *v_sigma, float *m_sh, float *v_sh, const dot_adam_params *params,
@@ -350,6 +351,22 @@ int dot_render_backward_rmsprop(dot_tree_t tree, const dot_rays *rays, const dot
                                 const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb, float *v_sigma,
                                 float *v_sh, const dot_rmsprop_params *params, const uint32_t *leaf_count,
                                 const void *records, size_t records_bytes, void *stream);
+
+/*
+ * dot_render_backward_adam -- dot_render_backward followed by one
+ *  dot_adam_step, fused in the same way as dot_render_backward_rmsprop: each
+ *  leaf's bucket sums feed the update directly and no dense gradient array
+ *  exists.  Same arithmetic as dot_render_backward into zeroed arrays followed
+ *  by dot_adam_step; every leaf is updated (a leaf no ray reached has g = 0:
+ *  both moments decay and its values still move by the decayed first moment).
+ *  Arguments and errors as in those two calls; the same dense fallback as
+ *  dot_render_backward_rmsprop.  FP32 storage only (DOT_EUNSUPPORTED
+ *  otherwise).
+ */
+int dot_render_backward_adam(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
+                             const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb, float *m_sigma,
+                             float *v_sigma, float *m_sh, float *v_sh, const dot_adam_params *params,
+                             const uint32_t *leaf_count, const void *records, size_t records_bytes, void *stream);
 
 /*
  * dot_sigma_signal -- the density as the training signal (the paper's Pr_sigma

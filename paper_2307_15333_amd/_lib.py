@@ -111,6 +111,10 @@ SIGNATURES = {
                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.POINTER(dot_rmsprop_params), C.c_void_p, C.c_void_p, C.c_size_t,
                                               C.c_void_p]),
+    "dot_render_backward_adam": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
+                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.POINTER(dot_adam_params), C.c_void_p, C.c_void_p,
+                                           C.c_size_t, C.c_void_p]),
     "dot_sigma_signal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dot_pixel_batch_workspace": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     "dot_pixel_batch": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,

@@ -270,6 +270,18 @@ class Octree:
                                                      C.c_size_t(records.numel() if records is not None else 0),
                                                      _stream()))
 
+    def backward_adam(self, rays, rgb, nseg, grad_rgb, state, step, lr_sigma=0.1, lr_sh=0.01, beta1=0.9,
+                      beta2=0.999, eps=1e-8, bg=(1.0, 1.0, 1.0), t_stop=1e-4, leaf_count=None, records=None):
+        """Adjoint and Adam step (1-based `step`) in one call (no dense gradient arrays)."""
+        op = render_opts(bg, t_stop)
+        p = L.dot_adam_params(lr_sigma=lr_sigma, lr_sh=lr_sh, beta1=beta1, beta2=beta2, eps=eps, step=int(step))
+        L.check(self.lib.dot_render_backward_adam(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
+                                                  _ptr(nseg), _ptr(grad_rgb), _ptr(state["m_sigma"]),
+                                                  _ptr(state["v_sigma"]), _ptr(state["m_sh"]), _ptr(state["v_sh"]),
+                                                  C.byref(p), _ptr(leaf_count), _ptr(records),
+                                                  C.c_size_t(records.numel() if records is not None else 0),
+                                                  _stream()))
+
     def rmsprop_state(self):
         Ln = self.n_leaves
         z = lambda *s: torch.zeros(s, dtype=torch.float32, device=self.device)

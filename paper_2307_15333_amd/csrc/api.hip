@@ -256,6 +256,16 @@ static int fill_opts(const dot_render_opts* o, float bg[3], float& thr, const ch
     return DOT_OK;
 }
 
+// Adam's constants: decays in [0, 1), eps positive and finite, 1-based step
+static int check_adam(const dot_adam_params& p, const char* who) {
+    if (!(p.beta1 >= 0.f && p.beta1 < 1.f && p.beta2 >= 0.f && p.beta2 < 1.f))
+        return fail(DOT_EINVAL, std::string(who) + ": beta1 and beta2 must be in [0, 1)");
+    if (!(p.eps > 0.f && p.eps < __builtin_huge_valf()))
+        return fail(DOT_EINVAL, std::string(who) + ": eps must be positive and finite");
+    if (p.step < 1) return fail(DOT_EINVAL, std::string(who) + ": step must be >= 1");
+    return DOT_OK;
+}
+
 }  // namespace dot
 
 using namespace dot;
@@ -507,6 +517,43 @@ int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_re
     return DOT_OK;
 }
 
+int dot_render_backward_adam(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, const float* rgb_fwd,
+                             const int32_t* nseg, const float* grad_rgb, float* m_sigma, float* v_sigma, float* m_sh,
+                             float* v_sh, const dot_adam_params* params, const uint32_t* leaf_count,
+                             const void* records, size_t records_bytes, void* stream) {
+    if (!t || !params) return fail(DOT_EINVAL, "dot_render_backward_adam: NULL tree or params");
+    if (t->storage != DOT_F32)
+        return fail(DOT_EUNSUPPORTED, "dot_render_backward_adam: only FP32 leaf storage is trainable");
+    if (int rc = check_adam(*params, "dot_render_backward_adam")) return rc;
+    if (!m_sigma || !v_sigma || !m_sh || !v_sh)
+        return fail(DOT_EINVAL, "dot_render_backward_adam: moment buffers are required");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_render_backward_adam");
+    if (rc) return rc;
+    if (rb.n_rays > 0 && (!rgb_fwd || !nseg || !grad_rgb))
+        return fail(DOT_EINVAL, "dot_render_backward_adam: rgb_fwd, nseg and grad_rgb are required");
+    BwdArgs a{};
+    float bg[3];
+    rc = fill_opts(opts, bg, a.thr, "dot_render_backward_adam");
+    if (rc) return rc;
+    a.rgb_fwd = rgb_fwd;
+    a.nseg = nseg;
+    a.grad_rgb = grad_rgb;
+    a.m_sigma = m_sigma;
+    a.v_sigma = v_sigma;
+    a.m_sh = m_sh;
+    a.v_sh = v_sh;
+    a.adam = params;
+    a.leaf_count = leaf_count;
+    if (records && !leaf_count) return fail(DOT_EINVAL, "dot_render_backward_adam: records need leaf_count");
+    rc = records_for(records, records_bytes, rb.n_rays, a.rec, "dot_render_backward_adam");
+    if (rc) return rc;
+    hipError_t e = launch_render_bwd(*t, rb, a, static_cast<hipStream_t>(stream));
+    if (e == hipErrorOutOfMemory) return fail(DOT_ENOMEM, "dot_render_backward_adam: scratch allocation failed");
+    if (e != hipSuccess) return hip_fail(e, "dot_render_backward_adam: launch");
+    return DOT_OK;
+}
+
 int dot_render_stats(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, int64_t counts[4],
                      void* stream) {
     if (!t || !counts) return fail(DOT_EINVAL, "dot_render_stats: NULL argument");
@@ -537,7 +584,7 @@ int dot_adam_step(dot_tree_t t, const float* grad_sigma, const float* grad_sh, f
     if (t->storage != DOT_F32) return fail(DOT_EUNSUPPORTED, "dot_adam_step: only FP32 leaf storage is trainable");
     if (!grad_sigma || !grad_sh || !m_sigma || !v_sigma || !m_sh || !v_sh)
         return fail(DOT_EINVAL, "dot_adam_step: gradient and moment buffers are required");
-    if (p->step < 1) return fail(DOT_EINVAL, "dot_adam_step: step must be >= 1");
+    if (int rc = check_adam(*p, "dot_adam_step")) return rc;
     hipError_t e = launch_adam(*t, grad_sigma, grad_sh, m_sigma, v_sigma, m_sh, v_sh, *p,
                                static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_adam_step: launch");

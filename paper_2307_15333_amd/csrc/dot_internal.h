@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 
@@ -173,16 +174,29 @@ struct BwdArgs {
     const uint32_t* leaf_count;
     // the forward's segment records (a == null: replay by traversal)
     SegRecords rec;
-    // fused RMSProp (grad_* unused): square averages and parameters, or null
+    // fused optimiser step (grad_* unused): RMSProp (rms) or Adam (adam, with
+    // first moments m_*), second moments v_*; both null: plain adjoint
+    float* m_sigma;
+    float* m_sh;
     float* v_sigma;
     float* v_sh;
     const dot_rmsprop_params* rms;
+    const dot_adam_params* adam;
 };
 
 // RMSProp on one parameter: v = alpha v + (1 - alpha) g^2; theta -= lr g / (sqrt(v) + eps)
 __device__ __forceinline__ void rmsprop_update(float& theta, float& v, float g, float lr, float alpha, float eps) {
     v = alpha * v + (1.f - alpha) * g * g;
     theta -= lr * g / (sqrtf(v) + eps);
+}
+
+// Adam (Kingma & Ba) on one parameter: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// theta -= lr (m / bc1) / (sqrt(v / bc2) + eps) with bc = 1 - b^t
+__device__ __forceinline__ void adam_update(float& theta, float& m, float& v, float g, float lr, float b1, float b2,
+                                            float eps, float bc1, float bc2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    theta -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
 }
 
 hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArgs& a, hipStream_t s);
@@ -194,6 +208,11 @@ hipError_t launch_decode_planes(int storage, const void* src, float* dst, int64_
                                 int src_stride, hipStream_t s);
 hipError_t launch_adam(const dot_tree& t, const float* gs, const float* gh, float* ms, float* vs,
                        float* mh, float* vh, const dot_adam_params& p, hipStream_t s);
+// Adam's bias corrections 1 - beta1^t and 1 - beta2^t (host, FP32)
+inline void adam_bias_corrections(const dot_adam_params& p, float& bc1, float& bc2) {
+    bc1 = 1.f - powf(p.beta1, (float)p.step);
+    bc2 = 1.f - powf(p.beta2, (float)p.step);
+}
 // exclusive scan of n uint32 values; *tot receives the total (device); bsum
 // needs scan_scratch_elems(n) elements
 int64_t scan_scratch_elems(int64_t n);

@@ -77,9 +77,7 @@ hipError_t launch_decode_planes(int storage, const void* src, float* dst, int64_
     return hipGetLastError();
 }
 
-// Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
-// theta -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
-// Parameter j < L is sigma[j]; j >= L is SH coefficient (j-L) of the dense
+// Adam (adam_update) on every parameter.  Parameter j < L is sigma[j]; j >= L is SH coefficient (j-L) of the dense
 // [L][3K] layout, stored at row stride `stride` in the plane.
 __global__ void adam_kernel(float* __restrict__ sigma, float* __restrict__ sh, const float* __restrict__ gs,
                             const float* __restrict__ gh, float* __restrict__ ms, float* __restrict__ vs,
@@ -106,11 +104,13 @@ __global__ void adam_kernel(float* __restrict__ sigma, float* __restrict__ sh, c
             theta = &sh[r * stride + c];
             lr = p.lr_sh;
         }
-        m = p.beta1 * *mp + (1.f - p.beta1) * g;
-        v = p.beta2 * *vp + (1.f - p.beta2) * g * g;
+        m = *mp;
+        v = *vp;
+        float th = *theta;
+        adam_update(th, m, v, g, lr, p.beta1, p.beta2, p.eps, bc1, bc2);
         *mp = m;
         *vp = v;
-        *theta -= lr * (m / bc1) / (sqrtf(v / bc2) + p.eps);
+        *theta = th;
     }
 }
 
@@ -118,8 +118,8 @@ hipError_t launch_adam(const dot_tree& t, const float* gs, const float* gh, floa
                        float* vh, const dot_adam_params& p, hipStream_t s) {
     int nv = 3 * (t.degree + 1) * (t.degree + 1);
     int64_t n = t.n_leaves * (1 + nv);
-    float bc1 = 1.f - powf(p.beta1, (float)p.step);
-    float bc2 = 1.f - powf(p.beta2, (float)p.step);
+    float bc1, bc2;
+    adam_bias_corrections(p, bc1, bc2);
     hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, static_cast<float*>(t.sigma),
                        static_cast<float*>(t.sh), gs, gh, ms, vs, mh, vh, t.n_leaves, nv, t.sh_stride, p, bc1,
                        bc2);

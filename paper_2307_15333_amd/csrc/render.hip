@@ -573,17 +573,39 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const 
     }
 }
 
-// The same reduction feeding RMSProp for every leaf (untouched leaves have
-// g = 0: their square averages decay, their values stay).
-template <int DEG>
-__global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const uint32_t* __restrict__ offset,
-                                                                const uint32_t* __restrict__ base0,
-                                                                const uint32_t* __restrict__ count,
-                                                                const uint32_t* __restrict__ cursor,
-                                                                const float* __restrict__ rows,
-                                                                float* __restrict__ sigma, float* __restrict__ sh,
-                                                                int stride, float* __restrict__ vs,
-                                                                float* __restrict__ vh, dot_rmsprop_params p) {
+// A fused optimiser step, by value: RMSProp (d1 = alpha) or Adam (d1, d2 =
+// beta1, beta2; bc1, bc2 = its bias corrections; m_* = first moments).
+enum { OPT_NONE = 0, OPT_RMSPROP = 1, OPT_ADAM = 2 };
+struct FusedOpt {
+    float lr_sigma, lr_sh, eps, d1, d2, bc1, bc2;
+    float *m_sigma, *m_sh, *v_sigma, *v_sh;
+};
+
+template <int OPT>
+__device__ __forceinline__ void fused_update(float* theta, float* m, float* v, float g, float lr, const FusedOpt& o) {
+    float th = *theta, vv = *v;
+    if constexpr (OPT == OPT_ADAM) {
+        float mm = *m;
+        adam_update(th, mm, vv, g, lr, o.d1, o.d2, o.eps, o.bc1, o.bc2);
+        *m = mm;
+    } else {
+        rmsprop_update(th, vv, g, lr, o.d1, o.eps);
+    }
+    *theta = th;
+    *v = vv;
+}
+
+// The same reduction feeding the optimiser for every leaf (untouched leaves
+// have g = 0: RMSProp only decays their square averages, Adam still moves
+// them by its decayed first moment).
+template <int DEG, int OPT>
+__global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const uint32_t* __restrict__ offset,
+                                                              const uint32_t* __restrict__ base0,
+                                                              const uint32_t* __restrict__ count,
+                                                              const uint32_t* __restrict__ cursor,
+                                                              const float* __restrict__ rows,
+                                                              float* __restrict__ sigma, float* __restrict__ sh,
+                                                              int stride, FusedOpt o) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int NV = 3 * K;
     constexpr int KP = K + 1;
@@ -595,10 +617,7 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const
     for (int j = 0; j < NV; ++j) acc[j] = 0.f;
     if (l < L) {
         bucket_sum<DEG>(l, offset, base0, count, cursor, rows, gs, acc);
-        float th = sigma[l], v = vs[l];
-        rmsprop_update(th, v, gs, p.lr_sigma, p.alpha, p.eps);
-        sigma[l] = th;
-        vs[l] = v;
+        fused_update<OPT>(sigma + l, o.m_sigma + l, o.v_sigma + l, gs, o.lr_sigma, o);
     }
     const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
 #pragma unroll
@@ -609,28 +628,23 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_rmsprop_kernel(int64_t L, const
         __syncthreads();
         for (int i = threadIdx.x; i < nl * K; i += RED_BLOCK) {
             const int r = i / K, k = i - r * K;
-            const int64_t col = (int64_t)ch * K + k;
-            float* t = sh + (l0 + r) * stride + col;
-            float* vp = vh + (l0 + r) * NV + col;
-            float th = *t, v = *vp;
-            rmsprop_update(th, v, stage[r * KP + k], p.lr_sh, p.alpha, p.eps);
-            *t = th;
-            *vp = v;
+            const int64_t q = (l0 + r) * NV + (int64_t)ch * K + k;
+            fused_update<OPT>(sh + (l0 + r) * stride + ch * K + k, o.m_sh + q, o.v_sh + q, stage[r * KP + k],
+                              o.lr_sh, o);
         }
     }
 }
 
 // Heavy buckets (many rows per leaf, e.g. a small tree under a large batch):
 // one wave per leaf, lanes stride over the rows, then a butterfly reduction of
-// the 1 + 3K sums across the wave; lane j then owns column j.  FUSED applies
-// RMSProp to every leaf, otherwise the sums are added to the gradient arrays.
-template <int DEG, bool FUSED>
+// the 1 + 3K sums across the wave; lane j then owns column j.  A fused OPT
+// updates every leaf, otherwise the sums are added to the gradient arrays.
+template <int DEG, int OPT>
 __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
     int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ base0,
     const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
-    float* __restrict__ gsig,
-    float* __restrict__ gsh, float* __restrict__ sigma, float* __restrict__ sh, int stride, float* __restrict__ vs,
-    float* __restrict__ vh, dot_rmsprop_params p) {
+    float* __restrict__ gsig, float* __restrict__ gsh, float* __restrict__ sigma, float* __restrict__ sh, int stride,
+    FusedOpt o) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int NV = 3 * K;
     constexpr int RS = bwd_row_floats<DEG>();
@@ -670,19 +684,11 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
 #pragma unroll
         for (int j = 0; j < NV; ++j)
             if (lane == j) mine = acc[j];
-        if constexpr (FUSED) {
-            if (lane < NV) {
-                float t = sh[l * stride + lane], v = vh[l * NV + lane];
-                rmsprop_update(t, v, mine, p.lr_sh, p.alpha, p.eps);
-                sh[l * stride + lane] = t;
-                vh[l * NV + lane] = v;
-            }
-            if (lane == 0) {
-                float t = sigma[l], v = vs[l];
-                rmsprop_update(t, v, gs, p.lr_sigma, p.alpha, p.eps);
-                sigma[l] = t;
-                vs[l] = v;
-            }
+        if constexpr (OPT != OPT_NONE) {
+            if (lane < NV)
+                fused_update<OPT>(sh + l * stride + lane, o.m_sh + l * NV + lane, o.v_sh + l * NV + lane, mine,
+                                  o.lr_sh, o);
+            if (lane == 0) fused_update<OPT>(sigma + l, o.m_sigma + l, o.v_sigma + l, gs, o.lr_sigma, o);
         } else if (m > 0) {
             if (lane < NV && mine != 0.f) gsh[l * NV + lane] += mine;
             if (lane == 0) gsig[l] += gs;
@@ -690,20 +696,52 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
     }
 }
 
-template <int DEG>
-static void launch_reduce_wave(const dot_tree& t, const BwdArgs& a, bool fused, const uint32_t* offset,
-                               const uint32_t* base0, const uint32_t* count, const uint32_t* cursor,
-                               const float* rows, hipStream_t s) {
+static FusedOpt fused_opt(const BwdArgs& a) {
+    FusedOpt o{};
+    o.m_sigma = a.m_sigma;
+    o.m_sh = a.m_sh;
+    o.v_sigma = a.v_sigma;
+    o.v_sh = a.v_sh;
+    if (a.adam) {
+        o.lr_sigma = a.adam->lr_sigma;
+        o.lr_sh = a.adam->lr_sh;
+        o.eps = a.adam->eps;
+        o.d1 = a.adam->beta1;
+        o.d2 = a.adam->beta2;
+        adam_bias_corrections(*a.adam, o.bc1, o.bc2);
+    } else if (a.rms) {
+        o.lr_sigma = a.rms->lr_sigma;
+        o.lr_sh = a.rms->lr_sh;
+        o.eps = a.rms->eps;
+        o.d1 = a.rms->alpha;
+    }
+    return o;
+}
+
+static int opt_kind(const BwdArgs& a) { return a.adam ? OPT_ADAM : a.rms ? OPT_RMSPROP : OPT_NONE; }
+
+template <int DEG, int OPT>
+static void launch_reduce_wave_opt(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
+                                   const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
     const int64_t L = t.n_leaves;
     const unsigned g = (unsigned)std::min<int64_t>((L + RED_BLOCK / WAVE - 1) / (RED_BLOCK / WAVE), 1 << 16);
-    const dot_rmsprop_params p = fused ? *a.rms : dot_rmsprop_params{};
-    if (fused)
-        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, true>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0, count,
-                           cursor, rows, nullptr, nullptr, static_cast<float*>(t.sigma), static_cast<float*>(t.sh),
-                           t.sh_stride, a.v_sigma, a.v_sh, p);
+    if constexpr (OPT == OPT_NONE)
+        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, OPT>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0,
+                           count, cursor, rows, a.grad_sigma, a.grad_sh, nullptr, nullptr, 0, FusedOpt{});
     else
-        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, false>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0,
-                           count, cursor, rows, a.grad_sigma, a.grad_sh, nullptr, nullptr, 0, nullptr, nullptr, p);
+        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, OPT>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0,
+                           count, cursor, rows, nullptr, nullptr, static_cast<float*>(t.sigma),
+                           static_cast<float*>(t.sh), t.sh_stride, fused_opt(a));
+}
+
+template <int DEG>
+static void launch_reduce_wave(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
+                               const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
+    switch (opt_kind(a)) {
+        case OPT_RMSPROP: launch_reduce_wave_opt<DEG, OPT_RMSPROP>(t, a, offset, base0, count, cursor, rows, s); break;
+        case OPT_ADAM: launch_reduce_wave_opt<DEG, OPT_ADAM>(t, a, offset, base0, count, cursor, rows, s); break;
+        default: launch_reduce_wave_opt<DEG, OPT_NONE>(t, a, offset, base0, count, cursor, rows, s); break;
+    }
 }
 
 // buckets holding at least this many rows on average are reduced a wave per leaf
@@ -801,17 +839,15 @@ __global__ void add_u32_kernel(const uint32_t* __restrict__ a, const uint32_t* _
 // bucket scratch beyond this many bytes falls back to the atomic adjoint
 static constexpr double kBucketBytesMax = 8.0 * (1ull << 30);
 
-static hipError_t bwd_rmsprop_dense(const dot_tree& t, const RayBatch& rb, const BwdArgs& a0, dim3 grid,
-                                    hipStream_t s);
-static hipError_t launch_rmsprop_zero_grad(const dot_tree& t, const BwdArgs& a, hipStream_t s) {
+static hipError_t bwd_fused_dense(const dot_tree& t, const RayBatch& rb, const BwdArgs& a0, dim3 grid, hipStream_t s);
+static hipError_t launch_fused_zero_grad(const dot_tree& t, const BwdArgs& a, hipStream_t s) {
     RayBatch none{};
-    return bwd_rmsprop_dense(t, none, a, dim3(1), s);
+    return bwd_fused_dense(t, none, a, dim3(1), s);
 }
 
 // Fused path when the buckets cannot be used: dense gradients from the atomic
-// adjoint, then the elementwise RMSProp step.
-static hipError_t bwd_rmsprop_dense(const dot_tree& t, const RayBatch& rb, const BwdArgs& a0, dim3 grid,
-                                    hipStream_t s) {
+// adjoint, then the elementwise optimiser step.
+static hipError_t bwd_fused_dense(const dot_tree& t, const RayBatch& rb, const BwdArgs& a0, dim3 grid, hipStream_t s) {
     const int nv = 3 * (t.degree + 1) * (t.degree + 1);
     float* g = static_cast<float*>(t.alloc.get((size_t)t.n_leaves * (1 + nv) * 4));
     if (!g) return hipErrorOutOfMemory;
@@ -822,26 +858,33 @@ static hipError_t bwd_rmsprop_dense(const dot_tree& t, const RayBatch& rb, const
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s,
                        reinterpret_cast<uint32_t*>(g), n);
     hipError_t e = rb.n_tiles ? bwd_atomic(t, rb, a, grid, s) : hipGetLastError();
-    if (e == hipSuccess) e = launch_rmsprop(t, a.grad_sigma, a.grad_sh, a.v_sigma, a.v_sh, *a.rms, s);
+    if (e == hipSuccess)
+        e = a.adam ? launch_adam(t, a.grad_sigma, a.grad_sh, a.m_sigma, a.v_sigma, a.m_sh, a.v_sh, *a.adam, s)
+                   : launch_rmsprop(t, a.grad_sigma, a.grad_sh, a.v_sigma, a.v_sh, *a.rms, s);
     t.alloc.put(g);
     return e;
 }
 
 template <int DEG>
-static void launch_bwd_rmsprop(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
-                               const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
+static void launch_bwd_fused(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
+                             const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
     const int64_t L = t.n_leaves;
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
-    hipLaunchKernelGGL(bwd_rmsprop_kernel<DEG>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows,
-                       static_cast<float*>(t.sigma), static_cast<float*>(t.sh), t.sh_stride, a.v_sigma, a.v_sh,
-                       *a.rms);
+    float* sg = static_cast<float*>(t.sigma);
+    float* sh = static_cast<float*>(t.sh);
+    if (a.adam)
+        hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_ADAM>), dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count,
+                           cursor, rows, sg, sh, t.sh_stride, fused_opt(a));
+    else
+        hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_RMSPROP>), dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0,
+                           count, cursor, rows, sg, sh, t.sh_stride, fused_opt(a));
 }
 
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s) {
-    const bool fused = a.rms != nullptr;
+    const bool fused = opt_kind(a) != OPT_NONE;
     if (rb.n_tiles == 0) {
-        // no rays: a fused step still decays the square averages (g = 0)
-        return fused ? launch_rmsprop_zero_grad(t, a, s) : hipSuccess;
+        // no rays: a fused step still runs with g = 0 (decaying moments)
+        return fused ? launch_fused_zero_grad(t, a, s) : hipSuccess;
     }
     dim3 grid((unsigned)((rb.n_tiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
     const int64_t L = t.n_leaves;
@@ -868,7 +911,7 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     };
     if (!total || !offset || !cursor || !bsum || !tot) {
         drop();
-        return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
+        return fused ? bwd_fused_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     unsigned fg = (unsigned)std::min<int64_t>((L + 255) / 256, 65536);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L);
@@ -895,7 +938,7 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     if ((double)m * rs * 4 <= kBucketBytesMax) rows = static_cast<float*>(t.alloc.get((size_t)std::max<uint32_t>(m, 1) * rs * 4));
     if (!rows) {
         drop();
-        return fused ? bwd_rmsprop_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
+        return fused ? bwd_fused_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     if (a.rec.a) {
         // replay the recorded segments; re-traverse only the rays with more
@@ -926,17 +969,17 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
     if ((uint64_t)m >= (uint64_t)kWaveRowsPerLeaf * (uint64_t)L) {
         switch (t.degree) {
-            case 0: launch_reduce_wave<0>(t, a, fused, offset, base0, count, cursor, rows, s); break;
-            case 1: launch_reduce_wave<1>(t, a, fused, offset, base0, count, cursor, rows, s); break;
-            case 2: launch_reduce_wave<2>(t, a, fused, offset, base0, count, cursor, rows, s); break;
-            default: launch_reduce_wave<3>(t, a, fused, offset, base0, count, cursor, rows, s); break;
+            case 0: launch_reduce_wave<0>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 1: launch_reduce_wave<1>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 2: launch_reduce_wave<2>(t, a, offset, base0, count, cursor, rows, s); break;
+            default: launch_reduce_wave<3>(t, a, offset, base0, count, cursor, rows, s); break;
         }
     } else if (fused) {
         switch (t.degree) {
-            case 0: launch_bwd_rmsprop<0>(t, a, offset, base0, count, cursor, rows, s); break;
-            case 1: launch_bwd_rmsprop<1>(t, a, offset, base0, count, cursor, rows, s); break;
-            case 2: launch_bwd_rmsprop<2>(t, a, offset, base0, count, cursor, rows, s); break;
-            default: launch_bwd_rmsprop<3>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 0: launch_bwd_fused<0>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 1: launch_bwd_fused<1>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 2: launch_bwd_fused<2>(t, a, offset, base0, count, cursor, rows, s); break;
+            default: launch_bwd_fused<3>(t, a, offset, base0, count, cursor, rows, s); break;
         }
     } else switch (t.degree) {
         case 0: hipLaunchKernelGGL(bwd_reduce_kernel<0>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;

@@ -47,7 +47,7 @@ class TrainConfig:
     recursive: bool = False
     reinit: bool = False            # ablation: new leaves start at zero instead of fused values
     refine: bool = True
-    fused: bool = True              # RMSProp applied inside the adjoint's per-leaf reduction
+    fused: bool = True              # the optimiser step applied inside the adjoint's per-leaf reduction
     record_segments: int = 96       # segments per ray the forward records for the adjoint's replay
     bg: tuple = (1.0, 1.0, 1.0)
     t_stop: float = 1e-4
@@ -113,11 +113,16 @@ class Trainer:
                                                       leaf_count=self._cnt, records=self._rec)
         loss, grad = core.mse_loss(rgb, self.targets, ids)
         self.opt_step += 1
-        if c.optimizer == "rmsprop" and c.fused:
+        if c.fused:
             # adjoint and update in one call: the gradient never exists as dense arrays
-            self.tree.backward_rmsprop(rays, rgb, nseg, grad, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
-                                       alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt,
-                                       records=self._rec)
+            if c.optimizer == "rmsprop":
+                self.tree.backward_rmsprop(rays, rgb, nseg, grad, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
+                                           alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt,
+                                           records=self._rec)
+            else:
+                self.tree.backward_adam(rays, rgb, nseg, grad, self.state, self.opt_step, lr_sigma=c.lr_sigma,
+                                        lr_sh=c.lr_sh, beta1=c.beta1, beta2=c.beta2, eps=c.eps, bg=c.bg,
+                                        t_stop=c.t_stop, leaf_count=self._cnt, records=self._rec)
             return loss
         if self.gs is None:
             t = self.tree

@@ -2,6 +2,8 @@
 
 * dot_mse_loss against the FP64 MSE definition (loss and gradient),
 * dot_rmsprop_step against the FP64 RMSProp update on seeded gradients,
+* the fused adjoint + RMSProp / Adam calls against the oracle's gradient and
+  the FP64 optimisers, and the fused Adam bit for bit against the split path,
 * dot_sigma_signal bit for bit against max(stored sigma, 0),
 * whole epochs of the loop -- permuted batches, render with the fused signal,
   MSE, adjoint, RMSProp, and a refinement every second epoch -- against the
@@ -205,6 +207,127 @@ def test_rmsprop_rejects_bad_arguments():
             with pytest.raises(L.DotError) as e:
                 tree.backward_rmsprop(empty, z, torch.zeros(0, dtype=torch.int32, device="cuda"), z, st, **kw)
             assert e.value.code == code
+        tree.close()
+
+
+def _adam_state_np(st):
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in st.items()}
+
+
+@pytest.mark.parametrize("depth,n_rays", [(3, 20000), (6, 3000)])
+def test_fused_backward_adam_bit_matches_split_path(depth, n_rays):
+    """Adjoint + Adam in one call against dot_render_backward into zeroed
+    arrays followed by dot_adam_step, on two copies of one tree replaying the
+    same forward records (no overflow, so both sides sum every bucket in the
+    same order): parameters and both moments bit for bit, over two steps.
+    The small tree under the large batch is reduced a wave per leaf, the large
+    tree under the small batch a thread per leaf."""
+    core = _core()
+    s = synth.random_tree_scene(depth, 2, seed=60 + depth)
+    views = synth.random_sphere_cameras(6, 3.5, 64, 64, seed=3)
+    ci, pi = synth.pixel_batch(6, 64, 64, n_rays, seed=4)
+    rays = core.Rays.pixels(views, ci, pi)
+    g = torch.as_tensor(np.random.default_rng(5).normal(size=(ci.shape[0], 3)) * 1e-3, dtype=torch.float32,
+                        device="cuda")
+    split, fused = core.Octree.from_scene(s), core.Octree.from_scene(s)
+    st_a, st_b = split.adam_state(), fused.adam_state()
+    rec = torch.empty(core.Octree.records_bytes(rays.n_rays), dtype=torch.uint8, device="cuda")
+    gs = torch.zeros(split.n_leaves, device="cuda")
+    gh = torch.zeros((split.n_leaves, 3, split.K), device="cuda")
+    for step in (1, 2):
+        rgb, ns, cnt = split.render_train(rays, records=rec)
+        torch.cuda.synchronize()
+        assert int(rec[:4].cpu().numpy().view(np.uint32)[0]) == 0          # no overflow ray
+        gs.zero_()
+        gh.zero_()
+        split.backward(rays, rgb, ns, g, gs, gh, leaf_count=cnt, records=rec)
+        split.adam_step(gs, gh, st_a, step)
+        fused.backward_adam(rays, rgb, ns, g, st_b, step, leaf_count=cnt, records=rec)
+        ea, eb = split.export(), fused.export()
+        assert np.array_equal(ea["sigma"], eb["sigma"]) and np.array_equal(ea["sh"], eb["sh"])
+        for k in st_a:
+            assert torch.equal(st_a[k], st_b[k]), k
+    rows, L = int(cnt.sum()), split.n_leaves               # reducer choice: rows >= 32 L -> a wave per leaf
+    assert (rows >= 32 * L) == (depth == 3), (rows, L)
+    split.close()
+    fused.close()
+
+
+@pytest.mark.parametrize("degree", [0, 3])
+def test_fused_backward_adam_matches_oracle(degree):
+    """Adjoint + Adam in one call against the oracle's FP64 gradient followed
+    by torch.optim.Adam in FP64 on the CPU (eps = 1e-4, where the update is
+    Lipschitz in the gradient with constant lr / eps, as in the RMSProp test);
+    then an empty batch (step 2, g = 0): both moments decay and every leaf
+    still moves by the decayed first moment, checked against the same FP64
+    optimiser."""
+    core = _core()
+    s = synth.random_tree_scene(5, degree, seed=50 + degree)
+    s = dataclasses.replace(s, sigma64=np.where(s.sigma64 < 1e-6, 0.0, s.sigma64))
+    views = synth.random_sphere_cameras(6, 3.5, 32, 32, seed=7)
+    ci, pi = synth.pixel_batch(6, 32, 32, 3000, seed=8)
+    rays = core.Rays.pixels(views, ci, pi)
+    o, d = O.camera_rays(views, ci, pi)
+    g = np.random.default_rng(9).normal(size=(ci.shape[0], 3)) * 1e-3
+    tree = core.Octree.from_scene(s)
+    st = tree.adam_state()
+    rgb, ns = tree.render(rays, nseg=True)
+    tree.backward_adam(rays, rgb, ns, torch.as_tensor(g, dtype=torch.float32, device="cuda"), st, 1, eps=1e-4)
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    gs, gh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64))
+    p_sig = torch.tensor(s.sigma.astype(np.float64), requires_grad=True)
+    p_sh = torch.tensor(s.sh.astype(np.float64), requires_grad=True)
+    opt = torch.optim.Adam([{"params": [p_sig], "lr": 0.1}, {"params": [p_sh], "lr": 0.01}], betas=(0.9, 0.999),
+                           eps=1e-4)
+    p_sig.grad, p_sh.grad = torch.tensor(gs), torch.tensor(gh)
+    opt.step()
+    ex = tree.export()
+    np.testing.assert_allclose(ex["sigma"], p_sig.detach().numpy(), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(ex["sh"], p_sh.detach().numpy(), rtol=1e-6, atol=1e-6)
+    got = _adam_state_np(st)
+    # m = (1 - beta1) g carries the gradient's FP32 error (bounded relative to max|g|)
+    for key, ref in (("m_sigma", gs), ("m_sh", gh)):
+        np.testing.assert_allclose(got[key], 0.1 * ref, rtol=1e-5, atol=1e-5 * 0.1 * np.abs(ref).max())
+    assert_square_average(got["v_sigma"], 1e-3 * gs * gs, gs, 0.999)
+    assert_square_average(got["v_sh"], 1e-3 * gh * gh, gh, 0.999)
+    # step 2 on an empty batch: g = 0 everywhere
+    empty = core.Rays.pixels(views, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    z = torch.zeros((0, 3), device="cuda")
+    before, s1 = tree.export(), got
+    tree.backward_adam(empty, z, torch.zeros(0, dtype=torch.int32, device="cuda"), z, st, 2, eps=1e-4)
+    ex2 = tree.export()
+    got2 = _adam_state_np(st)
+    bc1, bc2 = 1.0 - 0.9 ** 2, 1.0 - 0.999 ** 2
+    for th_key, m_key, v_key, lr in (("sigma", "m_sigma", "v_sigma", 0.1), ("sh", "m_sh", "v_sh", 0.01)):
+        m2, v2 = 0.9 * s1[m_key], 0.999 * s1[v_key]
+        np.testing.assert_allclose(got2[m_key], m2, rtol=1e-6, atol=0)
+        np.testing.assert_allclose(got2[v_key], v2, rtol=1e-6, atol=0)
+        want = before[th_key].astype(np.float64) - lr * (m2 / bc1) / (np.sqrt(v2 / bc2) + 1e-4)
+        np.testing.assert_allclose(ex2[th_key], want, rtol=1e-6, atol=1e-6)
+    assert np.any(ex2["sigma"] != before["sigma"])      # untouched leaves move too
+    tree.close()
+
+
+def test_adam_rejects_bad_arguments():
+    from paper_2307_15333_amd import _lib as L
+    core = _core()
+    s = synth.random_tree_scene(3, 1, seed=1)
+    views = synth.random_sphere_cameras(1, 3.5, 8, 8, seed=1)
+    empty = core.Rays.pixels(views, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    z = torch.zeros((0, 3), device="cuda")
+    zi = torch.zeros(0, dtype=torch.int32, device="cuda")
+    for storage, kw, step, code in (("f16", {}, 1, L.DOT_EUNSUPPORTED), ("f32", {"beta1": 1.0}, 1, L.DOT_EINVAL),
+                                    ("f32", {"beta2": -0.1}, 1, L.DOT_EINVAL), ("f32", {"eps": 0.0}, 1, L.DOT_EINVAL),
+                                    ("f32", {"eps": float("nan")}, 1, L.DOT_EINVAL), ("f32", {}, 0, L.DOT_EINVAL)):
+        tree = core.Octree.from_scene(s, storage)
+        st = tree.adam_state()
+        with pytest.raises(L.DotError) as e:
+            tree.adam_step(torch.zeros(tree.n_leaves, device="cuda"),
+                           torch.zeros((tree.n_leaves, 3, tree.K), device="cuda"), st, step, **kw)
+        assert e.value.code == code
+        with pytest.raises(L.DotError) as e:
+            tree.backward_adam(empty, z, zi, z, st, step, **kw)
+        assert e.value.code == code
         tree.close()
 
 
