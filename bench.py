@@ -452,18 +452,25 @@ def terrain_precision(torch, core, synth, args):
     return out
 
 
-def train_step(torch, core, synth, args):
-    """One optimisation step -- forward, MSE, hand-written backward, Adam --
-    over 2^18 random rays of 100 64x64 views of the 8.6k-leaf sphere octree (SH
-    perturbed by N(0, 0.05^2)), through the training driver."""
-    from paper_2307_15333_amd import train as TR
+def _train_setup(torch, core, synth):
     gt = synth.sphere_scene()
     start = synth.perturb_sh(gt, 0.05, seed=3)
     views = synth.training_views(100)
     gt_tree = core.Octree.from_scene(gt)
     target = gt_tree.render(core.Rays.cameras(views))           # [100*64*64, 3]
     gt_tree.close()
-    tree = core.Octree.from_scene(start)
+    return core.Octree.from_scene(start), views, target
+
+
+def train_step(torch, core, synth, args):
+    """One optimisation step -- forward, MSE, hand-written backward, Adam --
+    over 2^18 random rays of 100 64x64 views of the 8.6k-leaf sphere octree (SH
+    perturbed by N(0, 0.05^2)), through the training driver (adjoint and Adam
+    fused); then the same step through the autograd Function (DotRender),
+    PyTorch's MSE and loss.backward(), and the library's Adam on the dense
+    gradients autograd returns."""
+    from paper_2307_15333_amd import train as TR
+    tree, views, target = _train_setup(torch, core, synth)
     B = 1 << 18
     tr = TR.Trainer(tree, views, target, TR.TrainConfig(optimizer="adam", batch_rays=B, refine=False, seed=3))
     perm = tr.permutation()
@@ -481,8 +488,43 @@ def train_step(torch, core, synth, args):
     tree.close()
     l0, l1 = float(losses[0]), float(losses[-1])
     log(f"train step: {dt * 1e3:.3f} ms, {B / dt / 1e6:.1f} Mrays/s, loss {l0:.3e} -> {l1:.3e}")
+
+    # the autograd route over the same batch
+    tree, views, target = _train_setup(torch, core, synth)
+    W = H = 64
+    _, cams_raw = core.Rays._cams_tensor(views, "cuda")
+    sigma, sh = tree.plane_views()
+    p_sig, p_sh = sigma.detach().requires_grad_(), sh.detach().requires_grad_()     # alias the planes
+    state = tree.adam_state()
+    ws = None
+    a_losses = []
+
+    def step(k):
+        nonlocal ws
+        cam, pix, ids, ws = core.pixel_batch(idx, W, H, len(views), ws)
+        rays = core.Rays.pixels_device(cams_raw, len(views), cam, pix)
+        rgb = core.render_autograd(tree, p_sig, p_sh, rays)
+        loss = torch.nn.functional.mse_loss(rgb, target[ids])
+        p_sig.grad = p_sh.grad = None
+        loss.backward()
+        tree.adam_step(p_sig.grad, p_sh.grad, state, k)
+        return loss.detach()
+
+    for k in range(1, 3):
+        step(k)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(3, 3 + steps):
+        a_losses.append(step(k))
+    torch.cuda.synchronize()
+    da = (time.perf_counter() - t) / steps
+    tree.close()
+    log(f"train step (autograd Function): {da * 1e3:.3f} ms, {B / da / 1e6:.1f} Mrays/s, "
+        f"loss {float(a_losses[0]):.3e} -> {float(a_losses[-1]):.3e}")
     return {"train_step_ms": round(dt * 1e3, 3), "train_step_mrays": round(B / dt / 1e6, 1),
-            "train_rays_per_step": B, "train_loss_first_last": [l0, l1]}
+            "train_rays_per_step": B, "train_loss_first_last": [l0, l1],
+            "train_step_autograd_ms": round(da * 1e3, 3), "train_step_autograd_mrays": round(B / da / 1e6, 1),
+            "train_autograd_loss_first_last": [float(a_losses[0]), float(a_losses[-1])]}
 
 
 def alg1_loop(torch, core, synth, scene, args):

@@ -184,8 +184,13 @@ struct BwdArgs {
     const dot_adam_params* adam;
 };
 
+// The optimiser updates below are evaluated without contraction into FMAs, so
+// every kernel that applies them (the elementwise steps and the fused
+// reductions) rounds the same way and their results agree bit for bit.
+//
 // RMSProp on one parameter: v = alpha v + (1 - alpha) g^2; theta -= lr g / (sqrt(v) + eps)
 __device__ __forceinline__ void rmsprop_update(float& theta, float& v, float g, float lr, float alpha, float eps) {
+#pragma clang fp contract(off)
     v = alpha * v + (1.f - alpha) * g * g;
     theta -= lr * g / (sqrtf(v) + eps);
 }
@@ -194,6 +199,7 @@ __device__ __forceinline__ void rmsprop_update(float& theta, float& v, float g, 
 // theta -= lr (m / bc1) / (sqrt(v / bc2) + eps) with bc = 1 - b^t
 __device__ __forceinline__ void adam_update(float& theta, float& m, float& v, float g, float lr, float b1, float b2,
                                             float eps, float bc1, float bc2) {
+#pragma clang fp contract(off)
     m = b1 * m + (1.f - b1) * g;
     v = b2 * v + (1.f - b2) * g * g;
     theta -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);

@@ -582,23 +582,69 @@ struct FusedOpt {
 };
 
 template <int OPT>
+__device__ __forceinline__ void opt_apply(float& th, float& m, float& v, float g, float lr, const FusedOpt& o) {
+    if constexpr (OPT == OPT_ADAM)
+        adam_update(th, m, v, g, lr, o.d1, o.d2, o.eps, o.bc1, o.bc2);
+    else
+        rmsprop_update(th, v, g, lr, o.d1, o.eps);
+}
+
+template <int OPT>
 __device__ __forceinline__ void fused_update(float* theta, float* m, float* v, float g, float lr, const FusedOpt& o) {
-    float th = *theta, vv = *v;
-    if constexpr (OPT == OPT_ADAM) {
-        float mm = *m;
-        adam_update(th, mm, vv, g, lr, o.d1, o.d2, o.eps, o.bc1, o.bc2);
-        *m = mm;
-    } else {
-        rmsprop_update(th, vv, g, lr, o.d1, o.eps);
-    }
+    float th = *theta, vv = *v, mm = 0.f;
+    if constexpr (OPT == OPT_ADAM) mm = *m;
+    opt_apply<OPT>(th, mm, vv, g, lr, o);
+    if constexpr (OPT == OPT_ADAM) *m = mm;
     *theta = th;
     *v = vv;
+}
+
+// The optimiser step on channel ch of a block's nl leaves, whose SH sums sit
+// in stage (K per leaf, padded to KP).  Item i = (leaf r, run q) covers W
+// consecutive columns (W = 4: float4 accesses, when K % 4 == 0 and the planes
+// are 16-byte aligned).  hit[r] = 0 marks a leaf with an empty bucket (g = 0):
+// RMSProp then leaves its values exactly as they are (lr 0 / (sqrt(v) + eps)
+// = 0) and only decays the square average, so the values are neither read
+// nor written; Adam still moves such a leaf by its first moment.
+template <int K, int W, int OPT>
+__device__ __forceinline__ void fused_channel(int64_t l0, int nl, int ch, const float* stage, const int* hit,
+                                              float* __restrict__ sh, int stride, const FusedOpt& o) {
+    constexpr int KP = K + 1;
+    constexpr int NV = 3 * K;
+    constexpr int Q = K / W;
+    static_assert(K % W == 0, "runs tile the channel");
+    struct alignas(4 * W) Run {
+        float x[W];
+    };
+    for (int i = threadIdx.x; i < nl * Q; i += RED_BLOCK) {
+        const int r = i / Q, q = i - r * Q;
+        const int64_t col = (int64_t)ch * K + q * W;
+        Run* vp = reinterpret_cast<Run*>(o.v_sh + (l0 + r) * NV + col);
+        Run v = *vp;
+        if (OPT == OPT_RMSPROP && !hit[r]) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                float th = 0.f, m = 0.f;
+                opt_apply<OPT>(th, m, v.x[e], 0.f, o.lr_sh, o);
+            }
+        } else {
+            Run* tp = reinterpret_cast<Run*>(sh + (l0 + r) * stride + col);
+            Run* mp = reinterpret_cast<Run*>(o.m_sh + (l0 + r) * NV + col);
+            Run th = *tp, m{};
+            if constexpr (OPT == OPT_ADAM) m = *mp;
+#pragma unroll
+            for (int e = 0; e < W; ++e) opt_apply<OPT>(th.x[e], m.x[e], v.x[e], stage[r * KP + q * W + e], o.lr_sh, o);
+            *tp = th;
+            if constexpr (OPT == OPT_ADAM) *mp = m;
+        }
+        *vp = v;
+    }
 }
 
 // The same reduction feeding the optimiser for every leaf (untouched leaves
 // have g = 0: RMSProp only decays their square averages, Adam still moves
 // them by its decayed first moment).
-template <int DEG, int OPT>
+template <int DEG, int OPT, int W>
 __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const uint32_t* __restrict__ offset,
                                                               const uint32_t* __restrict__ base0,
                                                               const uint32_t* __restrict__ count,
@@ -610,14 +656,21 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const u
     constexpr int NV = 3 * K;
     constexpr int KP = K + 1;
     __shared__ float stage[RED_BLOCK * KP];
+    __shared__ int hit[RED_BLOCK];
     const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
     const int64_t l = l0 + threadIdx.x;
     float gs = 0.f, acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.f;
     if (l < L) {
-        bucket_sum<DEG>(l, offset, base0, count, cursor, rows, gs, acc);
-        fused_update<OPT>(sigma + l, o.m_sigma + l, o.v_sigma + l, gs, o.lr_sigma, o);
+        const bool h = bucket_sum<DEG>(l, offset, base0, count, cursor, rows, gs, acc);
+        hit[threadIdx.x] = h;
+        if (OPT == OPT_RMSPROP && !h) {
+            float th = 0.f, m = 0.f;          // g = 0: sigma stays, its square average decays
+            opt_apply<OPT>(th, m, o.v_sigma[l], 0.f, o.lr_sigma, o);
+        } else {
+            fused_update<OPT>(sigma + l, o.m_sigma + l, o.v_sigma + l, gs, o.lr_sigma, o);
+        }
     }
     const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
 #pragma unroll
@@ -626,12 +679,7 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const u
 #pragma unroll
         for (int k = 0; k < K; ++k) stage[threadIdx.x * KP + k] = acc[ch * K + k];
         __syncthreads();
-        for (int i = threadIdx.x; i < nl * K; i += RED_BLOCK) {
-            const int r = i / K, k = i - r * K;
-            const int64_t q = (l0 + r) * NV + (int64_t)ch * K + k;
-            fused_update<OPT>(sh + (l0 + r) * stride + ch * K + k, o.m_sh + q, o.v_sh + q, stage[r * KP + k],
-                              o.lr_sh, o);
-        }
+        fused_channel<K, W, OPT>(l0, (int)nl, ch, stage, hit, sh, stride, o);
     }
 }
 
@@ -870,14 +918,30 @@ static void launch_bwd_fused(const dot_tree& t, const BwdArgs& a, const uint32_t
                              const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
     const int64_t L = t.n_leaves;
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
+    constexpr int K = (DEG + 1) * (DEG + 1);
     float* sg = static_cast<float*>(t.sigma);
     float* sh = static_cast<float*>(t.sh);
+    const FusedOpt o = fused_opt(a);
+    auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    const bool vec = K % 4 == 0 && t.sh_stride % 4 == 0 && a16(sh) && a16(o.v_sh) && (!a.adam || a16(o.m_sh));
+    const dim3 g(rg), b(RED_BLOCK);
+    if constexpr (K % 4 == 0) {
+        if (vec) {
+            if (a.adam)
+                hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_ADAM, 4>), g, b, 0, s, L, offset, base0, count, cursor,
+                                   rows, sg, sh, t.sh_stride, o);
+            else
+                hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_RMSPROP, 4>), g, b, 0, s, L, offset, base0, count,
+                                   cursor, rows, sg, sh, t.sh_stride, o);
+            return;
+        }
+    }
     if (a.adam)
-        hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_ADAM>), dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count,
-                           cursor, rows, sg, sh, t.sh_stride, fused_opt(a));
+        hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_ADAM, 1>), g, b, 0, s, L, offset, base0, count, cursor, rows, sg,
+                           sh, t.sh_stride, o);
     else
-        hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_RMSPROP>), dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0,
-                           count, cursor, rows, sg, sh, t.sh_stride, fused_opt(a));
+        hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_RMSPROP, 1>), g, b, 0, s, L, offset, base0, count, cursor, rows,
+                           sg, sh, t.sh_stride, o);
 }
 
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s) {

@@ -214,23 +214,41 @@ def _adam_state_np(st):
     return {k: v.cpu().numpy().astype(np.float64) for k, v in st.items()}
 
 
-@pytest.mark.parametrize("depth,n_rays", [(3, 20000), (6, 3000)])
-def test_fused_backward_adam_bit_matches_split_path(depth, n_rays):
-    """Adjoint + Adam in one call against dot_render_backward into zeroed
-    arrays followed by dot_adam_step, on two copies of one tree replaying the
-    same forward records (no overflow, so both sides sum every bucket in the
-    same order): parameters and both moments bit for bit, over two steps.
-    The small tree under the large batch is reduced a wave per leaf, the large
-    tree under the small batch a thread per leaf."""
+def _state_like(st, misalign):
+    """The optimiser state, or copies of it 4 bytes off 16-byte alignment."""
+    if not misalign:
+        return st
+    out = {}
+    for k, v in st.items():
+        buf = torch.zeros(v.numel() + 1, dtype=v.dtype, device=v.device)
+        out[k] = buf[1:].view(v.shape)
+    return out
+
+
+@pytest.mark.parametrize("depth,n_rays,degree,opt,misalign", [
+    (3, 20000, 2, "adam", False), (6, 3000, 2, "adam", False), (6, 3000, 3, "adam", False),
+    (3, 20000, 1, "rmsprop", False), (6, 3000, 3, "rmsprop", False), (6, 3000, 2, "rmsprop", False),
+    (6, 3000, 3, "rmsprop", True)])
+def test_fused_backward_bit_matches_split_path(depth, n_rays, degree, opt, misalign):
+    """Adjoint + optimiser in one call against dot_render_backward into zeroed
+    arrays followed by the optimiser step, on two copies of one tree replaying
+    the same forward records (no overflow, so both sides sum every bucket in
+    the same order): parameters and optimiser state bit for bit, over two
+    steps.  The small trees under the large batch are reduced a wave per leaf,
+    the large trees under the small batch a thread per leaf -- with float4
+    runs at degrees 1 and 3 (16-byte aligned state), scalar runs at degree 2 or
+    with misaligned state -- and RMSProp there skips the values of leaves with
+    empty buckets."""
     core = _core()
-    s = synth.random_tree_scene(depth, 2, seed=60 + depth)
+    s = synth.random_tree_scene(depth, degree, seed=60 + depth)
     views = synth.random_sphere_cameras(6, 3.5, 64, 64, seed=3)
     ci, pi = synth.pixel_batch(6, 64, 64, n_rays, seed=4)
     rays = core.Rays.pixels(views, ci, pi)
     g = torch.as_tensor(np.random.default_rng(5).normal(size=(ci.shape[0], 3)) * 1e-3, dtype=torch.float32,
                         device="cuda")
     split, fused = core.Octree.from_scene(s), core.Octree.from_scene(s)
-    st_a, st_b = split.adam_state(), fused.adam_state()
+    new_state = (lambda t: t.adam_state()) if opt == "adam" else (lambda t: t.rmsprop_state())
+    st_a, st_b = new_state(split), _state_like(new_state(fused), misalign)
     rec = torch.empty(core.Octree.records_bytes(rays.n_rays), dtype=torch.uint8, device="cuda")
     gs = torch.zeros(split.n_leaves, device="cuda")
     gh = torch.zeros((split.n_leaves, 3, split.K), device="cuda")
@@ -241,14 +259,21 @@ def test_fused_backward_adam_bit_matches_split_path(depth, n_rays):
         gs.zero_()
         gh.zero_()
         split.backward(rays, rgb, ns, g, gs, gh, leaf_count=cnt, records=rec)
-        split.adam_step(gs, gh, st_a, step)
-        fused.backward_adam(rays, rgb, ns, g, st_b, step, leaf_count=cnt, records=rec)
+        if opt == "adam":
+            split.adam_step(gs, gh, st_a, step)
+            fused.backward_adam(rays, rgb, ns, g, st_b, step, leaf_count=cnt, records=rec)
+        else:
+            split.rmsprop_step(gs, gh, st_a)
+            fused.backward_rmsprop(rays, rgb, ns, g, st_b, leaf_count=cnt, records=rec)
         ea, eb = split.export(), fused.export()
         assert np.array_equal(ea["sigma"], eb["sigma"]) and np.array_equal(ea["sh"], eb["sh"])
         for k in st_a:
             assert torch.equal(st_a[k], st_b[k]), k
-    rows, L = int(cnt.sum()), split.n_leaves               # reducer choice: rows >= 32 L -> a wave per leaf
+    per_leaf = cnt.sum(0)
+    rows, L = int(per_leaf.sum()), split.n_leaves            # reducer choice: rows >= 32 L -> a wave per leaf
     assert (rows >= 32 * L) == (depth == 3), (rows, L)
+    if depth == 6:
+        assert int((per_leaf == 0).sum()) > 0                # some buckets are empty
     split.close()
     fused.close()
 
