@@ -368,13 +368,26 @@ class DotRender(torch.autograd.Function):
 
     ``sigma``/``sh`` are the tree's plane views (see Octree.plane_views); the
     gradients returned are dense FP32 [L] and [L,3,K].  A ``signal`` buffer, if
-    given, receives the fused training signal of the forward pass."""
+    given, receives the fused training signal of the forward pass.  On an FP32
+    tree the forward is the training forward: it also counts each leaf's
+    segments and records up to ``record_segments`` segments per ray, which the
+    adjoint replays instead of traversing the tree again (rays with more are
+    re-traversed for the rest); ``record_segments=0`` or reduced-precision
+    leaves give the plain forward and an adjoint by re-traversal."""
 
     @staticmethod
-    def forward(ctx, sigma, sh, tree, rays, bg, t_stop, signal=None, signal_mode="max"):
-        rgb, nseg = tree.render(rays, bg=bg, t_stop=t_stop, nseg=True, signal=signal, signal_mode=signal_mode)
+    def forward(ctx, sigma, sh, tree, rays, bg, t_stop, signal=None, signal_mode="max", record_segments=32):
+        cnt = rec = None
+        if tree.storage == "f32" and record_segments > 0:
+            rec = torch.empty(Octree.records_bytes(rays.n_rays, record_segments), dtype=torch.uint8,
+                              device=tree.device)
+            rgb, nseg, cnt = tree.render_train(rays, bg=bg, t_stop=t_stop, signal=signal, signal_mode=signal_mode,
+                                               records=rec)
+        else:
+            rgb, nseg = tree.render(rays, bg=bg, t_stop=t_stop, nseg=True, signal=signal, signal_mode=signal_mode)
         ctx.save_for_backward(rgb, nseg)
         ctx.tree, ctx.rays, ctx.bg, ctx.t_stop = tree, rays, bg, t_stop
+        ctx.cnt, ctx.rec = cnt, rec
         return rgb
 
     @staticmethod
@@ -384,9 +397,12 @@ class DotRender(torch.autograd.Function):
         Ln = tree.n_leaves
         gs = torch.zeros(Ln, dtype=torch.float32, device=rgb.device)
         gh = torch.zeros((Ln, 3, tree.K), dtype=torch.float32, device=rgb.device)
-        tree.backward(ctx.rays, rgb, nseg, grad_rgb.contiguous().float(), gs, gh, bg=ctx.bg, t_stop=ctx.t_stop)
-        return gs, gh, None, None, None, None, None, None
+        tree.backward(ctx.rays, rgb, nseg, grad_rgb.contiguous().float(), gs, gh, bg=ctx.bg, t_stop=ctx.t_stop,
+                      leaf_count=ctx.cnt, records=ctx.rec)
+        ctx.cnt = ctx.rec = None
+        return gs, gh, None, None, None, None, None, None, None
 
 
-def render_autograd(tree, sigma, sh, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max"):
-    return DotRender.apply(sigma, sh, tree, rays, bg, t_stop, signal, signal_mode)
+def render_autograd(tree, sigma, sh, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max",
+                    record_segments=32):
+    return DotRender.apply(sigma, sh, tree, rays, bg, t_stop, signal, signal_mode, record_segments)

@@ -174,6 +174,8 @@ static void release(dot_tree* t) {
     t->alloc.put(t->palette);
     t->alloc.put(t->links);
     t->links = nullptr;
+    if (t->host_rb) (void)hipHostFree(t->host_rb);
+    t->host_rb = nullptr;
     t->child = nullptr;
     t->sigma = nullptr;
     t->sh = nullptr;

@@ -77,6 +77,9 @@ struct dot_tree {
     int32_t palette_bits = 0;
     uint32_t* links = nullptr;      // device [n_leaves][6], null when off or not built
     bool links_on = true;           // keep face-neighbour links (rebuilt after refinement)
+    // pinned host words the adjoint reads back (allocated on first use; one
+    // adjoint at a time per tree, like every other call that uses its scratch)
+    mutable uint32_t* host_rb = nullptr;
 
     dot::TreeView view() const {
         dot::TreeView v;

@@ -877,9 +877,11 @@ static void launch_emit(int deg, const TreeView& tv, const RayBatch& rb, const B
     }
 }
 
-// c = a + b elementwise (a bucket's two regions)
+// c = a + b elementwise (a bucket's two regions); the first thread also copies
+// *w_src to *w_dst (a word the host reads back together with the scan total)
 __global__ void add_u32_kernel(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint32_t* __restrict__ c,
-                               int64_t n) {
+                               int64_t n, const uint32_t* __restrict__ w_src, uint32_t* __restrict__ w_dst) {
+    if (w_src && blockIdx.x == 0 && threadIdx.x == 0) *w_dst = *w_src;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         c[i] = a[i] + b[i];
 }
@@ -987,17 +989,24 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
             default: hipLaunchKernelGGL(bwd_count_kernel<DOT_BF16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
         }
     } else {
-        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, base0, count, total, L);
+        // tot[1] = the forward's overflow count (zero without records)
+        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, base0, count, total, L,
+                           a.rec.a ? a.rec.overflow : nullptr, tot + 1);
     }
     hipError_t e = scan_u32(total, offset, L, bsum, tot, s);
-    uint32_t m = 0, overflow = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&m, tot, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && a.rec.a) e = hipMemcpyAsync(&overflow, a.rec.overflow, 4, hipMemcpyDeviceToHost, s);
+    // the row total and the overflow count in one copy into pinned memory, one wait
+    if (e == hipSuccess && !t.host_rb) {
+        void* h = nullptr;
+        e = hipHostMalloc(&h, 16, hipHostMallocDefault);
+        if (e == hipSuccess) t.host_rb = static_cast<uint32_t*>(h);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(t.host_rb, tot, a.rec.a ? 8 : 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         drop();
         return e;
     }
+    const uint32_t m = t.host_rb[0], overflow = a.rec.a ? t.host_rb[1] : 0u;
     float* rows = nullptr;
     if ((double)m * rs * 4 <= kBucketBytesMax) rows = static_cast<float*>(t.alloc.get((size_t)std::max<uint32_t>(m, 1) * rs * 4));
     if (!rows) {

@@ -71,7 +71,11 @@ def test_backward_random_tree_explicit_rays():
     assert _rel(gs, rs) <= GTOL and _rel(gh, rh) <= GTOL
 
 
-def test_autograd_function_mse():
+@pytest.mark.parametrize("record_segments", [32, 2, 0])
+def test_autograd_function_mse(record_segments):
+    """Through the autograd Function: with the training forward's records
+    (32: every ray fits; 2: most rays are re-traversed past their records)
+    and with the plain forward (0)."""
     core = _core()
     s = synth.sphere_scene()
     cams = synth.cameras([(40.0, 30.0, 4.0, 48, 40)])
@@ -81,7 +85,7 @@ def test_autograd_function_mse():
     sigma = sig_v.detach().requires_grad_()
     sh = sh_v.detach().requires_grad_()
     target = torch.full((rays.n_rays, 3), 0.4, device="cuda")
-    rgb = core.render_autograd(tree, sigma, sh, rays, t_stop=0.0)
+    rgb = core.render_autograd(tree, sigma, sh, rays, t_stop=0.0, record_segments=record_segments)
     loss = torch.mean((rgb - target) ** 2)
     loss.backward()
     assert sigma.grad.shape == sigma.shape and sh.grad.shape == sh.shape

@@ -78,7 +78,7 @@ def _tile_shift(n, total):
 
 
 @pytest.mark.parametrize("n_cams,W,H,n", [(3, 40, 24, 0), (3, 40, 24, 1), (3, 40, 24, 2000), (100, 800, 800, 1 << 20),
-                                          (5, 37, 53, 9805)])
+                                          (5, 37, 53, 9805), (100, 64, 64, 1 << 18), (60, 128, 128, 900000)])
 def test_pixel_batch_orders_a_batch_by_tile(n_cams, W, H, n):
     core = _core()
     total = n_cams * W * H
