@@ -427,8 +427,7 @@ int dot_render_train(dot_tree_t t, const dot_rays* rays, const dot_render_opts* 
     rc = records_for(records, records_bytes, rb.n_rays, a.rec, "dot_render_train");
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_fill_u32(leaf_count_out, 2 * t->n_leaves, s);
-    if (e == hipSuccess && a.rec.a) e = launch_fill_u32(a.rec.overflow, 1, s);
+    hipError_t e = launch_fill_u32(leaf_count_out, 2 * t->n_leaves, s, a.rec.a ? a.rec.overflow : nullptr);
     if (e == hipSuccess) e = launch_render_fwd(*t, rb, a, s);
     if (e != hipSuccess) return hip_fail(e, "dot_render_train: launch");
     return DOT_OK;

@@ -210,7 +210,7 @@ __device__ __forceinline__ void adam_update(float& theta, float& m, float& v, fl
 
 hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArgs& a, hipStream_t s);
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s, uint32_t* word = nullptr);
 hipError_t launch_encode_planes(int storage, const float* src, void* dst, int64_t rows, int src_cols,
                                 int dst_stride, hipStream_t s);
 hipError_t launch_decode_planes(int storage, const void* src, float* dst, int64_t rows, int dst_cols,

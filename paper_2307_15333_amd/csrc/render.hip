@@ -795,14 +795,17 @@ static void launch_reduce_wave(const dot_tree& t, const BwdArgs& a, const uint32
 // buckets holding at least this many rows on average are reduced a wave per leaf
 static constexpr uint32_t kWaveRowsPerLeaf = 32;
 
-__global__ void fill_u32_kernel(uint32_t* p, int64_t n) {
+// p[0, n) = 0, and *word = 0 when given (one launch for an array and a counter)
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t* word) {
+    if (word && blockIdx.x == 0 && threadIdx.x == 0) *word = 0u;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
 }
 
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s, p, n);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s, uint32_t* word) {
+    if (n <= 0 && !word) return hipSuccess;
+    const int64_t g = std::max<int64_t>((n + 255) / 256, 1);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>(g, 65536)), dim3(256), 0, s, p, n, word);
     return hipGetLastError();
 }
 
@@ -877,13 +880,17 @@ static void launch_emit(int deg, const TreeView& tv, const RayBatch& rb, const B
     }
 }
 
-// c = a + b elementwise (a bucket's two regions); the first thread also copies
-// *w_src to *w_dst (a word the host reads back together with the scan total)
+// c = a + b elementwise (a bucket's two regions) and z = 0 (the bucket
+// cursors); the first thread also copies *w_src to *w_dst (a word the host
+// reads back together with the scan total)
 __global__ void add_u32_kernel(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint32_t* __restrict__ c,
-                               int64_t n, const uint32_t* __restrict__ w_src, uint32_t* __restrict__ w_dst) {
+                               uint32_t* __restrict__ z, int64_t n, const uint32_t* __restrict__ w_src,
+                               uint32_t* __restrict__ w_dst) {
     if (w_src && blockIdx.x == 0 && threadIdx.x == 0) *w_dst = *w_src;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         c[i] = a[i] + b[i];
+        z[i] = 0u;
+    }
 }
 
 // bucket scratch beyond this many bytes falls back to the atomic adjoint
@@ -906,7 +913,7 @@ static hipError_t bwd_fused_dense(const dot_tree& t, const RayBatch& rb, const B
     a.grad_sh = g + t.n_leaves;
     const int64_t n = t.n_leaves * (1 + nv);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s,
-                       reinterpret_cast<uint32_t*>(g), n);
+                       reinterpret_cast<uint32_t*>(g), n, nullptr);
     hipError_t e = rb.n_tiles ? bwd_atomic(t, rb, a, grid, s) : hipGetLastError();
     if (e == hipSuccess)
         e = a.adam ? launch_adam(t, a.grad_sigma, a.grad_sh, a.m_sigma, a.v_sigma, a.m_sh, a.v_sh, *a.adam, s)
@@ -980,9 +987,9 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         return fused ? bwd_fused_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
     unsigned fg = (unsigned)std::min<int64_t>((L + 255) / 256, 65536);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L);
     if (!a.leaf_count) {
-        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count_own, L);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L, nullptr);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count_own, L, nullptr);
         switch (t.storage) {
             case DOT_F32: hipLaunchKernelGGL(bwd_count_kernel<DOT_F32>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
             case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
@@ -990,7 +997,7 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         }
     } else {
         // tot[1] = the forward's overflow count (zero without records)
-        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, base0, count, total, L,
+        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, base0, count, total, cursor, L,
                            a.rec.a ? a.rec.overflow : nullptr, tot + 1);
     }
     hipError_t e = scan_u32(total, offset, L, bsum, tot, s);

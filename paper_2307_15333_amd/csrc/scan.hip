@@ -12,8 +12,9 @@ constexpr int TPB = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 
+template <int NT = TPB>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& total) {
-    __shared__ uint32_t wsum[TPB / 64];
+    __shared__ uint32_t wsum[NT / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t x = v;
 #pragma unroll
@@ -26,7 +27,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& t
     uint32_t base = 0;
     total = 0;
 #pragma unroll
-    for (int j = 0; j < TPB / 64; ++j) {
+    for (int j = 0; j < NT / 64; ++j) {
         if (j < w) base += wsum[j];
         total += wsum[j];
     }
@@ -85,14 +86,17 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const u
     }
 }
 
-// small arrays: one workgroup walks the tiles in order, carrying the running
-// total (one launch instead of three)
+// small arrays: one workgroup of 1024 threads walks tiles of 16K elements in
+// order, carrying the running total (one launch instead of three; an array of
+// up to 16K elements is one tile, so one load round trip)
+constexpr int SINGLE_TPB = 1024;
+constexpr int64_t SINGLE_TILE = (int64_t)SINGLE_TPB * SCAN_ITEMS;
 constexpr int64_t SCAN_SINGLE_MAX = 16 * SCAN_TILE;
 
-__global__ void k_scan_single(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ out,
-                              uint32_t* __restrict__ tot) {
+__global__ __launch_bounds__(SINGLE_TPB) void k_scan_single(const uint32_t* __restrict__ in, int64_t n,
+                                                            uint32_t* __restrict__ out, uint32_t* __restrict__ tot) {
     uint32_t carry = 0;
-    for (int64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+    for (int64_t t0 = 0; t0 < n; t0 += SINGLE_TILE) {
         const int64_t base = t0 + (int64_t)threadIdx.x * SCAN_ITEMS;
         uint32_t v[SCAN_ITEMS];
         uint32_t acc = 0;
@@ -103,7 +107,7 @@ __global__ void k_scan_single(const uint32_t* __restrict__ in, int64_t n, uint32
             acc += v[j];
         }
         uint32_t total;
-        uint32_t off = block_exclusive_scan(acc, total) + carry;
+        uint32_t off = block_exclusive_scan<SINGLE_TPB>(acc, total) + carry;
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             int64_t i = base + j;
@@ -122,7 +126,7 @@ int64_t scan_scratch_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE +
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (n <= SCAN_SINGLE_MAX) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(TPB), 0, s, in, n, out, tot);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SINGLE_TPB), 0, s, in, n, out, tot);
         return hipGetLastError();
     }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
