@@ -376,7 +376,7 @@ class DotRender(torch.autograd.Function):
     leaves give the plain forward and an adjoint by re-traversal."""
 
     @staticmethod
-    def forward(ctx, sigma, sh, tree, rays, bg, t_stop, signal=None, signal_mode="max", record_segments=32):
+    def forward(ctx, sigma, sh, tree, rays, bg, t_stop, signal=None, signal_mode="max", record_segments=96):
         cnt = rec = None
         if tree.storage == "f32" and record_segments > 0:
             rec = torch.empty(Octree.records_bytes(rays.n_rays, record_segments), dtype=torch.uint8,
@@ -404,5 +404,5 @@ class DotRender(torch.autograd.Function):
 
 
 def render_autograd(tree, sigma, sh, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max",
-                    record_segments=32):
+                    record_segments=96):
     return DotRender.apply(sigma, sh, tree, rays, bg, t_stop, signal, signal_mode, record_segments)

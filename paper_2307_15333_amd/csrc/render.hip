@@ -589,14 +589,16 @@ __device__ __forceinline__ void opt_apply(float& th, float& m, float& v, float g
         rmsprop_update(th, v, g, lr, o.d1, o.eps);
 }
 
+// theta[ti], v[si] (and Adam's m[si]) updated in place with gradient g
 template <int OPT>
-__device__ __forceinline__ void fused_update(float* theta, float* m, float* v, float g, float lr, const FusedOpt& o) {
-    float th = *theta, vv = *v, mm = 0.f;
-    if constexpr (OPT == OPT_ADAM) mm = *m;
+__device__ __forceinline__ void fused_update(float* theta, int64_t ti, float* m, float* v, int64_t si, float g,
+                                             float lr, const FusedOpt& o) {
+    float th = theta[ti], vv = v[si], mm = 0.f;
+    if constexpr (OPT == OPT_ADAM) mm = m[si];
     opt_apply<OPT>(th, mm, vv, g, lr, o);
-    if constexpr (OPT == OPT_ADAM) *m = mm;
-    *theta = th;
-    *v = vv;
+    if constexpr (OPT == OPT_ADAM) m[si] = mm;
+    theta[ti] = th;
+    v[si] = vv;
 }
 
 // The optimiser step on channel ch of a block's nl leaves, whose SH sums sit
@@ -629,13 +631,12 @@ __device__ __forceinline__ void fused_channel(int64_t l0, int nl, int ch, const 
             }
         } else {
             Run* tp = reinterpret_cast<Run*>(sh + (l0 + r) * stride + col);
-            Run* mp = reinterpret_cast<Run*>(o.m_sh + (l0 + r) * NV + col);
             Run th = *tp, m{};
-            if constexpr (OPT == OPT_ADAM) m = *mp;
+            if constexpr (OPT == OPT_ADAM) m = *reinterpret_cast<const Run*>(o.m_sh + (l0 + r) * NV + col);
 #pragma unroll
             for (int e = 0; e < W; ++e) opt_apply<OPT>(th.x[e], m.x[e], v.x[e], stage[r * KP + q * W + e], o.lr_sh, o);
             *tp = th;
-            if constexpr (OPT == OPT_ADAM) *mp = m;
+            if constexpr (OPT == OPT_ADAM) *reinterpret_cast<Run*>(o.m_sh + (l0 + r) * NV + col) = m;
         }
         *vp = v;
     }
@@ -669,7 +670,7 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const u
             float th = 0.f, m = 0.f;          // g = 0: sigma stays, its square average decays
             opt_apply<OPT>(th, m, o.v_sigma[l], 0.f, o.lr_sigma, o);
         } else {
-            fused_update<OPT>(sigma + l, o.m_sigma + l, o.v_sigma + l, gs, o.lr_sigma, o);
+            fused_update<OPT>(sigma, l, o.m_sigma, o.v_sigma, l, gs, o.lr_sigma, o);
         }
     }
     const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
@@ -733,10 +734,8 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
         for (int j = 0; j < NV; ++j)
             if (lane == j) mine = acc[j];
         if constexpr (OPT != OPT_NONE) {
-            if (lane < NV)
-                fused_update<OPT>(sh + l * stride + lane, o.m_sh + l * NV + lane, o.v_sh + l * NV + lane, mine,
-                                  o.lr_sh, o);
-            if (lane == 0) fused_update<OPT>(sigma + l, o.m_sigma + l, o.v_sigma + l, gs, o.lr_sigma, o);
+            if (lane < NV) fused_update<OPT>(sh, l * stride + lane, o.m_sh, o.v_sh, l * NV + lane, mine, o.lr_sh, o);
+            if (lane == 0) fused_update<OPT>(sigma, l, o.m_sigma, o.v_sigma, l, gs, o.lr_sigma, o);
         } else if (m > 0) {
             if (lane < NV && mine != 0.f) gsh[l * NV + lane] += mine;
             if (lane == 0) gsig[l] += gs;

@@ -48,7 +48,10 @@ class TrainConfig:
     reinit: bool = False            # ablation: new leaves start at zero instead of fused values
     refine: bool = True
     fused: bool = True              # the optimiser step applied inside the adjoint's per-leaf reduction
-    record_segments: int = 96       # segments per ray the forward records for the adjoint's replay
+    # segments per ray the forward records for the adjoint's replay; a ray with more is re-traversed for the rest
+    # by a few long-running waves at the end of the adjoint, so the capacity covers the deepest rays (the buffer,
+    # n x capacity x 28 B, is address space: only the recorded slots are written)
+    record_segments: int = 256
     bg: tuple = (1.0, 1.0, 1.0)
     t_stop: float = 1e-4
     seed: int = 0

@@ -71,10 +71,10 @@ def test_backward_random_tree_explicit_rays():
     assert _rel(gs, rs) <= GTOL and _rel(gh, rh) <= GTOL
 
 
-@pytest.mark.parametrize("record_segments", [32, 2, 0])
+@pytest.mark.parametrize("record_segments", [96, 2, 0])
 def test_autograd_function_mse(record_segments):
     """Through the autograd Function: with the training forward's records
-    (32: every ray fits; 2: most rays are re-traversed past their records)
+    (96: every ray fits; 2: most rays are re-traversed past their records)
     and with the plain forward (0)."""
     core = _core()
     s = synth.sphere_scene()
