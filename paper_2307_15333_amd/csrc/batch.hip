@@ -50,22 +50,25 @@ __global__ void k_pb_zero(uint32_t* __restrict__ p, int64_t n) {
         p[i] = 0u;
 }
 
-__global__ void k_pb_count(const int64_t* __restrict__ ids, int64_t n, PixelGeo g, uint32_t* __restrict__ count) {
+// Many bins: one global atomic per ray, whose return value is the ray's rank
+// in its bin, so the scatter needs none (offset[bin] + rank).
+__global__ void k_pb_count(const int64_t* __restrict__ ids, int64_t n, PixelGeo g, uint32_t* __restrict__ count,
+                           uint32_t* __restrict__ rank) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         int64_t id = ids[r];
         int32_t cam, pix;
-        atomicAdd(&count[tile_bin(id, g, cam, pix)], 1u);
+        rank[r] = atomicAdd(&count[tile_bin(id, g, cam, pix)], 1u);
     }
 }
 
-__global__ void k_pb_scatter(const int64_t* __restrict__ ids, int64_t n, PixelGeo g, uint32_t* __restrict__ cursor,
-                             int32_t* __restrict__ cam_out, int32_t* __restrict__ pix_out,
-                             int64_t* __restrict__ id_out) {
+__global__ void k_pb_scatter(const int64_t* __restrict__ ids, int64_t n, PixelGeo g, const uint32_t* __restrict__ offset,
+                             const uint32_t* __restrict__ rank, int32_t* __restrict__ cam_out,
+                             int32_t* __restrict__ pix_out, int64_t* __restrict__ id_out) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         int64_t id = ids[r];
         int32_t cam, pix;
         const int64_t b = tile_bin(id, g, cam, pix);
-        const uint32_t pos = atomicAdd(&cursor[b], 1u);
+        const uint32_t pos = offset[b] + rank[r];
         cam_out[pos] = cam;
         pix_out[pos] = pix;
         if (id_out) id_out[pos] = id;
@@ -143,7 +146,8 @@ unsigned grid_of(int64_t n) {
 
 size_t pixel_batch_workspace_bytes(int64_t n, int32_t W, int32_t H, int32_t n_cams) {
     const PixelGeo g = make_geo(n, W, H, n_cams);
-    return sizeof(uint32_t) * (size_t)(2 * g.bins + scan_scratch_elems(g.bins) + 1);
+    const int64_t ranks = g.bins <= LDS_BINS ? 0 : n;    // the many-bin path keeps each ray's rank
+    return sizeof(uint32_t) * (size_t)(2 * g.bins + scan_scratch_elems(g.bins) + 1 + ranks);
 }
 
 hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t H, int32_t n_cams, int32_t* cam_out,
@@ -154,20 +158,21 @@ hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t 
     uint32_t* cursor = count + g.bins;
     uint32_t* bsum = cursor + g.bins;
     uint32_t* tot = bsum + scan_scratch_elems(g.bins);
+    uint32_t* rank = tot + 1;
     const bool lds = g.bins <= LDS_BINS;
     const unsigned gl = (unsigned)((n + CHUNK - 1) / CHUNK);
     hipLaunchKernelGGL(k_pb_zero, dim3(grid_of(g.bins)), dim3(256), 0, s, count, g.bins);
     if (lds)
         hipLaunchKernelGGL(k_pb_count_lds, dim3(gl), dim3(256), 0, s, ids, n, g, count);
     else
-        hipLaunchKernelGGL(k_pb_count, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, count);
+        hipLaunchKernelGGL(k_pb_count, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, count, rank);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = scan_u32(count, cursor, g.bins, bsum, tot, s);
     if (e != hipSuccess) return e;
     if (lds)
         hipLaunchKernelGGL(k_pb_scatter_lds, dim3(gl), dim3(256), 0, s, ids, n, g, cursor, cam_out, pix_out, id_out);
     else
-        hipLaunchKernelGGL(k_pb_scatter, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, cursor, cam_out, pix_out,
+        hipLaunchKernelGGL(k_pb_scatter, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, cursor, rank, cam_out, pix_out,
                            id_out);
     return hipGetLastError();
 }

@@ -64,26 +64,69 @@ __global__ void k_scan_bsums(uint32_t* __restrict__ bsum, int64_t nb, uint32_t* 
     if (threadIdx.x == 0) *tot = total;
 }
 
+// A thread's SCAN_ITEMS consecutive elements from base: four 16-byte loads when
+// VEC (both arrays 16-byte aligned) and the run lies inside the array, else
+// element by element; store_run writes the exclusive prefix from `off`.
+template <bool VEC>
+__device__ __forceinline__ uint32_t load_run(const uint32_t* __restrict__ in, int64_t base, int64_t n,
+                                             uint32_t (&v)[SCAN_ITEMS]) {
+    if (VEC && base + SCAN_ITEMS <= n) {
+        const uint4* p = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS / 4; ++q) {
+            const uint4 x = p[q];
+            v[4 * q] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) v[j] = base + j < n ? in[base + j] : 0u;
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) acc += v[j];
+    return acc;
+}
+
+template <bool VEC>
+__device__ __forceinline__ void store_run(uint32_t* __restrict__ out, int64_t base, int64_t n,
+                                          const uint32_t (&v)[SCAN_ITEMS], uint32_t off) {
+    if (VEC && base + SCAN_ITEMS <= n) {
+        uint4* p = reinterpret_cast<uint4*>(out + base);
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS / 4; ++q) {
+            uint4 x;
+            x.x = off;
+            off += v[4 * q];
+            x.y = off;
+            off += v[4 * q + 1];
+            x.z = off;
+            off += v[4 * q + 2];
+            x.w = off;
+            off += v[4 * q + 3];
+            p[q] = x;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            if (base + j < n) out[base + j] = off;
+            off += v[j];
+        }
+    }
+}
+
+template <bool VEC>
 __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ bsum,
                              uint32_t* __restrict__ out) {
     // each thread owns SCAN_ITEMS consecutive elements of the tile
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
-    uint32_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int64_t i = base + j;
-        v[j] = i < n ? in[i] : 0u;
-        acc += v[j];
-    }
+    const uint32_t acc = load_run<VEC>(in, base, n, v);
     uint32_t total;
-    uint32_t off = block_exclusive_scan(acc, total) + bsum[blockIdx.x];
-#pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int64_t i = base + j;
-        if (i < n) out[i] = off;
-        off += v[j];
-    }
+    const uint32_t off = block_exclusive_scan(acc, total) + bsum[blockIdx.x];
+    store_run<VEC>(out, base, n, v, off);
 }
 
 // small arrays: one workgroup of 1024 threads walks tiles of 16K elements in
@@ -93,27 +136,17 @@ constexpr int SINGLE_TPB = 1024;
 constexpr int64_t SINGLE_TILE = (int64_t)SINGLE_TPB * SCAN_ITEMS;
 constexpr int64_t SCAN_SINGLE_MAX = 16 * SCAN_TILE;
 
+template <bool VEC>
 __global__ __launch_bounds__(SINGLE_TPB) void k_scan_single(const uint32_t* __restrict__ in, int64_t n,
                                                             uint32_t* __restrict__ out, uint32_t* __restrict__ tot) {
     uint32_t carry = 0;
     for (int64_t t0 = 0; t0 < n; t0 += SINGLE_TILE) {
         const int64_t base = t0 + (int64_t)threadIdx.x * SCAN_ITEMS;
         uint32_t v[SCAN_ITEMS];
-        uint32_t acc = 0;
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            int64_t i = base + j;
-            v[j] = i < n ? in[i] : 0u;
-            acc += v[j];
-        }
+        const uint32_t acc = load_run<VEC>(in, base, n, v);
         uint32_t total;
-        uint32_t off = block_exclusive_scan<SINGLE_TPB>(acc, total) + carry;
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            int64_t i = base + j;
-            if (i < n) out[i] = off;
-            off += v[j];
-        }
+        const uint32_t off = block_exclusive_scan<SINGLE_TPB>(acc, total) + carry;
+        store_run<VEC>(out, base, n, v, off);
         carry += total;
     }
     if (threadIdx.x == 0) *tot = carry;
@@ -125,14 +158,21 @@ int64_t scan_scratch_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE +
 
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s) {
     if (n == 0) return hipSuccess;
+    const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
     if (n <= SCAN_SINGLE_MAX) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SINGLE_TPB), 0, s, in, n, out, tot);
+        if (vec)
+            hipLaunchKernelGGL(k_scan_single<true>, dim3(1), dim3(SINGLE_TPB), 0, s, in, n, out, tot);
+        else
+            hipLaunchKernelGGL(k_scan_single<false>, dim3(1), dim3(SINGLE_TPB), 0, s, in, n, out, tot);
         return hipGetLastError();
     }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum);
     hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(TPB), 0, s, bsum, nb, tot);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum, out);
+    if (vec)
+        hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum, out);
+    else
+        hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)nb), dim3(TPB), 0, s, in, n, bsum, out);
     return hipGetLastError();
 }
 
