@@ -7,6 +7,7 @@ provides device memory (through the allocator hook) and streams.
 from __future__ import annotations
 
 import ctypes as C
+import functools
 
 import numpy as np
 import torch
@@ -105,11 +106,19 @@ class Rays:
 
 
 def render_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal_mode="max"):
+    if isinstance(bg, tuple) and len(bg) == 3:
+        return _render_opts(tuple(float(x) for x in bg), float(t_stop), signal_mode)
     bg = np.broadcast_to(np.asarray(bg, np.float32), (3,))
+    return _render_opts(tuple(float(x) for x in bg), float(t_stop), signal_mode)
+
+
+@functools.lru_cache(maxsize=64)
+def _render_opts(bg, t_stop, signal_mode):
+    # the library only reads the struct (const pointer), so equal options share one
     o = L.dot_render_opts()
     for a in range(3):
-        o.bg[a] = float(bg[a])
-    o.t_stop = float(t_stop)
+        o.bg[a] = bg[a]
+    o.t_stop = t_stop
     o.signal_mode = {"max": L.DOT_SIGNAL_MAX, "sum": L.DOT_SIGNAL_SUM}[signal_mode]
     return o
 
@@ -194,12 +203,16 @@ class Octree:
         return (rgb, ns) if nseg else rgb
 
     def render_train(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max", leaf_count=None,
-                     records=None):
+                     records=None, out=None):
         """Training forward: (rgb, nseg, leaf_count) -- leaf_count ([2, L]: recorded and other segments per
         leaf) feeds the adjoint's buckets; `records` (uint8 device buffer of records_bytes(n) bytes, or None)
-        receives the segments the adjoint replays."""
-        rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device=self.device)
-        ns = torch.empty(rays.n_rays, dtype=torch.int32, device=self.device)
+        receives the segments the adjoint replays.  `out` = (rgb, nseg) of a previous call of the same size is
+        written again instead of allocating."""
+        if out is not None and out[0].shape[0] == rays.n_rays:
+            rgb, ns = out
+        else:
+            rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device=self.device)
+            ns = torch.empty(rays.n_rays, dtype=torch.int32, device=self.device)
         if leaf_count is None or leaf_count.numel() < 2 * self.n_leaves:
             leaf_count = torch.empty((2, self.n_leaves), dtype=torch.int32, device=self.device)
         op = render_opts(bg, t_stop, signal_mode)
@@ -209,6 +222,7 @@ class Octree:
         return rgb, ns, leaf_count
 
     @staticmethod
+    @functools.lru_cache(maxsize=64)
     def records_bytes(n_rays, max_segments=96):
         return int(L.load().dot_render_train_records_bytes(int(n_rays), int(max_segments)))
 
@@ -332,29 +346,42 @@ class Octree:
         return dict(child=child, sigma=sigma, sh=sh, depth=depth)
 
 
-def pixel_batch(ray_ids, width, height, n_cams, workspace=None):
+def pixel_batch(ray_ids, width, height, n_cams, workspace=None, out=None):
     """(cam_idx int32, pix_idx int32, ray_ids int64) of the flat pixel ids
     `ray_ids` (int64 device [n]) in screen-tile order; `workspace` (uint8
-    device tensor) is reused when large enough.  Returns also the workspace."""
+    device tensor) is reused when large enough, and so are the three outputs
+    of a previous call passed as `out` when their size is n.  Returns also the
+    workspace."""
     lib = L.load()
     n = int(ray_ids.shape[0])
     assert ray_ids.dtype == torch.int64 and ray_ids.is_contiguous()
-    need = int(lib.dot_pixel_batch_workspace(n, width, height, n_cams))
+    need = _pixel_batch_workspace(n, int(width), int(height), int(n_cams))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=ray_ids.device)
-    cam = torch.empty(n, dtype=torch.int32, device=ray_ids.device)
-    pix = torch.empty(n, dtype=torch.int32, device=ray_ids.device)
-    ids = torch.empty(n, dtype=torch.int64, device=ray_ids.device)
+    if out is not None and out[0].shape[0] == n:
+        cam, pix, ids = out
+    else:
+        cam = torch.empty(n, dtype=torch.int32, device=ray_ids.device)
+        pix = torch.empty(n, dtype=torch.int32, device=ray_ids.device)
+        ids = torch.empty(n, dtype=torch.int64, device=ray_ids.device)
     L.check(lib.dot_pixel_batch(_ptr(ray_ids), C.c_int64(n), int(width), int(height), int(n_cams), _ptr(cam),
                                 _ptr(pix), _ptr(ids), _ptr(workspace), C.c_size_t(workspace.numel()), _stream()))
     return cam, pix, ids, workspace
 
 
-def mse_loss(pred, target, target_idx=None, grad=True, loss=True):
+@functools.lru_cache(maxsize=64)
+def _pixel_batch_workspace(n, width, height, n_cams):
+    return int(L.load().dot_pixel_batch_workspace(n, width, height, n_cams))
+
+
+def mse_loss(pred, target, target_idx=None, grad=True, loss=True, grad_out=None):
     """(loss, grad_rgb) of pred [n,3] against target rows (target_idx: int64 [n]
     or None); either may be skipped.  loss is a device float64 scalar."""
     n = pred.shape[0]
-    g = torch.empty_like(pred) if grad else None
+    if grad and grad_out is not None and grad_out.shape == pred.shape:
+        g = grad_out
+    else:
+        g = torch.empty_like(pred) if grad else None
     lo = torch.empty((), dtype=torch.float64, device=pred.device) if loss else None
     if target_idx is not None:
         assert target_idx.dtype == torch.int64 and target_idx.shape[0] == n

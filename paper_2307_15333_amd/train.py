@@ -86,6 +86,7 @@ class Trainer:
         self.epoch = 0
         self.opt_step = 0
         self._ws = None
+        self._pb = self._fw = self._grad = None     # per-batch buffers, reused while the batch size stays
         self._rec = None        # segment records of the current batch (forward -> adjoint)
         self._reset_optimizer()
 
@@ -104,7 +105,10 @@ class Trainer:
         indices into the flattened [n_cams, H, W] images).  Returns the batch
         loss as a device float64 scalar."""
         c = self.cfg
-        cam, pix, ids, self._ws = core.pixel_batch(idx.contiguous(), self.W, self.H, self.n_cams, self._ws)
+        # the batch's buffers are kept from one step to the next (same batch size)
+        cam, pix, ids, self._ws = core.pixel_batch(idx.contiguous(), self.W, self.H, self.n_cams, self._ws,
+                                                   out=self._pb)
+        self._pb = (cam, pix, ids)
         rays = core.Rays.pixels_device(self.cams_raw, self.n_cams, cam, pix)
         mode = "sum" if c.signal == "sum" else "max"
         # the training forward also counts each leaf's segments and records the
@@ -113,8 +117,10 @@ class Trainer:
         if self._rec is None or self._rec.numel() < need:
             self._rec = torch.empty(need, dtype=torch.uint8, device=self.device)
         rgb, nseg, self._cnt = self.tree.render_train(rays, bg=c.bg, t_stop=c.t_stop, signal=signal, signal_mode=mode,
-                                                      leaf_count=self._cnt, records=self._rec)
-        loss, grad = core.mse_loss(rgb, self.targets, ids)
+                                                      leaf_count=self._cnt, records=self._rec, out=self._fw)
+        self._fw = (rgb, nseg)
+        loss, grad = core.mse_loss(rgb, self.targets, ids, grad_out=self._grad)
+        self._grad = grad
         self.opt_step += 1
         if c.fused:
             # adjoint and update in one call: the gradient never exists as dense arrays
