@@ -618,27 +618,51 @@ __device__ __forceinline__ void fused_channel(int64_t l0, int nl, int ch, const 
     struct alignas(4 * W) Run {
         float x[W];
     };
-    for (int i = threadIdx.x; i < nl * Q; i += RED_BLOCK) {
-        const int r = i / Q, q = i - r * Q;
-        const int64_t col = (int64_t)ch * K + q * W;
-        Run* vp = reinterpret_cast<Run*>(o.v_sh + (l0 + r) * NV + col);
-        Run v = *vp;
-        if (OPT == OPT_RMSPROP && !hit[r]) {
+    // two items per iteration, both items' loads issued before either update
+    constexpr int U = 2;
+    const int ni = nl * Q;
+    for (int i0 = threadIdx.x; i0 < ni; i0 += U * RED_BLOCK) {
+        Run v[U], th[U], m[U];
+        bool live[U], full[U];
 #pragma unroll
-            for (int e = 0; e < W; ++e) {
-                float th = 0.f, m = 0.f;
-                opt_apply<OPT>(th, m, v.x[e], 0.f, o.lr_sh, o);
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * RED_BLOCK;
+            live[u] = i < ni;
+            full[u] = false;
+            if (live[u]) {
+                const int r = i / Q, q = i - r * Q;
+                const int64_t col = (int64_t)ch * K + q * W;
+                v[u] = *reinterpret_cast<const Run*>(o.v_sh + (l0 + r) * NV + col);
+                full[u] = !(OPT == OPT_RMSPROP && !hit[r]);
+                if (full[u]) {
+                    th[u] = *reinterpret_cast<const Run*>(sh + (l0 + r) * stride + col);
+                    if constexpr (OPT == OPT_ADAM) m[u] = *reinterpret_cast<const Run*>(o.m_sh + (l0 + r) * NV + col);
+                }
             }
-        } else {
-            Run* tp = reinterpret_cast<Run*>(sh + (l0 + r) * stride + col);
-            Run th = *tp, m{};
-            if constexpr (OPT == OPT_ADAM) m = *reinterpret_cast<const Run*>(o.m_sh + (l0 + r) * NV + col);
-#pragma unroll
-            for (int e = 0; e < W; ++e) opt_apply<OPT>(th.x[e], m.x[e], v.x[e], stage[r * KP + q * W + e], o.lr_sh, o);
-            *tp = th;
-            if constexpr (OPT == OPT_ADAM) *reinterpret_cast<Run*>(o.m_sh + (l0 + r) * NV + col) = m;
         }
-        *vp = v;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!live[u]) continue;
+            const int i = i0 + u * RED_BLOCK;
+            const int r = i / Q, q = i - r * Q;
+            const int64_t col = (int64_t)ch * K + q * W;
+            if (!full[u]) {
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    float t0 = 0.f, m0 = 0.f;
+                    opt_apply<OPT>(t0, m0, v[u].x[e], 0.f, o.lr_sh, o);
+                }
+            } else {
+                Run mm{};
+                if constexpr (OPT == OPT_ADAM) mm = m[u];
+#pragma unroll
+                for (int e = 0; e < W; ++e)
+                    opt_apply<OPT>(th[u].x[e], mm.x[e], v[u].x[e], stage[r * KP + q * W + e], o.lr_sh, o);
+                *reinterpret_cast<Run*>(sh + (l0 + r) * stride + col) = th[u];
+                if constexpr (OPT == OPT_ADAM) *reinterpret_cast<Run*>(o.m_sh + (l0 + r) * NV + col) = mm;
+            }
+            *reinterpret_cast<Run*>(o.v_sh + (l0 + r) * NV + col) = v[u];
+        }
     }
 }
 
