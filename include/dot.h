@@ -249,7 +249,9 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  direction -- into its leaf's bucket, then per-leaf sums that expand the SH
  *  outer product), which needs device scratch of 32 B (16 B at degree 0) per
  *  contributing segment from the tree's allocator and synchronises `stream`
- *  once to size it; beyond 8 GiB of
+ *  once to size it (the size is read back through a 16-byte pinned host
+ *  buffer the tree allocates on first use and keeps until dot_free, so the
+ *  adjoints of one tree must not run concurrently); beyond 8 GiB of
  *  scratch, or if it cannot be allocated, the terms go straight to the
  *  arrays with FP32 atomics.  Summation order, hence the last bits, depends
  *  on scheduling.  leaf_count: NULL, or the [2][n_leaves] counts
