@@ -146,6 +146,13 @@ def test_calls_on_null_handles_fail_cleanly():
     assert lib.dot_refine(None, None, C.byref(p), None, None) == L.DOT_EINVAL
     rp = L.dot_rmsprop_params(lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8)
     assert lib.dot_rmsprop_step(None, None, None, None, None, C.byref(rp), None) == L.DOT_EINVAL
+    assert lib.dot_render_backward_rmsprop(None, C.byref(r), None, None, None, None, None, None, C.byref(rp), None,
+                                           None, 0, None) == L.DOT_EINVAL
+    ap = L.dot_adam_params(lr_sigma=0.1, lr_sh=0.01, beta1=0.9, beta2=0.999, eps=1e-8, step=1)
+    assert lib.dot_adam_step(None, None, None, None, None, None, None, C.byref(ap), None) == L.DOT_EINVAL
+    assert lib.dot_render_backward_adam(None, C.byref(r), None, None, None, None, None, None, None, None,
+                                        C.byref(ap), None, None, 0, None) == L.DOT_EINVAL
+    assert b"NULL tree" in lib.dot_last_error()
     assert lib.dot_sigma_signal(None, None, None) == L.DOT_EINVAL
 
 
