@@ -345,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_list_kernel(TreeView tv, RayBa
 // wait on them.  Same ray-to-lane mapping as the traversal kernels.
 template <int DEG>
 __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArgs a, int64_t L, const uint32_t* offset,
-                                                             const uint32_t* base0, float* rows) {
+                                                             uint32_t n_rows, float* rows) {
     constexpr int RS = bwd_row_floats<DEG>();
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
@@ -379,27 +379,23 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
     A1 = A0;
     B1 = B0;
     if (nrec > 1) load_rec(1, A1, B1, s1);
+    // A slot is below its leaf's recorded count by construction; records of
+    // another batch or tree are caught only as far as staying in bounds goes
+    // (leaf id < L, row < n_rows), so the one per-leaf read is the offset.
     int leaf0 = __float_as_int(A0.x);
-    bool ok0 = (uint64_t)(uint32_t)leaf0 < (uint64_t)L;   // records of another tree: stop, stay in bounds
-    uint32_t off0 = 0, lim0 = 0;
-    if (ok0) {
-        off0 = offset[leaf0];
-        lim0 = base0[leaf0];
-    }
+    bool ok0 = (uint64_t)(uint32_t)leaf0 < (uint64_t)L;
+    uint32_t off0 = ok0 ? offset[leaf0] : 0u;
     for (int i = 0; i < nrec && ok0; ++i) {
-        // record i + 1's bucket data and record i + 2 are requested first
+        // record i + 1's bucket offset and record i + 2 are requested first
         bool ok1 = false;
-        uint32_t off1 = 0, lim1 = 0;
+        uint32_t off1 = 0;
         float4 A2 = A1;
         float2 B2 = B1;
         uint32_t s2 = s1;
         if (i + 1 < nrec) {
             const int leaf1 = __float_as_int(A1.x);
             ok1 = (uint64_t)(uint32_t)leaf1 < (uint64_t)L;
-            if (ok1) {
-                off1 = offset[leaf1];
-                lim1 = base0[leaf1];
-            }
+            if (ok1) off1 = offset[leaf1];
             if (i + 2 < nrec) load_rec(i + 2, A2, B2, s2);
         }
         const float delta = A0.y, tau = A0.z;
@@ -423,7 +419,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
             out[6] = d[2];
             out[7] = 0.f;
         }
-        if (s0 < lim0) {
+        if ((uint64_t)off0 + s0 < (uint64_t)n_rows) {
             float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)off0 + s0) * RS);
 #pragma unroll
             for (int q = 0; q < RS / 4; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
@@ -435,7 +431,6 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
         s0 = s1;
         ok0 = ok1;
         off0 = off1;
-        lim0 = lim1;
         A1 = A2;
         B1 = B2;
         s1 = s2;
@@ -1046,10 +1041,10 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     if (a.rec.a) {
         // replay the recorded segments; re-traverse only the rays with more
         switch (t.degree) {
-            case 0: hipLaunchKernelGGL(bwd_emit_rec_kernel<0>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
-            case 1: hipLaunchKernelGGL(bwd_emit_rec_kernel<1>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
-            case 2: hipLaunchKernelGGL(bwd_emit_rec_kernel<2>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
-            default: hipLaunchKernelGGL(bwd_emit_rec_kernel<3>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, base0, rows); break;
+            case 0: hipLaunchKernelGGL(bwd_emit_rec_kernel<0>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, m, rows); break;
+            case 1: hipLaunchKernelGGL(bwd_emit_rec_kernel<1>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, m, rows); break;
+            case 2: hipLaunchKernelGGL(bwd_emit_rec_kernel<2>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, m, rows); break;
+            default: hipLaunchKernelGGL(bwd_emit_rec_kernel<3>, grid, dim3(BLOCK), 0, s, rb, a, L, offset, m, rows); break;
         }
         if (overflow > 0) {
             // only FP32 trees record (training storage)
