@@ -371,7 +371,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_rec_kernel(RayBatch rb, BwdArg
         B_ = a.rec.b[j];
         s_ = a.rec.slot[j];
     };
-    // record i (with its bucket offset and recorded-region size), record i + 1
+    // record i (with its bucket offset), record i + 1
     float4 A0, A1;
     float2 B0, B1;
     uint32_t s0 = 0, s1 = 0;
