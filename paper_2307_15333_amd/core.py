@@ -106,15 +106,21 @@ class Rays:
 
 
 def render_opts(bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal_mode="max"):
-    if isinstance(bg, tuple) and len(bg) == 3:
-        return _render_opts(tuple(float(x) for x in bg), float(t_stop), signal_mode)
-    bg = np.broadcast_to(np.asarray(bg, np.float32), (3,))
+    """A dot_render_opts struct of the caller's own (free to modify)."""
+    o = _opts(bg, t_stop, signal_mode)
+    return type(o).from_buffer_copy(o)
+
+
+def _opts(bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal_mode="max"):
+    # the binding's calls share one struct per option set: the library only
+    # reads it (const pointer) and nothing here writes it
+    if not (isinstance(bg, tuple) and len(bg) == 3):
+        bg = np.broadcast_to(np.asarray(bg, np.float32), (3,))
     return _render_opts(tuple(float(x) for x in bg), float(t_stop), signal_mode)
 
 
 @functools.lru_cache(maxsize=64)
 def _render_opts(bg, t_stop, signal_mode):
-    # the library only reads the struct (const pointer), so equal options share one
     o = L.dot_render_opts()
     for a in range(3):
         o.bg[a] = bg[a]
@@ -197,7 +203,7 @@ class Octree:
     def render(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, nseg=False, signal=None, signal_mode="max"):
         rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device=self.device)
         ns = torch.empty(rays.n_rays, dtype=torch.int32, device=self.device) if nseg else None
-        op = render_opts(bg, t_stop, signal_mode)
+        op = _opts(bg, t_stop, signal_mode)
         L.check(self.lib.dot_render(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb), _ptr(ns),
                                     _ptr(signal), _stream()))
         return (rgb, ns) if nseg else rgb
@@ -215,7 +221,7 @@ class Octree:
             ns = torch.empty(rays.n_rays, dtype=torch.int32, device=self.device)
         if leaf_count is None or leaf_count.numel() < 2 * self.n_leaves:
             leaf_count = torch.empty((2, self.n_leaves), dtype=torch.int32, device=self.device)
-        op = render_opts(bg, t_stop, signal_mode)
+        op = _opts(bg, t_stop, signal_mode)
         L.check(self.lib.dot_render_train(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb), _ptr(ns),
                                           _ptr(signal), _ptr(leaf_count), _ptr(records),
                                           C.c_size_t(records.numel() if records is not None else 0), _stream()))
@@ -227,21 +233,21 @@ class Octree:
         return int(L.load().dot_render_train_records_bytes(int(n_rays), int(max_segments)))
 
     def accumulate_signal(self, rays, signal, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal_mode="max"):
-        op = render_opts(bg, t_stop, signal_mode)
+        op = _opts(bg, t_stop, signal_mode)
         L.check(self.lib.dot_accumulate_signal(self.handle, C.byref(rays.struct), C.byref(op), _ptr(signal),
                                                _stream()))
         return signal
 
     def backward(self, rays, rgb, nseg, grad_rgb, grad_sigma, grad_sh, bg=(1.0, 1.0, 1.0), t_stop=1e-4,
                  leaf_count=None, records=None):
-        op = render_opts(bg, t_stop)
+        op = _opts(bg, t_stop)
         L.check(self.lib.dot_render_backward(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
                                              _ptr(nseg), _ptr(grad_rgb), _ptr(grad_sigma), _ptr(grad_sh),
                                              _ptr(leaf_count), _ptr(records),
                                              C.c_size_t(records.numel() if records is not None else 0), _stream()))
 
     def render_stats(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
-        op = render_opts(bg, t_stop)
+        op = _opts(bg, t_stop)
         out = (C.c_int64 * 4)()
         L.check(self.lib.dot_render_stats(self.handle, C.byref(rays.struct), C.byref(op), out, _stream()))
         return dict(rays=out[0], segments=out[1], sh_fetches=out[2], index_reads=out[3])
@@ -276,7 +282,7 @@ class Octree:
     def backward_rmsprop(self, rays, rgb, nseg, grad_rgb, state, lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8,
                          bg=(1.0, 1.0, 1.0), t_stop=1e-4, leaf_count=None, records=None):
         """Adjoint and RMSProp step in one call (no dense gradient arrays)."""
-        op = render_opts(bg, t_stop)
+        op = _opts(bg, t_stop)
         p = L.dot_rmsprop_params(lr_sigma=lr_sigma, lr_sh=lr_sh, alpha=alpha, eps=eps)
         L.check(self.lib.dot_render_backward_rmsprop(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
                                                      _ptr(nseg), _ptr(grad_rgb), _ptr(state["v_sigma"]),
@@ -287,7 +293,7 @@ class Octree:
     def backward_adam(self, rays, rgb, nseg, grad_rgb, state, step, lr_sigma=0.1, lr_sh=0.01, beta1=0.9,
                       beta2=0.999, eps=1e-8, bg=(1.0, 1.0, 1.0), t_stop=1e-4, leaf_count=None, records=None):
         """Adjoint and Adam step (1-based `step`) in one call (no dense gradient arrays)."""
-        op = render_opts(bg, t_stop)
+        op = _opts(bg, t_stop)
         p = L.dot_adam_params(lr_sigma=lr_sigma, lr_sh=lr_sh, beta1=beta1, beta2=beta2, eps=eps, step=int(step))
         L.check(self.lib.dot_render_backward_adam(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
                                                   _ptr(nseg), _ptr(grad_rgb), _ptr(state["m_sigma"]),
