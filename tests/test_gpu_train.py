@@ -278,6 +278,48 @@ def test_fused_backward_bit_matches_split_path(depth, n_rays, degree, opt, misal
     fused.close()
 
 
+@pytest.mark.parametrize("opt", ["rmsprop", "adam"])
+def test_fused_backward_bit_matches_split_path_full_size(opt):
+    """The Alg. 1 launch configuration: the 3.54M-leaf torus+box tree, a
+    2^20-ray tile-ordered batch of 100 800x800 views, 256 records per ray.
+    Fused adjoint + optimiser against the split path on two copies of the
+    tree, parameters and state compared on the device bit for bit."""
+    core = _core()
+    s = synth.torus_box_scene()
+    views = synth.sphere_views(100)
+    W, H = int(views[0]["width"]), int(views[0]["height"])
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    ids = torch.randperm(len(views) * W * H, generator=gen, device="cuda")[:1 << 20].contiguous()
+    _, cams_raw = core.Rays._cams_tensor(views, "cuda")
+    cam, pix, _, _ = core.pixel_batch(ids, W, H, len(views))
+    rays = core.Rays.pixels_device(cams_raw, len(views), cam, pix)
+    g = torch.randn((rays.n_rays, 3), generator=gen, device="cuda") * 1e-3
+    split, fused = core.Octree.from_scene(s), core.Octree.from_scene(s)
+    new_state = (lambda t: t.adam_state()) if opt == "adam" else (lambda t: t.rmsprop_state())
+    st_a, st_b = new_state(split), new_state(fused)
+    rec = torch.empty(core.Octree.records_bytes(rays.n_rays, 256), dtype=torch.uint8, device="cuda")
+    gs = torch.zeros(split.n_leaves, device="cuda")
+    gh = torch.zeros((split.n_leaves, 3, split.K), device="cuda")
+    rgb, ns, cnt = split.render_train(rays, records=rec)
+    torch.cuda.synchronize()
+    assert int(rec[:4].cpu().numpy().view(np.uint32)[0]) == 0          # no overflow ray
+    split.backward(rays, rgb, ns, g, gs, gh, leaf_count=cnt, records=rec)
+    if opt == "adam":
+        split.adam_step(gs, gh, st_a, 1)
+        fused.backward_adam(rays, rgb, ns, g, st_b, 1, leaf_count=cnt, records=rec)
+    else:
+        split.rmsprop_step(gs, gh, st_a)
+        fused.backward_rmsprop(rays, rgb, ns, g, st_b, leaf_count=cnt, records=rec)
+    for pa, pb in zip(split.plane_views(), fused.plane_views()):
+        assert torch.equal(pa, pb)
+    for k in st_a:
+        assert torch.equal(st_a[k], st_b[k]), k
+    per_leaf = cnt.sum(0)
+    assert int((per_leaf == 0).sum()) > 0 and int(per_leaf.sum()) < 32 * split.n_leaves   # thread-per-leaf, skips
+    split.close()
+    fused.close()
+
+
 @pytest.mark.parametrize("degree", [0, 3])
 def test_fused_backward_adam_matches_oracle(degree):
     """Adjoint + Adam in one call against the oracle's FP64 gradient followed
