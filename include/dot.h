@@ -384,7 +384,7 @@ int dot_sigma_signal(dot_tree_t tree, float *signal_out, void *stream);
  *  n_cams cameras of width x height (a slice of the epoch's permutation).
  *  Writes the same rays as a DOT_RAYS_PIXELS list, cam_idx_out / pix_idx_out
  *  (DEVICE int32 [n]), grouped by screen tile -- square tiles sized to hold
- *  about 64 of the batch's rays, in camera-then-row-major tile order; order
+ *  about 16 of the batch's rays, in camera-then-row-major tile order; order
  *  inside a tile unspecified -- so that a wave traces neighbouring pixels.
  *  ray_ids_out (DEVICE int64 [n] or NULL) receives the ids in the new order,
  *  for use as the target rows of dot_mse_loss.  The batch's content is

@@ -20,7 +20,14 @@ struct PixelGeo {
     int64_t bins;     // n_cams * tpv
 };
 
-// tile edge 2^shift chosen so a tile holds about one wave of the batch's rays
+// tile edge 2^shift: the smallest (8 to 128 pixels) whose tile holds about 16
+// of the batch's rays, so a wave takes the rays of a few neighbouring tiles.
+// (Measured on 2^20 random rays of 100 800x800 views: a step of the training
+// loop is 4% faster than with about 64 rays per tile, where a wave's rays
+// spread over a tile twice as wide; numbering the tiles in Morton order
+// instead of row-major gave nothing more.)
+constexpr double RAYS_PER_TILE = 16.0;
+
 PixelGeo make_geo(int64_t n, int32_t W, int32_t H, int32_t n_cams) {
     PixelGeo g;
     g.W = W;
@@ -28,7 +35,7 @@ PixelGeo make_geo(int64_t n, int32_t W, int32_t H, int32_t n_cams) {
     g.total = (int64_t)n_cams * W * H;
     const double density = g.total > 0 ? (double)n / (double)g.total : 1.0;
     int shift = 3;
-    while (shift < 7 && (double)(1 << (2 * shift)) * density < 64.0) ++shift;
+    while (shift < 7 && (double)(1 << (2 * shift)) * density < RAYS_PER_TILE) ++shift;
     g.shift = shift;
     g.tw = (W + (1 << shift) - 1) >> shift;
     g.tpv = (int64_t)g.tw * ((H + (1 << shift) - 1) >> shift);

@@ -70,9 +70,9 @@ def test_mse_loss_matches_oracle():
 
 
 def _tile_shift(n, total):
-    # documented rule: the smallest tile edge 2^s (8 <= 2^s <= 128) holding ~64 rays of the batch
+    # documented rule: the smallest tile edge 2^s (8 <= 2^s <= 128) holding ~16 rays of the batch
     s = 3
-    while s < 7 and (1 << (2 * s)) * (n / total) < 64.0:
+    while s < 7 and (1 << (2 * s)) * (n / total) < 16.0:
         s += 1
     return s
 
