@@ -9,11 +9,15 @@ steps:
                          rays and colour channels, and its gradient.
   * ``rmsprop``       -- the optimiser of Sec. 3.3 (RMSProp): a decayed mean of
                          squared gradients scales each parameter's step.
+  * ``adam``          -- Adam (Kingma & Ba, 2015), the optimiser the
+                         differentiable training-step workload uses on the same
+                         parameters: decayed first and second moments, each
+                         divided by its bias correction 1 - beta^t.
   * ``sigma_signal``  -- the density used as the refinement signal in the
                          Pr_sigma ablation (Sec. 3.1, Tab. 3): max(sigma, 0).
   * ``train``         -- epochs of Alg. 1: for each batch of the given ray
                          permutation render (with the signal Q), MSE, adjoint,
-                         optimiser step; every T-th epoch prune(Q, tau) and
+                         optimiser step (RMSProp, or Adam); every T-th epoch prune(Q, tau) and
                          sample(Q, gamma) through the refinement oracle.
 
 Parameters are kept in FP64 between steps; the refinement oracle rounds the
@@ -42,13 +46,27 @@ def rmsprop(theta, g, v, lr, alpha, eps):
     return theta - lr * g / (np.sqrt(v) + eps), v
 
 
+def adam(theta, g, m, v, t, lr, beta1, beta2, eps):
+    """Step t >= 1: m <- beta1 m + (1 - beta1) g; v <- beta2 v + (1 - beta2) g^2;
+    theta <- theta - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+    Returns (theta, m, v)."""
+    if t < 1:
+        raise ValueError("Adam steps are numbered from 1")
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
 def sigma_signal(sigma):
     return np.maximum(np.asarray(sigma, np.float64), 0.0)
 
 
 def train(child, sigma, sh, degree, bbox_min, bbox_size, origins, dirs, targets, perms, batch, interval=20,
           tau=1e-3, gamma=0.01, prune_le=True, max_depth=10, recursive=False, reinit=False, signal="max",
-          lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
+          lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8, bg=(1.0, 1.0, 1.0), t_stop=1e-4, optimizer="rmsprop",
+          betas=(0.9, 0.999)):
     """Run len(perms) epochs (epoch i = 1, 2, ...; refine when i % interval == 0).
 
     origins/dirs/targets: [n, 3] per training ray; perms: list of index arrays
@@ -56,7 +74,11 @@ def train(child, sigma, sh, degree, bbox_min, bbox_size, origins, dirs, targets,
     child, sigma, sh (FP64) and depth of the final tree; history one dict per
     epoch with the batch losses, and at a refinement the signal that drove it
     (sig, and bounds sig_lo / sig_hi from the oracle's stopping-rule variants)
-    and the refinement counts."""
+    and the refinement counts.  optimizer: "rmsprop" (alpha, eps) or "adam"
+    (betas, eps); the optimiser state, and Adam's step count, start again from
+    zero after each refinement."""
+    if optimizer not in ("rmsprop", "adam"):
+        raise ValueError(optimizer)
     child = np.ascontiguousarray(child, np.int32).reshape(-1, 8)
     sigma = np.array(sigma, np.float64)
     K = (degree + 1) ** 2
@@ -65,6 +87,8 @@ def train(child, sigma, sh, degree, bbox_min, bbox_size, origins, dirs, targets,
     dirs = np.asarray(dirs, np.float64)
     targets = np.asarray(targets, np.float64)
     v_s, v_h = np.zeros_like(sigma), np.zeros_like(sh)
+    m_s, m_h = np.zeros_like(sigma), np.zeros_like(sh)
+    t_opt = 0
     depth = None
     mode = "sum" if signal == "sum" else "max"
     hist = []
@@ -80,8 +104,13 @@ def train(child, sigma, sh, degree, bbox_min, bbox_size, origins, dirs, targets,
             r = O.render(tree, origins[idx], dirs[idx], bg=bg, t_stop=t_stop, signal=want_q, signal_mode=mode)
             loss, grad = mse_loss(r["rgb"], targets[idx])
             gs, gh = O.backward(tree, origins[idx], dirs[idx], grad, bg=bg, t_stop=t_stop)
-            sigma, v_s = rmsprop(sigma, gs, v_s, lr_sigma, alpha, eps)
-            sh, v_h = rmsprop(sh, gh, v_h, lr_sh, alpha, eps)
+            if optimizer == "rmsprop":
+                sigma, v_s = rmsprop(sigma, gs, v_s, lr_sigma, alpha, eps)
+                sh, v_h = rmsprop(sh, gh, v_h, lr_sh, alpha, eps)
+            else:
+                t_opt += 1
+                sigma, m_s, v_s = adam(sigma, gs, m_s, v_s, t_opt, lr_sigma, betas[0], betas[1], eps)
+                sh, m_h, v_h = adam(sh, gh, m_h, v_h, t_opt, lr_sh, betas[0], betas[1], eps)
             losses.append(loss)
             if want_q:
                 for a, key in enumerate(("sig", "sig_lo", "sig_hi")):
@@ -101,6 +130,8 @@ def train(child, sigma, sh, degree, bbox_min, bbox_size, origins, dirs, targets,
             sh = out["sh"].astype(np.float64)
             depth = out["depth"]
             v_s, v_h = np.zeros_like(sigma), np.zeros_like(sh)
+            m_s, m_h = np.zeros_like(sigma), np.zeros_like(sh)
+            t_opt = 0
             rec.update(merged=out["merged"], subdivided=out["subdivided"], k=out["k"], depth=depth)
         rec["leaves"] = sigma.shape[0]
         hist.append(rec)

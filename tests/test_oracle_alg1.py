@@ -1,8 +1,8 @@
 """Pins of the training-loop oracle (Alg. 1) and its per-step pieces.
 
 The loss and optimiser pieces are checked against PyTorch's own CPU
-implementations of the same definitions (MSE, RMSProp) and against closed
-forms; the loop is checked through properties that any correct
+implementations of the same definitions (MSE, RMSProp, Adam) and against
+closed forms; the loop is checked through properties that any correct
 implementation of Alg. 1 has: order-independence of the MAX signal, the
 fixed point at a perfect fit, a falling loss, and the refinement counts.
 None of these calls the HIP library.
@@ -59,6 +59,46 @@ def test_rmsprop_constant_gradient_closed_form():
     np.testing.assert_allclose(th, expect, rtol=1e-12)
 
 
+def test_adam_matches_torch_adam():
+    rng = np.random.default_rng(4)
+    theta0 = rng.normal(size=50)
+    grads = [rng.normal(size=50) * 10.0 ** rng.uniform(-6, 1, size=50) for _ in range(7)]
+    for lr, b1, b2, eps in ((0.1, 0.9, 0.999, 1e-8), (0.01, 0.8, 0.99, 1e-4)):
+        p = torch.nn.Parameter(torch.tensor(theta0, dtype=torch.float64))
+        opt = torch.optim.Adam([p], lr=lr, betas=(b1, b2), eps=eps)
+        th, m, v = theta0.copy(), np.zeros(50), np.zeros(50)
+        for t, g in enumerate(grads, start=1):
+            p.grad = torch.tensor(g, dtype=torch.float64)
+            opt.step()
+            th, m, v = A.adam(th, g, m, v, t, lr, b1, b2, eps)
+            np.testing.assert_allclose(m, opt.state[p]["exp_avg"].numpy(), rtol=1e-13, atol=0)
+            np.testing.assert_allclose(v, opt.state[p]["exp_avg_sq"].numpy(), rtol=1e-13, atol=0)
+        np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+    with pytest.raises(ValueError):
+        A.adam(theta0, grads[0], np.zeros(50), np.zeros(50), 0, 0.1, 0.9, 0.999, 1e-8)
+
+
+def test_adam_constant_gradient_closed_form():
+    # With a constant gradient g from m = v = 0: m_t = (1 - b1^t) g and
+    # v_t = (1 - b2^t) g^2, so the bias-corrected moments are g and g^2 and
+    # every step moves theta by exactly lr g / (|g| + eps).  A bias correction
+    # off by one step, or the two betas swapped, breaks this.
+    g, lr, b1, b2, eps = np.array([0.3, -2.0, 1e-5]), 0.1, 0.9, 0.999, 1e-8
+    th, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    expect = np.zeros(3)
+    for t in range(1, 9):
+        th, m, v = A.adam(th, g, m, v, t, lr, b1, b2, eps)
+        expect -= lr * g / (np.abs(g) + eps)
+        np.testing.assert_allclose(m, (1 - b1 ** t) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1 - b2 ** t) * g * g, rtol=1e-12)
+        np.testing.assert_allclose(th, expect, rtol=1e-12)
+    # a zero gradient after a constant one: the first moment decays, theta keeps moving
+    th2, m2, v2 = A.adam(th, np.zeros(3), m, v, 9, lr, b1, b2, eps)
+    want = th - lr * (b1 * m / (1 - b1 ** 9)) / (np.sqrt(b2 * v / (1 - b2 ** 9)) + eps)
+    np.testing.assert_allclose(th2, want, rtol=1e-13)
+    assert np.all(th2 != th)
+
+
 def test_sigma_signal_is_the_clamped_density():
     s = np.array([-3.0, -0.0, 0.0, 1e-30, 2.5])
     np.testing.assert_array_equal(A.sigma_signal(s), [0.0, 0.0, 0.0, 1e-30, 2.5])
@@ -73,6 +113,40 @@ def _setup(n_views=3, size=16, seed=5):
 
 def _args(sc):
     return (sc.child, sc.sigma64, sc.sh32, sc.degree, sc.bbox_min, sc.bbox_size)
+
+
+def test_loop_adam_steps_are_the_adam_pieces_and_restart_after_refinement():
+    # The loop's Adam is the per-step Adam with a step count that starts at 1
+    # and starts again, with zero moments, after a refinement.  Two epochs of
+    # two batches, a refinement after each that changes no leaf (tau below
+    # every signal, gamma = 0) but rounds the values to the FP32 storage; the
+    # density's learning rate is 0, so the rays' segments stay fixed and the SH
+    # updates can be replayed by hand from the pieces.
+    sc, cams, o, d = _setup(n_views=1, size=8)
+    n = o.shape[0]
+    tgt = np.random.default_rng(9).uniform(size=(n, 3))
+    perm = [np.arange(n), np.arange(n)]
+    st, hist = A.train(*_args(sc), o, d, tgt, perm, n // 2, interval=1, lr_sigma=0.0, lr_sh=0.05, tau=-1.0,
+                       gamma=0.0, optimizer="adam", eps=1e-6)
+    assert all(h["merged"] == 0 and h["subdivided"] == 0 for h in hist)
+    sh = sc.sh32.astype(np.float64)
+    for epoch in range(2):
+        m, v = np.zeros_like(sh), np.zeros_like(sh)
+        for t, b in enumerate((slice(0, n // 2), slice(n // 2, n)), start=1):
+            T = O.OracleTree(sc.child, sc.sigma64, sh, sc.degree, sc.bbox_min, sc.bbox_size)
+            r = O.render(T, o[b], d[b])
+            _, g = A.mse_loss(r["rgb"], tgt[b])
+            _, gh = O.backward(T, o[b], d[b], g)
+            sh, m, v = A.adam(sh, gh, m, v, t, 0.05, 0.9, 0.999, 1e-6)
+        sh = sh.astype(np.float32).astype(np.float64)      # the refinement's storage rounding
+    # equal up to the gradient's summation order (the oracle's threads) and an
+    # FP32 rounding that order can flip; a step count or moments carried over
+    # the refinement would move the SH by ~1e-2
+    np.testing.assert_allclose(st["sh"], sh, rtol=1e-6, atol=1e-7)
+    assert np.abs(st["sh"] - sc.sh32).max() > 1e-2
+    np.testing.assert_array_equal(st["sigma"], sc.sigma64.astype(np.float32))
+    with pytest.raises(ValueError):
+        A.train(*_args(sc), o, d, tgt, perm, n, optimizer="sgd")
 
 
 def test_loop_signal_and_losses_do_not_depend_on_the_ray_order():
@@ -106,25 +180,28 @@ def test_loop_sum_signal_is_the_sum_over_batches():
     np.testing.assert_allclose(hist[0]["sig"], full["sig"], rtol=1e-12, atol=1e-300)
 
 
-def test_loop_perfect_fit_is_a_fixed_point():
+@pytest.mark.parametrize("optimizer", ["rmsprop", "adam"])
+def test_loop_perfect_fit_is_a_fixed_point(optimizer):
     # Targets rendered from the starting tree: every residual, hence every
     # gradient and update, is exactly zero.  A wrong target row fails this.
     sc, cams, o, d = _setup()
     n = o.shape[0]
     tgt = O.render(O.OracleTree.from_scene(sc), o, d)["rgb"]
-    st, hist = A.train(*_args(sc), o, d, tgt, synth.ray_permutations(n, 2, 4), 128, interval=0)
+    st, hist = A.train(*_args(sc), o, d, tgt, synth.ray_permutations(n, 2, 4), 128, interval=0,
+                       optimizer=optimizer)
     assert all(np.all(h["losses"] == 0.0) for h in hist)
     np.testing.assert_array_equal(st["sigma"], sc.sigma64)
     np.testing.assert_array_equal(st["sh"], sc.sh32.astype(np.float64))
 
 
-def test_loop_reduces_the_loss():
+@pytest.mark.parametrize("optimizer", ["rmsprop", "adam"])
+def test_loop_reduces_the_loss(optimizer):
     sc, cams, o, d = _setup(n_views=4)
     n = o.shape[0]
     tgt = O.render(O.OracleTree.from_scene(sc), o, d)["rgb"]
     start = synth.perturb_sh(sc, std=0.3, seed=7)
     _, hist = A.train(*_args(start), o, d, tgt, synth.ray_permutations(n, 6, 5), 256, interval=0,
-                      lr_sigma=0.01, lr_sh=0.01)
+                      lr_sigma=0.01, lr_sh=0.01, optimizer=optimizer)
     first, last = hist[0]["losses"].mean(), hist[-1]["losses"].mean()
     assert last < 0.5 * first
 

@@ -362,6 +362,61 @@ def test_backward_matches_central_differences():
         assert fd == pytest.approx(gh.reshape(-1)[j], rel=1e-6, abs=1e-8)
 
 
+def test_backward_with_early_stop_matches_central_differences():
+    """With early termination (t_stop = 1e-4) the render is the sum truncated
+    after the segment that takes S past ln 1e4 (plus the background term), and
+    the adjoint must stop at that same segment.  On rays whose stop decision is
+    far from the threshold (no straddle within 1e-2 of optical depth, far more
+    than a perturbation of h moves S), central differences of the truncated
+    render pin the gradient of every leaf's density and of sampled SH
+    coefficients; leaves past or at the stop of some rays are included, so
+    adjoining one segment too many or too few fails."""
+    s = synth.random_tree_scene(3, 2, seed=17, sigma_max=12.0)
+    sig = s.sigma64 + 0.05
+    sh = s.sh64.copy()
+    cams = synth.cameras([(35.0, 25.0, 3.0, 16, 16), (-120.0, -30.0, 3.2, 16, 16)])
+    o, d = O.camera_rays(cams)
+    bg = np.array([0.3, 0.6, 0.9])
+    T = O.OracleTree(s.child, sig, sh, s.degree)
+    r = O.render(T, o, d, bg=bg, t_stop=1e-4, margin=1e-2)
+    full = O.render(T, o, d, bg=bg, t_stop=0.0)
+    keep = ~r["straddle"].astype(bool)
+    o, d = o[keep], d[keep]
+    stopped = (r["nseg"] < full["nseg"])[keep]
+    assert stopped.sum() > 50 and (~stopped).sum() > 20
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(o.shape[0], 3))
+    gs, gh = O.backward(T, o, d, g, bg=bg, t_stop=1e-4)
+    gs0, gh0 = O.backward(T, o, d, g, bg=bg, t_stop=0.0)
+    # the truncation changes the gradient of many leaves, each by far more than
+    # the differences' error (the terms past the stop carry T < 1e-4)
+    moved = np.where(np.abs(gs - gs0) > 1e-6)[0]
+    assert moved.shape[0] > 10
+
+    def loss(sig_, sh_):
+        rr = O.render(O.OracleTree(s.child, sig_, sh_, s.degree), o, d, bg=bg, t_stop=1e-4, margin=0.0)
+        return float((rr["rgb"] * g).sum())
+
+    h = 1e-5
+    for l in range(sig.shape[0]):
+        a, b = sig.copy(), sig.copy()
+        a[l] += h
+        b[l] -= h
+        fd = (loss(a, sh) - loss(b, sh)) / (2 * h)
+        assert fd == pytest.approx(gs[l], rel=1e-6, abs=1e-8), l
+    # SH: coefficients of the leaves whose gradient the truncation moved, and others
+    flat = np.abs(gh).reshape(-1)
+    K3 = 3 * (s.degree + 1) ** 2
+    on_moved = np.concatenate([np.arange(l * K3, (l + 1) * K3) for l in moved])
+    cand = np.union1d(rng.choice(on_moved, 16, replace=False), rng.choice(np.where(flat > 1e-4)[0], 16, replace=False))
+    for j in cand:
+        a, b = sh.copy().reshape(-1), sh.copy().reshape(-1)
+        a[j] += h
+        b[j] -= h
+        fd = (loss(sig, a.reshape(sh.shape)) - loss(sig, b.reshape(sh.shape))) / (2 * h)
+        assert fd == pytest.approx(gh.reshape(-1)[j], rel=1e-6, abs=1e-8), j
+
+
 def test_backward_single_leaf_closed_form():
     """One leaf: dC/dk = w c (1-c) Y(d); dC/dsigma = L e^{-sigma L}(c - bg)."""
     sigma, k0 = 1.3, 0.4
@@ -526,6 +581,39 @@ def test_refine_recursive_climbs_hierarchy():
     R = O.refine(T, signal, tau=0.0, sample_frac=0.0, max_depth=4, recursive=True)
     assert R["merged"] == 64 + 8 + 1
     assert R["sigma"].shape[0] == 1 and R["child"].shape[0] == 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_refine_recursive_merge_values_are_means_of_level_means(storage):
+    """Recursive pruning applies Eq. 3 level by level: a node whose children
+    were merged in the same pass gets the mean of their (already rounded)
+    means, not the mean of all the leaves below it.  Tree: the root's octant 0
+    is an internal node with 8 leaves, octants 1-7 are leaves; every value is
+    distinct.  Non-recursive: only the inner group merges; recursive: the
+    whole tree collapses to one leaf."""
+    rng = np.random.default_rng(40)
+    child = np.array([[1] + [-1 - (8 + j) for j in range(7)], [-1 - j for j in range(8)]], np.int32)
+    vals = rng.uniform(-3.0, 3.0, size=(15, 1 + 3 * 4))
+    vals = O.round_storage(vals, storage)             # stored values
+    T = O.OracleTree(child, vals[:, 0].copy(), vals[:, 1:].reshape(15, 3, 4).copy(), 1)
+    sig = np.zeros(15, np.float32)
+
+    def mean8(rows):
+        return O.round_storage(np.array([math.fsum(rows[:, j]) / 8.0 for j in range(rows.shape[1])]), storage)
+
+    inner = mean8(vals[:8])
+    R = O.refine(T, sig, tau=0.0, sample_frac=0.0, max_depth=4, recursive=False, storage=storage)
+    assert R["merged"] == 1 and R["sigma"].shape[0] == 8
+    np.testing.assert_array_equal(np.concatenate([R["sigma"][:1], R["sh"][0].reshape(-1)]), inner)
+    np.testing.assert_array_equal(R["sigma"][1:], vals[8:, 0])
+    R = O.refine(T, sig, tau=0.0, sample_frac=0.0, max_depth=4, recursive=True, storage=storage)
+    assert R["merged"] == 2 and R["sigma"].shape[0] == 1 and R["child"].shape[0] == 0
+    want = mean8(np.vstack([inner[None, :], vals[8:]]))
+    np.testing.assert_array_equal(np.concatenate([R["sigma"], R["sh"][0].reshape(-1)]), want)
+    # the mean over all 15 leaves (or over the 8 top-level cells without the
+    # inner rounding) is a different value: the pin tells the readings apart
+    flat = O.round_storage(vals.mean(axis=0), storage)
+    assert np.abs(flat - want).max() > 0.05
 
 
 def test_refine_reinit_zeroes_only_new_leaves():
