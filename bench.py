@@ -1,11 +1,13 @@
 """Benchmark of the octree volume renderer on one MI355X.
 
-Step = one forward pass of the renderer with the fused max-weight training
-signal over the 800x800 x 8-camera workload (torus+box SDF octree of depth 9,
-3.54M leaves, SH degree 3, FP32 leaves), inputs resident in HBM.  The JSON
-line also carries the roofline of the render kernel, the FP64 CPU oracle as
-a baseline, and the other measured forms of the hot path (FP16/BF16 leaves,
-the differentiable training step, refinement, serving latency).
+Step = one forward render (Eq. 1-2) of the 800x800 x 8-camera workload
+(torus+box SDF octree of depth 9, 3.54M leaves, SH degree 3, FP32 leaves),
+inputs resident in HBM.  The JSON line also carries the roofline of the render
+kernel (compulsory bytes: every distinct leaf the frame composites fetched
+once), the same frame with the fused max-weight signal (its buffer cleared in
+every step), the FP64 CPU oracle as a baseline, and the other measured forms
+of the hot path (FP16/BF16/palette leaves, the differentiable training step,
+refinement, serving latency).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
@@ -81,8 +83,8 @@ def main():
     ap.add_argument("--alg1-epochs", type=int, default=4, help="epochs of the end-to-end training loop (0: skip)")
     ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "terrain", "palette", "ablation"],
                     help="run one secondary measurement alone and print its JSON (for profiling it)")
-    ap.add_argument("--profile-copy", action="store_true",
-                    help="run one 1 GiB device copy and one render (counter calibration runs)")
+    ap.add_argument("--profile-copy", nargs="?", const="plain", choices=["plain", "fused"],
+                    help="run one 1 GiB device copy and four renders of the timed kind (counter runs)")
     ap.add_argument("--profile-dtypes", action="store_true",
                     help="render the benchmark frame once per leaf storage (FP32, FP16, BF16) for counter runs")
     args = ap.parse_args()
@@ -125,28 +127,38 @@ def main():
     lib = L.load()
 
     def step():
+        # the timed step: the plain render of the 8 views (no signal)
+        L.check(lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(opts), C.c_void_p(rgb.data_ptr()),
+                               None, None, core._stream()))
+
+    def fused_step():
+        # render with the fused max-weight signal into a signal buffer cleared first
+        signal.zero_()
         L.check(lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(opts), C.c_void_p(rgb.data_ptr()),
                                None, C.c_void_p(signal.data_ptr()), core._stream()))
 
     if args.profile_dtypes:
         for st in ("f32", "f16", "bf16"):
             t = tree if st == "f32" else core.Octree.from_scene(scene, st)
-            signal.zero_()
-            for _ in range(2):
+            for _ in range(3):
                 L.check(lib.dot_render(t.handle, C.byref(rays.struct), C.byref(opts), C.c_void_p(rgb.data_ptr()),
-                                       None, C.c_void_p(signal.data_ptr()), core._stream()))
+                                       None, None, core._stream()))
             torch.cuda.synchronize()
             if t is not tree:
                 t.close()
-        log("profile-dtypes: two renders per storage type done")
+        log("profile-dtypes: three plain renders per storage type done")
         return
     if args.profile_copy:
+        # counter calibration: a copy of known size, then the launch kind bench.py
+        # times (one warm-up render, then three timed-like renders back to back)
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
-        step()
         torch.cuda.synchronize()
-        log("profile-copy: one 1 GiB copy and one render done")
+        for _ in range(4):
+            fused_step() if args.profile_copy == "fused" else step()
+        torch.cuda.synchronize()
+        log(f"profile-copy: one 1 GiB copy and four {args.profile_copy} renders done")
         return
 
     for _ in range(args.warmup):
@@ -159,38 +171,49 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms = elapsed / args.steps * 1e3
     value = n_rays / (elapsed / args.steps) / 1e6
-    log(f"render fp32: {ms:.3f} ms/step, {value:.1f} Mrays/s")
+    log(f"render fp32 (plain): {ms:.3f} ms/step, {value:.1f} Mrays/s")
 
     # ---- roofline of the render kernel ----
     stats = tree.render_stats(rays)
     K = (scene.degree + 1) ** 2
+    row_bytes = 4 + 3 * K * 4
     leaf_bytes = stats["segments"] * 4 + stats["sh_fetches"] * 3 * K * 4
     kt = time_kernel(step, max(5, args.steps // 2), torch)
-    achieved = leaf_bytes / kt / 1e9
-    other = stats["index_reads"] * 4 + n_rays * 12 + stats["sh_fetches"] * 4
+    other = stats["index_reads"] * 4 + n_rays * 12
     # compulsory bytes: every distinct leaf the frame composites, fetched once
-    # (leaves with a positive signal received a positive weight, hence an SH fetch)
-    signal.zero_()
-    step()
+    # (a leaf with a positive signal received a positive weight, hence an SH
+    # fetch), plus the image written once
+    fused_step()
     n_touched = int((signal > 0).sum().item())
-    compulsory = n_touched * (4 + 3 * K * 4)
+    compulsory = n_touched * row_bytes + n_rays * 12
+    achieved = compulsory / kt / 1e9
     traffic = read_traffic()
+    tb = None if traffic is None else traffic["hbm_bytes_per_launch"]
     achievable = stream_read_gbps(torch, L, lib)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
-                "kernel": "render_fwd_kernel<F32,deg3>", "kernel_ms": round(kt * 1e3, 4),
-                "algorithmic_bytes_per_launch": int(leaf_bytes),
-                "per_unit": "4 B sigma per segment + 192 B SH per segment with sigma*delta > 0",
-                "units_per_launch": {"segments": stats["segments"], "sh_fetches": stats["sh_fetches"]},
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
+                "kernel": "render_fwd_kernel<F32,deg3> (plain render, no signal)", "kernel_ms": round(kt * 1e3, 4),
+                "per_unit": f"{row_bytes} B per distinct leaf composited (4 B sigma + {3 * K * 4} B SH, fetched "
+                            "once) + 12 B rgb per ray",
+                "units_per_launch": {"distinct_leaves_composited": n_touched, "rays": n_rays},
+                "compulsory_bytes_per_launch": int(compulsory),
+                "traffic_over_compulsory": None if tb is None else round(tb / compulsory, 2),
+                "traffic_GBps": None if tb is None else round(tb / kt / 1e9, 1),
+                "traffic_note": "FETCH_SIZE x read scale + WRITE_SIZE x write scale per plain render launch "
+                                "(rocprofv3, same launch kind as timed); FETCH_SIZE counts Infinity-Cache hits "
+                                "as well as HBM reads, so it bounds HBM traffic from above",
+                "cache_inclusive_leaf_bytes_per_launch": int(leaf_bytes),
+                "cache_inclusive_leaf_GBps": round(leaf_bytes / kt / 1e9, 1),
+                "cache_inclusive_per_unit": "4 B sigma per segment + 192 B SH per segment with sigma*delta > 0 "
+                                            "(what the lanes request; caches serve most of it)",
+                "cache_inclusive_units": {"segments": stats["segments"], "sh_fetches": stats["sh_fetches"]},
                 "other_bytes_per_launch": {"child_and_link_reads": stats["index_reads"] * 4, "rgb": n_rays * 12,
-                                           "signal_reads": stats["sh_fetches"] * 4, "total": int(other)},
-                "compulsory_bytes_per_launch": compulsory, "distinct_leaves_composited": n_touched,
-                "compulsory_GBps": round(compulsory / kt / 1e9, 1),
-                "achievable_read_GBps": round(achievable, 1),
-                "traffic_GBps": None if traffic is None else round(traffic["hbm_bytes_per_launch"] / kt / 1e9, 1)}
-    log(f"render kernel {kt * 1e3:.3f} ms; leaf-fetch {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak);"
-        f" segments/ray {stats['segments'] / n_rays:.2f}")
+                                           "total": int(other)},
+                "achievable_read_GBps": round(achievable, 1)}
+    log(f"render kernel {kt * 1e3:.3f} ms; compulsory {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM "
+        f"peak); cache-inclusive leaf bytes {leaf_bytes / kt / 1e9:.1f} GB/s; segments/ray "
+        f"{stats['segments'] / n_rays:.2f}")
+    fused = fused_signal_forms(torch, tree, rays, signal, rgb, fused_step, args)
 
     extra = {}
     if not args.no_extra:
@@ -207,11 +230,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded SDF octree, random SH; stands in for NeRF-synthetic 800x800 views)",
         "config": {"workload": "torus+box SDF octree, depth 9, %d leaves, SH degree 3, FP32 leaves, "
-                               "8 cameras x 800x800 on the radius-4 sphere, white bg, t_stop 1e-4, fused "
-                               "max-weight signal" % scene.n_leaves,
-                   "rays_per_step": n_rays, "parallelism": "single GPU"},
+                               "8 cameras x 800x800 on the radius-4 sphere, white bg, t_stop 1e-4, plain "
+                               "render" % scene.n_leaves,
+                   "rays_per_step": n_rays, "parallelism": "single GPU",
+                   "signal": "none in the timed step; the fused max-weight signal is timed separately "
+                             "(fused_signal), its buffer cleared inside every step"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fused_signal": fused,
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
@@ -236,33 +262,76 @@ def stream_read_gbps(torch, L, lib):
     return gbps
 
 
+def fused_signal_forms(torch, tree, rays, signal, rgb, fused_step, args):
+    """The render with the fused max-weight signal (Sec. 3.1) on the benchmark
+    frame.  Each timed step clears the signal buffer and renders into it, so
+    every launch issues the atomics of a fresh signal; the clear alone is timed
+    beside it.  The steady state -- the same frame rendered again into a filled
+    buffer, where the max filter skips every atomic -- is reported as a
+    labelled extra only."""
+    import ctypes as C
+    from paper_2307_15333_amd import _lib as L, core
+    reps = max(5, args.steps // 2)
+    kt = time_kernel(fused_step, reps, torch)
+    fill = time_kernel(signal.zero_, reps, torch)
+    op = core.render_opts()
+
+    def steady():
+        L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op), C.c_void_p(rgb.data_ptr()),
+                                    None, C.c_void_p(signal.data_ptr()), core._stream()))
+
+    ks = time_kernel(steady, reps, torch)
+    out = {"ms_per_step": round(kt * 1e3, 4), "mrays": round(rays.n_rays / kt / 1e6, 1),
+           "signal_clear_ms": round(fill * 1e3, 4), "render_ms": round((kt - fill) * 1e3, 4),
+           "steady_state_filled_buffer_ms": round(ks * 1e3, 4),
+           "note": "step = clear the [L] signal + render with fused max-weight signal; steady state = the same "
+                   "frame into an already filled buffer (no atomics pass the filter), not a workload"}
+    log(f"render fp32 + fused signal (cleared each step): {kt * 1e3:.3f} ms ({rays.n_rays / kt / 1e6:.1f} Mrays/s; "
+        f"clear {fill * 1e3:.3f} ms); steady state into a filled buffer {ks * 1e3:.3f} ms")
+    return out
+
+
+def render_times(torch, core, tree, rays, args):
+    """(plain render time, render-with-fused-signal time incl. the signal clear) of one tree."""
+    import ctypes as C
+    from paper_2307_15333_amd import _lib as L
+    sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
+    rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device="cuda")
+    op = core.render_opts()
+
+    def plain():
+        L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op), C.c_void_p(rgb.data_ptr()),
+                                    None, None, core._stream()))
+
+    def fused():
+        sig.zero_()
+        L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op), C.c_void_p(rgb.data_ptr()),
+                                    None, C.c_void_p(sig.data_ptr()), core._stream()))
+
+    reps = max(5, args.steps // 2)
+    return time_kernel(plain, reps, torch), time_kernel(fused, reps, torch), rgb
+
+
 def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
-    """FP16/BF16 leaves on the same workload, and the training step."""
+    """FP16/BF16 leaves on the same workload, plain and with the fused signal
+    (cleared each step), then the other forms of the path."""
     res = {}
     rays = core.Rays.cameras(cams)
     base = None
     for storage in ("f32", "f16", "bf16"):
         tree = tree_f32 if storage == "f32" else core.Octree.from_scene(scene, storage)
-        sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
-        rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device="cuda")
-
-        def fn(tree=tree, sig=sig, rgb=rgb):
-            import ctypes as C
-            from paper_2307_15333_amd import _lib as L
-            op = core.render_opts()
-            L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op),
-                                        C.c_void_p(rgb.data_ptr()), None, C.c_void_p(sig.data_ptr()),
-                                        core._stream()))
-
-        kt = time_kernel(fn, max(5, args.steps // 2), torch)
-        mr = rays.n_rays / kt / 1e6
+        kp, kf, _ = render_times(torch, core, tree, rays, args)
+        mp, mf = rays.n_rays / kp / 1e6, rays.n_rays / kf / 1e6
         if storage == "f32":
-            base = mr
-        res[f"render_{storage}_mrays"] = round(mr, 1)
+            base = (mp, mf)
+        res[f"render_{storage}_mrays"] = round(mp, 1)
+        res[f"render_{storage}_fused_signal_mrays"] = round(mf, 1)
         if storage != "f32":
-            res[f"render_{storage}_speedup_vs_f32"] = round(mr / base, 3)
+            res[f"render_{storage}_speedup_vs_f32"] = round(mp / base[0], 3)
+            res[f"render_{storage}_fused_signal_speedup_vs_f32"] = round(mf / base[1], 3)
             tree.close()
-        log(f"render {storage}: {kt * 1e3:.3f} ms, {mr:.1f} Mrays/s")
+        log(f"render {storage}: plain {kp * 1e3:.3f} ms ({mp:.1f} Mrays/s), with fused signal {kf * 1e3:.3f} ms "
+            f"({mf:.1f} Mrays/s)")
     res.update(palette_render(torch, core, scene, rays, base, args))
     res.update(train_step(torch, core, synth, args))
     if args.alg1_epochs > 0:
@@ -276,10 +345,8 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
 
 def palette_render(torch, core, scene, rays, base_mrays, args):
     """The torus+box octree compressed by the median-cut palette (2^16 FP16 rows, FP16 sigma,
-    uint16 index per leaf): build time, render Mrays/s with the fused signal,
-    and the image difference against the FP32 tree."""
-    import ctypes as C
-    from paper_2307_15333_amd import _lib as L
+    uint16 index per leaf): build time, render Mrays/s (plain and with the fused
+    signal cleared each step), and the image difference against the FP32 tree."""
     ref_tree = core.Octree.from_scene(scene, "f32")
     ref = ref_tree.render(rays)
     ref_tree.close()
@@ -289,23 +356,19 @@ def palette_render(torch, core, scene, rays, base_mrays, args):
     tree.quantize_sh(16)
     torch.cuda.synchronize()
     t_q = time.perf_counter() - t
-    sig = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
-    rgb = torch.empty((rays.n_rays, 3), dtype=torch.float32, device="cuda")
-    op = core.render_opts()
-
-    def fn():
-        L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op), C.c_void_p(rgb.data_ptr()), None,
-                                    C.c_void_p(sig.data_ptr()), core._stream()))
-
-    kt = time_kernel(fn, max(5, args.steps // 2), torch)
-    mr = rays.n_rays / kt / 1e6
+    kp, kf, rgb = render_times(torch, core, tree, rays, args)
+    mp, mf = rays.n_rays / kp / 1e6, rays.n_rays / kf / 1e6
     mse = float(((rgb - ref) ** 2).mean())
     psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
     tree.close()
-    speed = mr / base_mrays if base_mrays else None
-    log(f"render pal16 (median cut, 2^16 rows): quantize {t_q * 1e3:.0f} ms, {kt * 1e3:.3f} ms, {mr:.1f} Mrays/s "
-        f"(x{speed if speed is None else round(speed, 2)} FP32), PSNR vs FP32 tree {psnr:.1f} dB")
-    return {"render_pal16_mrays": round(mr, 1), "render_pal16_speedup_vs_f32": None if speed is None else round(speed, 3),
+    sp = mp / base_mrays[0] if base_mrays else None
+    sf = mf / base_mrays[1] if base_mrays else None
+    log(f"render pal16 (median cut, 2^16 rows): quantize {t_q * 1e3:.0f} ms, plain {kp * 1e3:.3f} ms ({mp:.1f} "
+        f"Mrays/s, x{sp if sp is None else round(sp, 2)} FP32), fused signal {mf:.1f} Mrays/s, PSNR vs FP32 tree "
+        f"{psnr:.1f} dB")
+    return {"render_pal16_mrays": round(mp, 1), "render_pal16_speedup_vs_f32": None if sp is None else round(sp, 3),
+            "render_pal16_fused_signal_mrays": round(mf, 1),
+            "render_pal16_fused_signal_speedup_vs_f32": None if sf is None else round(sf, 3),
             "pal16_quantize_ms": round(t_q * 1e3, 1), "pal16_psnr_vs_f32_db": round(psnr, 2)}
 
 

@@ -253,13 +253,17 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  buffer the tree allocates on first use and keeps until dot_free, so the
  *  adjoints of one tree must not run concurrently); beyond 8 GiB of
  *  scratch, or if it cannot be allocated, the terms go straight to the
- *  arrays with FP32 atomics.  Summation order, hence the last bits, depends
+ *  arrays with FP32 atomics; the same happens when n_rays times the tree's
+ *  bound on segments per ray (3 * 2^max_depth + 64) reaches 2^32, since
+ *  bucket offsets are 32-bit.  Summation order, hence the last bits, depends
  *  on scheduling.  leaf_count: NULL, or the [2][n_leaves] counts
  *  dot_render_train wrote for the same tree, rays and opts (the counting
  *  traversal is then skipped; counts or records from another batch give wrong
  *  gradients, never an access outside the buffers).  records: NULL, or the
  *  records that same dot_render_train call wrote (requires leaf_count;
- *  `records_bytes` as given to it).
+ *  `records_bytes` as given to it).  leaf_count without records (also after a
+ *  forward that recorded) re-traverses every ray and uses the two counts
+ *  summed.
  */
 int dot_render_backward(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
                         const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,

@@ -185,6 +185,8 @@ struct BwdArgs {
     float* v_sh;
     const dot_rmsprop_params* rms;
     const dot_adam_params* adam;
+    // rows of the bucket array, set by the adjoint before its emit kernels run
+    uint32_t n_rows = 0;
 };
 
 // The optimiser updates below are evaluated without contraction into FMAs, so

@@ -176,6 +176,7 @@ struct BwdEmit {
     const uint32_t* count;    // [L] rows of the second region
     uint32_t* cursor;
     float* rows;
+    uint32_t n_rows;          // rows of the bucket array: every store stays below it
     float Y[K];
     float d[3];
     float S = 0.f, T = 1.f;
@@ -185,8 +186,8 @@ struct BwdEmit {
     int skip = 0;             // contributing segments not to emit
 
     __device__ BwdEmit(const TreeView& tv_, const uint32_t* o, const uint32_t* b0, const uint32_t* n_, uint32_t* c,
-                       float* r)
-        : tv(tv_), offset(o), base0(b0), count(n_), cursor(c), rows(r) {}
+                       float* r, uint32_t nr)
+        : tv(tv_), offset(o), base0(b0), count(n_), cursor(c), rows(r), n_rows(nr) {}
 
     __device__ __forceinline__ bool operator()(int leaf, float delta) {
         ++n;
@@ -242,9 +243,9 @@ struct BwdEmit {
             // the region holds exactly the segments the counting found; a slot
             // past it is never written (the reduction reads written rows only)
             uint32_t k = atomicAdd(&cursor[leaf], 1u);
-            if (k < count[leaf]) {
-                const uint32_t b = base0 ? base0[leaf] : 0u;
-                float4* dst = reinterpret_cast<float4*>(rows + ((int64_t)offset[leaf] + b + k) * RS);
+            const uint64_t slot = (uint64_t)offset[leaf] + (base0 ? base0[leaf] : 0u) + k;
+            if (k < count[leaf] && slot < n_rows) {
+                float4* dst = reinterpret_cast<float4*>(rows + (int64_t)slot * RS);
 #pragma unroll
                 for (int j = 0; j < RS / 4; ++j)
                     dst[j] = make_float4(out[4 * j], out[4 * j + 1], out[4 * j + 2], out[4 * j + 3]);
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_kernel(TreeView tv, RayBatch r
     Ray r;
     int64_t rid;
     if (!make_ray(rb, tile, lane, r, rid)) return;
-    BwdEmit<DT, DEG> seg(tv, offset, base0, count, cursor, rows);
+    BwdEmit<DT, DEG> seg(tv, offset, base0, count, cursor, rows, a.n_rows);
     seg.limit = a.nseg[rid];
     if (seg.limit <= 0) return;
 #pragma unroll
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_emit_list_kernel(TreeView tv, RayBa
     const int64_t rid = list[i];
     if (rid < 0 || rid >= rb.n_rays) return;
     Ray r = ray_of(rb, rid);
-    BwdEmit<DT, DEG> seg(tv, offset, base0, count, cursor, rows);
+    BwdEmit<DT, DEG> seg(tv, offset, base0, count, cursor, rows, a.n_rows);
     seg.limit = a.nseg[rid];
     seg.skip = a.rec.cap;
     if (seg.limit <= 0) return;
@@ -981,13 +982,18 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     const int64_t L = t.n_leaves;
     const int rs = bwd_row_floats_rt(t.degree);
     TreeView tv = t.view();
-    // Bucket regions: with the training forward's counts, base0 = its recorded
-    // counts and count = its other counts; else no recorded region and count =
-    // our own counting pass.  `total` = base0 + count feeds the scan.
-    const uint32_t* base0 = a.leaf_count;
+    // Bucket regions: with the training forward's counts and its records,
+    // base0 = its recorded counts (rows the replay writes) and count = its
+    // other counts; with its counts but no records, every segment goes through
+    // the cursors, so there is no recorded region and count = the sum of the
+    // two (a forward that recorded would otherwise leave its recorded region
+    // unwritten); without counts, count = our own counting pass.  `total` =
+    // all rows of a leaf's bucket, which feeds the scan.
+    const bool replay = a.leaf_count && a.rec.a;
+    const uint32_t* base0 = replay ? a.leaf_count : nullptr;
     uint32_t* count_own = a.leaf_count ? nullptr : static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
-    const uint32_t* count = a.leaf_count ? a.leaf_count + L : count_own;
     uint32_t* total = a.leaf_count ? static_cast<uint32_t*>(t.alloc.get((size_t)L * 4)) : count_own;
+    const uint32_t* count = replay ? a.leaf_count + L : total;
     uint32_t* offset = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
     uint32_t* cursor = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
     uint32_t* bsum = static_cast<uint32_t*>(t.alloc.get((size_t)scan_scratch_elems(L) * 4));
@@ -1000,7 +1006,11 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         t.alloc.put(bsum);
         t.alloc.put(tot);
     };
-    if (!total || !offset || !cursor || !bsum || !tot) {
+    // Bucket offsets and the row total are 32-bit: a batch whose contributing
+    // segments (at most max_steps per ray) could reach 2^32 takes the atomic
+    // path instead, so a wrapped total can never size the rows.
+    const bool fits32 = (double)rb.n_rays * (double)tv.max_steps < 4294967295.0;
+    if (!fits32 || !total || !offset || !cursor || !bsum || !tot) {
         drop();
         return fused ? bwd_fused_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
@@ -1015,8 +1025,8 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         }
     } else {
         // tot[1] = the forward's overflow count (zero without records)
-        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, base0, count, total, cursor, L,
-                           a.rec.a ? a.rec.overflow : nullptr, tot + 1);
+        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, a.leaf_count, a.leaf_count + L, total, cursor,
+                           L, a.rec.a ? a.rec.overflow : nullptr, tot + 1);
     }
     hipError_t e = scan_u32(total, offset, L, bsum, tot, s);
     // the row total and the overflow count in one copy into pinned memory, one wait
@@ -1038,6 +1048,8 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         drop();
         return fused ? bwd_fused_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
     }
+    BwdArgs ae = a;
+    ae.n_rows = m;
     if (a.rec.a) {
         // replay the recorded segments; re-traverse only the rays with more
         switch (t.degree) {
@@ -1051,17 +1063,17 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
             const int64_t no = std::min<int64_t>(overflow, rb.n_rays);
             const dim3 lg((unsigned)((no + BLOCK - 1) / BLOCK));
             switch (t.degree) {
-                case 0: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 0>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
-                case 1: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 1>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
-                case 2: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 2>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
-                default: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 3>), lg, dim3(BLOCK), 0, s, tv, rb, a, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+                case 0: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 0>), lg, dim3(BLOCK), 0, s, tv, rb, ae, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+                case 1: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 1>), lg, dim3(BLOCK), 0, s, tv, rb, ae, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+                case 2: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 2>), lg, dim3(BLOCK), 0, s, tv, rb, ae, a.rec.olist, no, offset, base0, count, cursor, rows); break;
+                default: hipLaunchKernelGGL((bwd_emit_list_kernel<DOT_F32, 3>), lg, dim3(BLOCK), 0, s, tv, rb, ae, a.rec.olist, no, offset, base0, count, cursor, rows); break;
             }
         }
     } else {
         switch (t.storage) {
-            case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, a, offset, base0, count, cursor, rows, grid, s); break;
-            case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, a, offset, base0, count, cursor, rows, grid, s); break;
-            default: launch_emit<DOT_BF16>(t.degree, tv, rb, a, offset, base0, count, cursor, rows, grid, s); break;
+            case DOT_F32: launch_emit<DOT_F32>(t.degree, tv, rb, ae, offset, base0, count, cursor, rows, grid, s); break;
+            case DOT_F16: launch_emit<DOT_F16>(t.degree, tv, rb, ae, offset, base0, count, cursor, rows, grid, s); break;
+            default: launch_emit<DOT_BF16>(t.degree, tv, rb, ae, offset, base0, count, cursor, rows, grid, s); break;
         }
     }
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);

@@ -3,12 +3,13 @@
 Gradients are compared with the FP64 oracle's analytic gradient (itself pinned
 by central differences) with t_stop = 0, where the render is smooth: the
 infinity-norm error of each gradient array relative to its infinity norm must
-be <= 1e-4.  Adam is compared with torch.optim.Adam on the CPU.
+be <= 1e-4.  Adam is compared with the oracle's FP64 Adam.
 """
 import numpy as np
 import pytest
 import torch
 
+from oracle import alg1 as A
 from oracle import oracle as O
 from paper_2307_15333_amd import synth
 
@@ -99,27 +100,26 @@ def test_autograd_function_mse(record_segments):
     tree.close()
 
 
-def test_adam_step_matches_torch_adam():
+def test_adam_step_matches_oracle_adam():
+    """dot_adam_step over three steps against the oracle's Adam in FP64 on the
+    same FP32 gradients (lr 0.1 for sigma, 0.01 for SH)."""
     core = _core()
     s = synth.random_tree_scene(4, 2, seed=9)
     tree = core.Octree.from_scene(s)
     Ln, K = tree.n_leaves, tree.K
     rng = np.random.default_rng(0)
     state = tree.adam_state()
-    p_sig = torch.tensor(s.sigma.copy(), requires_grad=True)
-    p_sh = torch.tensor(s.sh.copy(), requires_grad=True)
-    opt = torch.optim.Adam([{"params": [p_sig], "lr": 0.1}, {"params": [p_sh], "lr": 0.01}],
-                           betas=(0.9, 0.999), eps=1e-8)
+    th_s, th_h = s.sigma.astype(np.float64), s.sh.astype(np.float64)
+    m_s, v_s, m_h, v_h = (np.zeros_like(th_s), np.zeros_like(th_s), np.zeros_like(th_h), np.zeros_like(th_h))
     for step in range(1, 4):
         gs = rng.normal(size=Ln).astype(np.float32)
         gh = rng.normal(size=(Ln, 3, K)).astype(np.float32)
         tree.adam_step(torch.tensor(gs, device="cuda"), torch.tensor(gh, device="cuda"), state, step)
-        p_sig.grad = torch.tensor(gs)
-        p_sh.grad = torch.tensor(gh)
-        opt.step()
+        th_s, m_s, v_s = A.adam(th_s, gs.astype(np.float64), m_s, v_s, step, 0.1, 0.9, 0.999, 1e-8)
+        th_h, m_h, v_h = A.adam(th_h, gh.astype(np.float64), m_h, v_h, step, 0.01, 0.9, 0.999, 1e-8)
     ex = tree.export()
-    np.testing.assert_allclose(ex["sigma"], p_sig.detach().numpy(), atol=2e-6, rtol=2e-6)
-    np.testing.assert_allclose(ex["sh"], p_sh.detach().numpy(), atol=2e-6, rtol=2e-6)
+    np.testing.assert_allclose(ex["sigma"], th_s, atol=2e-6, rtol=2e-6)
+    np.testing.assert_allclose(ex["sh"], th_h, atol=2e-6, rtol=2e-6)
     tree.close()
 
 
@@ -232,6 +232,42 @@ def test_backward_replaying_forward_records(scene_kind, max_segments):
         tree.render_train(rays, records=rec[:1000])
     tree.close()
     t2.close()
+
+
+def test_backward_counts_of_recording_forward_without_records():
+    """A training forward that recorded, then an adjoint given its counts but
+    not its records: every ray is re-traversed and each leaf's bucket holds
+    both count regions (no recorded region is left unwritten), so the
+    gradient equals the oracle's.  The fused RMSProp step takes the same
+    path."""
+    core = _core()
+    s = synth.random_tree_scene(5, 2, seed=91, p_split=0.5)
+    views = synth.random_sphere_cameras(5, 3.5, 24, 24, seed=92)
+    ci, pi = synth.pixel_batch(5, 24, 24, 2500, seed=93)
+    rays = core.Rays.pixels(views, ci, pi)
+    tree = core.Octree.from_scene(s)
+    # a records buffer smaller than the longest rays: both count regions are non-empty
+    rec = torch.empty(core.Octree.records_bytes(ci.shape[0], 4), dtype=torch.uint8, device="cuda")
+    rgb, ns, cnt = tree.render_train(rays, t_stop=0.0, records=rec)
+    c2 = cnt.cpu().numpy().reshape(2, -1)
+    assert c2[0].any() and c2[1].any()
+    g = np.random.default_rng(94).normal(size=(ci.shape[0], 3))
+    gt = torch.as_tensor(g, dtype=torch.float32, device="cuda")
+    Ln, K = tree.n_leaves, tree.K
+    gs = torch.zeros(Ln, device="cuda")
+    gh = torch.zeros((Ln, 3, K), device="cuda")
+    # poison the allocator's free memory so unwritten bucket rows would show
+    junk = torch.full((1 << 22,), 1e3, device="cuda")
+    del junk
+    tree.backward(rays, rgb, ns, gt, gs, gh, t_stop=0.0, leaf_count=cnt)
+    torch.cuda.synchronize()
+    o, d = O.camera_rays(views, ci, pi)
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    rs, rh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64), t_stop=0.0)
+    es, eh = _rel(gs.cpu().numpy(), rs), _rel(gh.cpu().numpy(), rh)
+    print(f"counts without records: grad_sigma rel {es:.3e}, grad_sh rel {eh:.3e}")
+    assert es <= GTOL and eh <= GTOL
+    tree.close()
 
 
 def test_backward_torus_box_full_size():

@@ -323,7 +323,7 @@ def test_fused_backward_bit_matches_split_path_full_size(opt):
 @pytest.mark.parametrize("degree", [0, 3])
 def test_fused_backward_adam_matches_oracle(degree):
     """Adjoint + Adam in one call against the oracle's FP64 gradient followed
-    by torch.optim.Adam in FP64 on the CPU (eps = 1e-4, where the update is
+    by the oracle's FP64 Adam (eps = 1e-4, where the update is
     Lipschitz in the gradient with constant lr / eps, as in the RMSProp test);
     then an empty batch (step 2, g = 0): both moments decay and every leaf
     still moves by the decayed first moment, checked against the same FP64
@@ -342,15 +342,12 @@ def test_fused_backward_adam_matches_oracle(degree):
     tree.backward_adam(rays, rgb, ns, torch.as_tensor(g, dtype=torch.float32, device="cuda"), st, 1, eps=1e-4)
     T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
     gs, gh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64))
-    p_sig = torch.tensor(s.sigma.astype(np.float64), requires_grad=True)
-    p_sh = torch.tensor(s.sh.astype(np.float64), requires_grad=True)
-    opt = torch.optim.Adam([{"params": [p_sig], "lr": 0.1}, {"params": [p_sh], "lr": 0.01}], betas=(0.9, 0.999),
-                           eps=1e-4)
-    p_sig.grad, p_sh.grad = torch.tensor(gs), torch.tensor(gh)
-    opt.step()
+    z = np.zeros_like
+    want_s, _, _ = A.adam(s.sigma.astype(np.float64), gs, z(gs), z(gs), 1, 0.1, 0.9, 0.999, 1e-4)
+    want_h, _, _ = A.adam(s.sh.astype(np.float64), gh, z(gh), z(gh), 1, 0.01, 0.9, 0.999, 1e-4)
     ex = tree.export()
-    np.testing.assert_allclose(ex["sigma"], p_sig.detach().numpy(), rtol=1e-6, atol=1e-6)
-    np.testing.assert_allclose(ex["sh"], p_sh.detach().numpy(), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(ex["sigma"], want_s, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(ex["sh"], want_h, rtol=1e-6, atol=1e-6)
     got = _adam_state_np(st)
     # m = (1 - beta1) g carries the gradient's FP32 error (bounded relative to max|g|)
     for key, ref in (("m_sigma", gs), ("m_sh", gh)):
@@ -364,12 +361,11 @@ def test_fused_backward_adam_matches_oracle(degree):
     tree.backward_adam(empty, z, torch.zeros(0, dtype=torch.int32, device="cuda"), z, st, 2, eps=1e-4)
     ex2 = tree.export()
     got2 = _adam_state_np(st)
-    bc1, bc2 = 1.0 - 0.9 ** 2, 1.0 - 0.999 ** 2
     for th_key, m_key, v_key, lr in (("sigma", "m_sigma", "v_sigma", 0.1), ("sh", "m_sh", "v_sh", 0.01)):
-        m2, v2 = 0.9 * s1[m_key], 0.999 * s1[v_key]
+        m1, v1 = s1[m_key].astype(np.float64), s1[v_key].astype(np.float64)
+        want, m2, v2 = A.adam(before[th_key].astype(np.float64), np.zeros_like(m1), m1, v1, 2, lr, 0.9, 0.999, 1e-4)
         np.testing.assert_allclose(got2[m_key], m2, rtol=1e-6, atol=0)
         np.testing.assert_allclose(got2[v_key], v2, rtol=1e-6, atol=0)
-        want = before[th_key].astype(np.float64) - lr * (m2 / bc1) / (np.sqrt(v2 / bc2) + 1e-4)
         np.testing.assert_allclose(ex2[th_key], want, rtol=1e-6, atol=1e-6)
     assert np.any(ex2["sigma"] != before["sigma"])      # untouched leaves move too
     tree.close()
@@ -420,6 +416,7 @@ LOOP_CASES = [
     dict(signal="max", recursive=False, reinit=False, tau=1e-3, gamma=0.03),
     dict(signal="sum", recursive=True, reinit=False, tau=1e-2, gamma=0.03),
     dict(signal="sigma", recursive=False, reinit=True, tau=1e-3, gamma=0.02),
+    dict(signal="max", recursive=False, reinit=False, tau=1e-3, gamma=0.03, optimizer="adam"),
 ]
 THETA_TOL = 1e-5     # per epoch, relative to max(1, |theta|)
 LOSS_TOL = 1e-4
@@ -446,7 +443,8 @@ def loop_inputs():
 def oracle_stage(state, sc, o, d, tgt, perms, case, tau, gamma):
     return A.train(state["child"], state["sigma"], state["sh"], sc.degree, sc.bbox_min, sc.bbox_size, o, d, tgt, perms,
                    BATCH, interval=2, tau=tau, gamma=gamma, max_depth=MAX_DEPTH, recursive=case["recursive"],
-                   reinit=case["reinit"], signal=case["signal"], lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=LOOP_EPS)
+                   reinit=case["reinit"], signal=case["signal"], lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=LOOP_EPS,
+                   optimizer=case.get("optimizer", "rmsprop"), betas=(0.9, 0.999))
 
 
 def _band(h):
@@ -490,7 +488,8 @@ def separated_gamma(h, depth, nominal, n_leaves):
     return (best + 0.5) / n_leaves
 
 
-@pytest.mark.parametrize("case", LOOP_CASES, ids=lambda c: f"{c['signal']}-rec{int(c['recursive'])}-re{int(c['reinit'])}")
+@pytest.mark.parametrize("case", LOOP_CASES, ids=lambda c: f"{c['signal']}-rec{int(c['recursive'])}-re{int(c['reinit'])}"
+                                                         f"-{c.get('optimizer', 'rmsprop')}")
 def test_loop_matches_oracle(case):
     """Two stages of two epochs; each stage ends with a refinement whose tau and
     gamma are chosen, from the oracle's own run, away from selection ties."""
@@ -499,7 +498,8 @@ def test_loop_matches_oracle(case):
     sc, start, cams, o, d, tgt, perms = loop_inputs()
     tree = core.Octree.from_scene(start)
     cfg = TR.TrainConfig(interval=2, batch_rays=BATCH, max_depth=MAX_DEPTH, recursive=case["recursive"],
-                         reinit=case["reinit"], signal=case["signal"], eps=LOOP_EPS)
+                         reinit=case["reinit"], signal=case["signal"], eps=LOOP_EPS,
+                         optimizer=case.get("optimizer", "rmsprop"))
     tr = TR.Trainer(tree, cams, tgt.reshape(N_VIEWS, SIZE, SIZE, 3), cfg)
     state = dict(child=start.child, sigma=start.sigma.astype(np.float64), sh=start.sh32.astype(np.float64))
     depth = np.asarray(start.leaf_depth)
