@@ -405,6 +405,28 @@ int dot_pixel_batch(const int64_t *ray_ids, int64_t n_rays, int32_t width, int32
                     size_t workspace_bytes, void *stream);
 
 /*
+ * dot_pixel_batch_noalloc -- dot_pixel_batch without a workspace argument, for
+ *  callers that cannot allocate device memory (code under HIP graph capture,
+ *  serving or training loops that forbid allocation).  Same arguments, outputs
+ *  and ordering contract as dot_pixel_batch; the scratch is a device array of
+ *  DOT_PIXEL_BATCH_SCRATCH_BYTES that the library holds on every GPU it runs
+ *  on until the process ends (found once per device, with that device
+ *  current).  The call allocates nothing.  All calls on one GPU share that
+ *  array, which keeps the last call's contents (the kernels clear what must
+ *  start at zero): calls that overlap on one GPU (on different streams, or
+ *  from different threads) race and give wrong orders.
+ *  Errors: as dot_pixel_batch, and DOT_EINVAL (before any device work) when
+ *  the batch needs more than DOT_PIXEL_BATCH_SCRATCH_BYTES of scratch, i.e.
+ *  when dot_pixel_batch_workspace(n, width, height, n_cams) exceeds it: about
+ *  4 bytes per ray plus 8 per screen tile, so batches of up to 2^21 rays fit
+ *  for any image set with fewer than 400,000 tiles, and about 3.5M rays of
+ *  100 views at 800x800.
+ */
+#define DOT_PIXEL_BATCH_SCRATCH_BYTES (16u << 20)
+int dot_pixel_batch_noalloc(const int64_t *ray_ids, int64_t n_rays, int32_t width, int32_t height, int32_t n_cams,
+                            int32_t *cam_idx_out, int32_t *pix_idx_out, int64_t *ray_ids_out, void *stream);
+
+/*
  * dot_mse_loss -- the photometric loss of a training step (Sec. 3 and Alg. 1:
  *  the prediction of a permuted ray batch against its ground-truth pixels)
  *  and its gradient with respect to the prediction:

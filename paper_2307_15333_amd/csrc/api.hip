@@ -637,6 +637,30 @@ int dot_pixel_batch(const int64_t* ray_ids, int64_t n_rays, int32_t width, int32
     return DOT_OK;
 }
 
+int dot_pixel_batch_noalloc(const int64_t* ray_ids, int64_t n_rays, int32_t width, int32_t height, int32_t n_cams,
+                            int32_t* cam_idx_out, int32_t* pix_idx_out, int64_t* ray_ids_out, void* stream) {
+    if (n_rays < 0) return fail(DOT_EINVAL, "dot_pixel_batch_noalloc: n_rays < 0");
+    if (width <= 0 || height <= 0 || n_cams <= 0)
+        return fail(DOT_EINVAL, "dot_pixel_batch_noalloc: width, height and n_cams must be positive");
+    if ((int64_t)width * height > INT32_MAX)
+        return fail(DOT_EINVAL, "dot_pixel_batch_noalloc: image larger than 2^31 pixels");
+    if (n_rays > (int64_t)UINT32_MAX) return fail(DOT_EINVAL, "dot_pixel_batch_noalloc: more than 2^32 - 1 rays");
+    if (n_rays == 0) return DOT_OK;
+    if (!ray_ids || !cam_idx_out || !pix_idx_out) return fail(DOT_EINVAL, "dot_pixel_batch_noalloc: NULL ids or outputs");
+    const size_t need = pixel_batch_workspace_bytes(n_rays, width, height, n_cams);
+    if (need > (size_t)DOT_PIXEL_BATCH_SCRATCH_BYTES)
+        return fail(DOT_EINVAL, "dot_pixel_batch_noalloc: the batch needs " + std::to_string(need) +
+                                    " bytes of scratch, more than the " +
+                                    std::to_string((size_t)DOT_PIXEL_BATCH_SCRATCH_BYTES) + " it holds");
+    void* ws = nullptr;
+    hipError_t e = pixel_batch_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(e, "dot_pixel_batch_noalloc: scratch address");
+    e = launch_pixel_batch(ray_ids, n_rays, width, height, n_cams, cam_idx_out, pix_idx_out, ray_ids_out, ws,
+                           static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_pixel_batch_noalloc: launch");
+    return DOT_OK;
+}
+
 int dot_mse_loss(const float* pred, const float* target, const int64_t* target_idx, int64_t n_rays,
                  float* grad_rgb_out, double* loss_out, void* stream) {
     if (n_rays < 0) return fail(DOT_EINVAL, "dot_mse_loss: n_rays < 0");

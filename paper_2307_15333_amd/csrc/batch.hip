@@ -7,6 +7,8 @@
 // the gradient a sum over the batch).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "dot_internal.h"
 
 namespace dot {
@@ -182,6 +184,35 @@ hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t 
         hipLaunchKernelGGL(k_pb_scatter, dim3(grid_of(n)), dim3(256), 0, s, ids, n, g, cursor, rank, cam_out, pix_out,
                            id_out);
     return hipGetLastError();
+}
+
+// Scratch of the no-allocation entry point: one array per GPU, held until the
+// process ends.  In host code `scratch` is only a stand-in for the symbol; the
+// kernels receive the device address hipGetSymbolAddress gives for the current
+// device, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[DOT_PIXEL_BATCH_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t pixel_batch_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace dot

@@ -236,6 +236,9 @@ hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx
 size_t pixel_batch_workspace_bytes(int64_t n, int32_t W, int32_t H, int32_t n_cams);
 hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t H, int32_t n_cams, int32_t* cam_out,
                               int32_t* pix_out, int64_t* id_out, void* ws, hipStream_t s);
+// device address of the no-allocation pixel batch's scratch on the current
+// device (DOT_PIXEL_BATCH_SCRATCH_BYTES)
+hipError_t pixel_batch_scratch(void** out);
 hipError_t launch_stream_read(const void* buf, size_t bytes, float* sink, hipStream_t s);
 size_t jobs_workspace_bytes(int n_jobs);
 int launch_render_jobs(const dot_render_job* jobs, int n_jobs, void* ws, size_t ws_bytes, hipStream_t s);

@@ -171,3 +171,20 @@ def test_batch_and_loss_argument_checks_need_no_device():
     w_sparse = lib.dot_pixel_batch_workspace(1 << 10, 800, 800, 2)
     assert 0 < w_sparse < w_dense
     assert lib.dot_pixel_batch_workspace(4, 4, 4, 0) == 0
+
+
+def test_noalloc_pixel_batch_argument_checks_need_no_device():
+    """The no-allocation pixel batch refuses, before any device work, what
+    dot_pixel_batch refuses and a batch whose scratch exceeds the array the
+    library holds (pointers here are stand-ins that are never dereferenced)."""
+    lib = L.load()
+    fake = C.c_void_p(256)
+    assert lib.dot_pixel_batch_noalloc(None, -1, 4, 4, 1, None, None, None, None) == L.DOT_EINVAL
+    assert lib.dot_pixel_batch_noalloc(None, 4, 0, 4, 1, None, None, None, None) == L.DOT_EINVAL
+    assert lib.dot_pixel_batch_noalloc(None, 4, 4, 4, 1, None, None, None, None) == L.DOT_EINVAL
+    assert b"NULL" in lib.dot_last_error()
+    assert lib.dot_pixel_batch_noalloc(None, 0, 4, 4, 1, None, None, None, None) == L.DOT_OK
+    n = 4_000_000
+    assert lib.dot_pixel_batch_workspace(n, 800, 800, 100) > (16 << 20)
+    assert lib.dot_pixel_batch_noalloc(fake, n, 800, 800, 100, fake, fake, None, None) == L.DOT_EINVAL
+    assert b"scratch" in lib.dot_last_error()
