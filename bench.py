@@ -57,18 +57,20 @@ def read_traffic():
     return rec
 
 
-def time_kernel(fn, reps, torch):
-    """Average duration of `fn` (one kernel launch on the current stream) by
-    HIP events recorded on that stream."""
+def time_kernel(fn, reps, torch, warmup=3):
+    """Median duration of `fn` (the launches it queues on the current stream)
+    over `reps` calls, each bracketed by HIP events recorded on that stream,
+    after `warmup` untimed calls."""
     s = torch.cuda.current_stream()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fn()
-    start.record(s)
-    for _ in range(reps):
+    for _ in range(warmup):
         fn()
-    end.record(s)
-    end.synchronize()
-    return start.elapsed_time(end) / reps / 1e3
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(s)
+        fn()
+        b.record(s)
+    ev[-1][1].synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev])) / 1e3
 
 
 def main():
@@ -81,7 +83,8 @@ def main():
     ap.add_argument("--no-terrain", action="store_true", help="skip the 19M-leaf terrain precision run")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--alg1-epochs", type=int, default=4, help="epochs of the end-to-end training loop (0: skip)")
-    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "terrain", "palette", "ablation"],
+    ap.add_argument("--only", choices=["train", "alg1", "refine", "serve", "serve_sweep", "terrain", "palette",
+                                       "ablation"],
                     help="run one secondary measurement alone and print its JSON (for profiling it)")
     ap.add_argument("--profile-copy", nargs="?", const="plain", choices=["plain", "fused"],
                     help="run one 1 GiB device copy and four renders of the timed kind (counter runs)")
@@ -113,7 +116,8 @@ def main():
               "palette": lambda: palette_render(torch, core, scene, core.Rays.cameras(cams), None, args),
               "ablation": lambda: ablation(torch, core, synth, scene, cams, args),
               "refine": lambda: refine_pass(torch, core, synth, scene),
-              "serve": lambda: serving(torch, core, synth, scene, args)}[args.only]
+              "serve": lambda: serving(torch, core, synth, scene, args),
+              "serve_sweep": lambda: serving_sweep(torch, core, synth, scene, args)}[args.only]
         print(json.dumps(fn()), flush=True)
         return
     tree = core.Octree.from_scene(scene, "f32")
@@ -178,7 +182,7 @@ def main():
     K = (scene.degree + 1) ** 2
     row_bytes = 4 + 3 * K * 4
     leaf_bytes = stats["segments"] * 4 + stats["sh_fetches"] * 3 * K * 4
-    kt = time_kernel(step, max(5, args.steps // 2), torch)
+    kt = time_kernel(step, max(20, args.steps), torch)
     other = stats["index_reads"] * 4 + n_rays * 12
     # compulsory bytes: every distinct leaf the frame composites, fetched once
     # (a leaf with a positive signal received a positive weight, hence an SH
@@ -271,7 +275,7 @@ def fused_signal_forms(torch, tree, rays, signal, rgb, fused_step, args):
     labelled extra only."""
     import ctypes as C
     from paper_2307_15333_amd import _lib as L, core
-    reps = max(5, args.steps // 2)
+    reps = max(20, args.steps)
     kt = time_kernel(fused_step, reps, torch)
     fill = time_kernel(signal.zero_, reps, torch)
     op = core.render_opts()
@@ -308,7 +312,7 @@ def render_times(torch, core, tree, rays, args):
         L.check(tree.lib.dot_render(tree.handle, C.byref(rays.struct), C.byref(op), C.c_void_p(rgb.data_ptr()),
                                     None, C.c_void_p(sig.data_ptr()), core._stream()))
 
-    reps = max(5, args.steps // 2)
+    reps = max(20, args.steps)
     return time_kernel(plain, reps, torch), time_kernel(fused, reps, torch), rgb
 
 
@@ -455,11 +459,10 @@ def refine_pass(torch, core, synth, scene):
             "refine_ms": round(t_ref * 1e3, 2), "refine_stats": st}
 
 
-def serving(torch, core, synth, c2_scene, args):
-    """Serving: four resident FP16 trees (two 8.6k-leaf spheres, two 3.5M-leaf torus+box trees),
-    Poisson arrivals at 200 req/s, resolutions uniform over {128^2, 256^2, 512^2,
-    800^2, 1920x1080}, continuous batching; latency percentiles after a warm-up."""
-    from paper_2307_15333_amd import serve
+def serving_trees(core, synth, c2_scene):
+    """The four resident FP16 trees of the serving workload: two 8.6k-leaf
+    spheres (the second re-seeded), the 3.5M-leaf torus+box tree and a copy of
+    it with re-drawn SH."""
     import dataclasses
     s1a = synth.sphere_scene()
     s1b = synth.make_scene(synth.sdf_sphere(0.5), 5, 2, seed=40)
@@ -467,21 +470,55 @@ def serving(torch, core, synth, c2_scene, args):
     sh_b = c2_scene.sh32.copy()
     sh_b[:, :, 1:] = (rng.standard_normal(sh_b[:, :, 1:].shape, dtype=np.float32) * np.float32(0.1))
     s2b = dataclasses.replace(c2_scene, sh32=sh_b)
-    trees = [core.Octree.from_scene(x, "f16") for x in (s1a, s1b, c2_scene, s2b)]
-    warm = 2.0
-    reqs = serve.poisson_requests(4, rate=200.0, duration=warm + args.serve_seconds, seed=4)
-    srv = serve.Server(trees, out_budget_bytes=2 << 30, max_tiles=65536)
+    return [core.Octree.from_scene(x, "f16") for x in (s1a, s1b, c2_scene, s2b)]
+
+
+def serve_once(serve, trees, rate, seconds, seed=4, warm=2.0, **kw):
+    reqs = serve.poisson_requests(4, rate=rate, duration=warm + seconds, seed=seed)
+    srv = serve.Server(trees, out_budget_bytes=2 << 30, max_tiles=65536, **kw)
     st = srv.run(reqs, warmup=warm)
+    offered = sum(r.rays for r in reqs if r.arrival >= warm) / seconds / 1e6
+    out = {"rate_req_s": rate, "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+           "mean_ms": round(st["mean_ms"], 3), "mrays": round(st["mrays_per_s"], 1),
+           "offered_mrays": round(offered, 1), "req_per_s": round(st["req_per_s"], 1),
+           "requests": st["requests"], "launches": st["launches"],
+           "requests_per_launch": round(st["mean_requests_per_launch"], 2),
+           "tiles_per_launch": round(st["mean_tiles_per_launch"], 1),
+           "gpu_busy_frac": round(st["gpu_busy_frac"], 3), "seconds": seconds}
+    log(f"serving at {rate} req/s: {out}")
+    return out
+
+
+def serving(torch, core, synth, c2_scene, args):
+    """Serving: four resident FP16 trees (two 8.6k-leaf spheres, two 3.5M-leaf torus+box trees),
+    Poisson arrivals at 200 req/s, resolutions uniform over {128^2, 256^2, 512^2,
+    800^2, 1920x1080}, continuous batching; latency percentiles after a warm-up."""
+    from paper_2307_15333_amd import serve
+    trees = serving_trees(core, synth, c2_scene)
+    st = serve_once(serve, trees, 200.0, args.serve_seconds)
     for t in trees:
         t.close()
-    offered = sum(r.rays for r in reqs if r.arrival >= warm) / args.serve_seconds / 1e6
-    log(f"serving: {st['requests']} requests, p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
-        f"{st['mrays_per_s']:.0f} Mrays/s (offered {offered:.0f}), {st['launches']} launches")
-    return {"serve_p50_ms": round(st["p50_ms"], 3), "serve_p99_ms": round(st["p99_ms"], 3),
-            "serve_mean_ms": round(st["mean_ms"], 3), "serve_mrays": round(st["mrays_per_s"], 1),
-            "serve_offered_mrays": round(offered, 1), "serve_req_per_s": round(st["req_per_s"], 1),
-            "serve_requests": st["requests"], "serve_seconds": args.serve_seconds,
-            "serve_launches": st["launches"]}
+    return {"serve_p50_ms": st["p50_ms"], "serve_p99_ms": st["p99_ms"], "serve_mean_ms": st["mean_ms"],
+            "serve_mrays": st["mrays"], "serve_offered_mrays": st["offered_mrays"], "serve_req_per_s": st["req_per_s"],
+            "serve_requests": st["requests"], "serve_seconds": args.serve_seconds, "serve_launches": st["launches"],
+            "serve_requests_per_launch": st["requests_per_launch"], "serve_tiles_per_launch": st["tiles_per_launch"],
+            "serve_gpu_busy_frac": st["gpu_busy_frac"]}
+
+
+def serving_sweep(torch, core, synth, c2_scene, args):
+    """The serving workload at offered loads from 200 req/s to beyond
+    saturation (about 611k rays per request, so 6000 req/s offers ~3.7 Grays/s):
+    per load p50/p99 latency, throughput, requests and tiles per launch, and the
+    fraction of the wall time the GPU spent in launches; launches on one stream
+    (back to back) and round-robin over two streams (a batch can start while
+    the previous one drains)."""
+    from paper_2307_15333_amd import serve
+    trees = serving_trees(core, synth, c2_scene)
+    out = {"sweep": [dict(serve_once(serve, trees, r, args.serve_seconds, streams=k), streams=k)
+                     for k in (1, 2) for r in (200.0, 1000.0, 3000.0, 6000.0)]}
+    for t in trees:
+        t.close()
+    return out
 
 
 def terrain_precision(torch, core, synth, args):
@@ -526,68 +563,85 @@ def _train_setup(torch, core, synth):
 
 
 def train_step(torch, core, synth, args):
-    """One optimisation step -- forward, MSE, hand-written backward, Adam --
-    over 2^18 random rays of 100 64x64 views of the 8.6k-leaf sphere octree (SH
-    perturbed by N(0, 0.05^2)), through the training driver (adjoint and Adam
-    fused); then the same step through the autograd Function (DotRender),
-    PyTorch's MSE and loss.backward(), and the library's Adam on the dense
-    gradients autograd returns."""
+    """The differentiable training step: forward, MSE, hand-written backward,
+    Adam, over 2^18 random rays of 100 64x64 views of the 8.6k-leaf sphere
+    octree (SH perturbed by N(0, 0.05^2)).  Config 4's number is the step
+    through the autograd Function (DotRender, MSELoss, loss.backward(), with
+    Adam applied inside the adjoint by FusedAdam).  Beside it: the training
+    driver's step (adjoint and Adam fused, no autograd), and the autograd step
+    with dense gradients returned to autograd, PyTorch's MSE and a separate
+    Adam kernel."""
     from paper_2307_15333_amd import train as TR
-    tree, views, target = _train_setup(torch, core, synth)
     B = 1 << 18
-    tr = TR.Trainer(tree, views, target, TR.TrainConfig(optimizer="adam", batch_rays=B, refine=False, seed=3))
-    perm = tr.permutation()
-    idx = perm[:B]
-    for _ in range(2):
-        tr.step(idx)
-    torch.cuda.synchronize()
-    steps = 10
-    losses = []
-    t = time.perf_counter()
-    for _ in range(steps):
-        losses.append(tr.step(idx))
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / steps
-    tree.close()
-    l0, l1 = float(losses[0]), float(losses[-1])
-    log(f"train step: {dt * 1e3:.3f} ms, {B / dt / 1e6:.1f} Mrays/s, loss {l0:.3e} -> {l1:.3e}")
-
-    # the autograd route over the same batch
-    tree, views, target = _train_setup(torch, core, synth)
+    steps = 20
     W = H = 64
-    _, cams_raw = core.Rays._cams_tensor(views, "cuda")
-    sigma, sh = tree.plane_views()
-    p_sig, p_sh = sigma.detach().requires_grad_(), sh.detach().requires_grad_()     # alias the planes
-    state = tree.adam_state()
-    ws = None
-    a_losses = []
 
-    def step(k):
-        nonlocal ws
-        cam, pix, ids, ws = core.pixel_batch(idx, W, H, len(views), ws)
-        rays = core.Rays.pixels_device(cams_raw, len(views), cam, pix)
-        rgb = core.render_autograd(tree, p_sig, p_sh, rays)
-        loss = torch.nn.functional.mse_loss(rgb, target[ids])
-        p_sig.grad = p_sh.grad = None
-        loss.backward()
-        tree.adam_step(p_sig.grad, p_sh.grad, state, k)
-        return loss.detach()
+    def timed(step_fn, n_warm=3):
+        for k in range(n_warm):
+            step_fn()
+        torch.cuda.synchronize()
+        losses = []
+        t = time.perf_counter()
+        for _ in range(steps):
+            losses.append(step_fn())
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, float(losses[0]), float(losses[-1])
 
-    for k in range(1, 3):
-        step(k)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for k in range(3, 3 + steps):
-        a_losses.append(step(k))
-    torch.cuda.synchronize()
-    da = (time.perf_counter() - t) / steps
+    # the training driver
+    tree, views, target = _train_setup(torch, core, synth)
+    tr = TR.Trainer(tree, views, target, TR.TrainConfig(optimizer="adam", batch_rays=B, refine=False, seed=3))
+    idx = tr.permutation()[:B]
+    dd, d0, d1 = timed(lambda: tr.step(idx))
     tree.close()
-    log(f"train step (autograd Function): {da * 1e3:.3f} ms, {B / da / 1e6:.1f} Mrays/s, "
-        f"loss {float(a_losses[0]):.3e} -> {float(a_losses[-1]):.3e}")
-    return {"train_step_ms": round(dt * 1e3, 3), "train_step_mrays": round(B / dt / 1e6, 1),
-            "train_rays_per_step": B, "train_loss_first_last": [l0, l1],
-            "train_step_autograd_ms": round(da * 1e3, 3), "train_step_autograd_mrays": round(B / da / 1e6, 1),
-            "train_autograd_loss_first_last": [float(a_losses[0]), float(a_losses[-1])]}
+    log(f"train step (training driver): {dd * 1e3:.3f} ms, {B / dd / 1e6:.1f} Mrays/s, loss {d0:.3e} -> {d1:.3e}")
+
+    def autograd_step_fn(dense):
+        tree, views, target = _train_setup(torch, core, synth)
+        _, cams_raw = core.Rays._cams_tensor(views, "cuda")
+        sigma, sh = tree.plane_views()
+        p_sig, p_sh = sigma.detach().requires_grad_(), sh.detach().requires_grad_()     # alias the planes
+        opt = None if dense else core.FusedAdam(tree)
+        state = tree.adam_state() if dense else None
+        st = {"ws": None, "k": 0}
+
+        def step():
+            cam, pix, ids, st["ws"] = core.pixel_batch(idx, W, H, len(views), st["ws"])
+            rays = core.Rays.pixels_device(cams_raw, len(views), cam, pix)
+            if dense:
+                rgb = core.render_autograd(tree, p_sig, p_sh, rays)
+                loss = torch.nn.functional.mse_loss(rgb, target[ids])
+                p_sig.grad = p_sh.grad = None
+                loss.backward()
+                st["k"] += 1
+                tree.adam_step(p_sig.grad, p_sh.grad, state, st["k"])
+            else:
+                rgb = core.render_autograd(tree, p_sig, p_sh, rays, optimizer=opt)
+                loss = core.mse_loss_autograd(rgb, target, ids)
+                loss.backward()
+            return loss.detach()
+
+        return tree, step
+
+    tree, fn = autograd_step_fn(False)
+    da, a0, a1 = timed(fn)
+    tree.close()
+    log(f"train step (autograd Function, MSELoss, Adam in the adjoint): {da * 1e3:.3f} ms, {B / da / 1e6:.1f} "
+        f"Mrays/s, loss {a0:.3e} -> {a1:.3e}")
+    tree, fn = autograd_step_fn(True)
+    dn, n0, n1 = timed(fn)
+    tree.close()
+    log(f"train step (autograd Function, dense gradients, torch MSE, dot_adam_step): {dn * 1e3:.3f} ms, "
+        f"{B / dn / 1e6:.1f} Mrays/s, loss {n0:.3e} -> {n1:.3e}")
+    return {"train_step_ms": round(da * 1e3, 3), "train_step_mrays": round(B / da / 1e6, 1),
+            "train_rays_per_step": B, "train_loss_first_last": [a0, a1],
+            "train_step_note": "config 4 through the autograd Function (DotRender + MSELoss + loss.backward(), "
+                               "Adam applied inside the adjoint)",
+            "train_driver_step_ms": round(dd * 1e3, 3), "train_driver_step_mrays": round(B / dd / 1e6, 1),
+            "train_driver_loss_first_last": [d0, d1],
+            "train_autograd_over_driver": round(da / dd, 3),
+            "train_step_autograd_dense_ms": round(dn * 1e3, 3),
+            "train_step_autograd_dense_mrays": round(B / dn / 1e6, 1),
+            "train_autograd_dense_loss_first_last": [n0, n1]}
 
 
 def alg1_loop(torch, core, synth, scene, args):

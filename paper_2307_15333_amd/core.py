@@ -227,6 +227,25 @@ class Octree:
                                           C.c_size_t(records.numel() if records is not None else 0), _stream()))
         return rgb, ns, leaf_count
 
+    def _take_records(self, n_rays, max_segments):
+        """A segment-records buffer for a training forward of n_rays rays with
+        room for max_segments per ray: the tree's kept buffer when it is free,
+        else a new one (an earlier forward's records still wait for their
+        backward)."""
+        need = self.records_bytes(n_rays, max_segments)
+        if getattr(self, "_rec_busy", False):
+            return torch.empty(need, dtype=torch.uint8, device=self.device)
+        buf = getattr(self, "_rec_buf", None)
+        if buf is None or buf.numel() < need or buf.numel() > 2 * need:
+            buf = self._rec_buf = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self._rec_busy = True
+        return buf[:need]
+
+    def _release_records(self, rec):
+        buf = getattr(self, "_rec_buf", None)
+        if rec is not None and buf is not None and rec.data_ptr() == buf.data_ptr():
+            self._rec_busy = False
+
     @staticmethod
     @functools.lru_cache(maxsize=64)
     def records_bytes(n_rays, max_segments=96):
@@ -396,6 +415,36 @@ def mse_loss(pred, target, target_idx=None, grad=True, loss=True, grad_out=None)
     return lo, g
 
 
+class FusedAdam:
+    """Adam on a tree's sigma and SH planes, applied inside the adjoint's
+    per-leaf reduction when passed to render_autograd (the dense gradients
+    are never formed); holds the moments and the 1-based step count."""
+
+    def __init__(self, tree, lr_sigma=0.1, lr_sh=0.01, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.tree = tree
+        self.state = tree.adam_state()
+        self.step = 0
+        self.hp = dict(lr_sigma=lr_sigma, lr_sh=lr_sh, beta1=beta1, beta2=beta2, eps=eps)
+
+    def backward_step(self, rays, rgb, nseg, grad_rgb, bg, t_stop, leaf_count, records):
+        self.step += 1
+        self.tree.backward_adam(rays, rgb, nseg, grad_rgb, self.state, self.step, bg=bg, t_stop=t_stop,
+                                leaf_count=leaf_count, records=records, **self.hp)
+
+
+class FusedRMSProp:
+    """RMSProp (Sec. 3.3) applied inside the adjoint's per-leaf reduction; see FusedAdam."""
+
+    def __init__(self, tree, lr_sigma=0.1, lr_sh=0.01, alpha=0.99, eps=1e-8):
+        self.tree = tree
+        self.state = tree.rmsprop_state()
+        self.hp = dict(lr_sigma=lr_sigma, lr_sh=lr_sh, alpha=alpha, eps=eps)
+
+    def backward_step(self, rays, rgb, nseg, grad_rgb, bg, t_stop, leaf_count, records):
+        self.tree.backward_rmsprop(rays, rgb, nseg, grad_rgb, self.state, bg=bg, t_stop=t_stop,
+                                   leaf_count=leaf_count, records=records, **self.hp)
+
+
 class DotRender(torch.autograd.Function):
     """C = render(sigma, sh; rays) with the hand-written adjoint as backward.
 
@@ -406,36 +455,67 @@ class DotRender(torch.autograd.Function):
     segments and records up to ``record_segments`` segments per ray, which the
     adjoint replays instead of traversing the tree again (rays with more are
     re-traversed for the rest); ``record_segments=0`` or reduced-precision
-    leaves give the plain forward and an adjoint by re-traversal."""
+    leaves give the plain forward and an adjoint by re-traversal.  The records
+    live in a buffer the tree keeps between calls, unless an earlier forward's
+    records still wait for their backward.  With ``optimizer`` (FusedAdam or FusedRMSProp) the
+    backward applies that optimiser step to the planes inside the adjoint and
+    returns no gradient for them."""
 
     @staticmethod
-    def forward(ctx, sigma, sh, tree, rays, bg, t_stop, signal=None, signal_mode="max", record_segments=96):
+    def forward(ctx, sigma, sh, tree, rays, bg, t_stop, signal=None, signal_mode="max", record_segments=96,
+                optimizer=None):
         cnt = rec = None
         if tree.storage == "f32" and record_segments > 0:
-            rec = torch.empty(Octree.records_bytes(rays.n_rays, record_segments), dtype=torch.uint8,
-                              device=tree.device)
+            rec = tree._take_records(rays.n_rays, record_segments)
             rgb, nseg, cnt = tree.render_train(rays, bg=bg, t_stop=t_stop, signal=signal, signal_mode=signal_mode,
                                                records=rec)
         else:
             rgb, nseg = tree.render(rays, bg=bg, t_stop=t_stop, nseg=True, signal=signal, signal_mode=signal_mode)
         ctx.save_for_backward(rgb, nseg)
         ctx.tree, ctx.rays, ctx.bg, ctx.t_stop = tree, rays, bg, t_stop
-        ctx.cnt, ctx.rec = cnt, rec
+        ctx.cnt, ctx.rec, ctx.optimizer = cnt, rec, optimizer
         return rgb
 
     @staticmethod
     def backward(ctx, grad_rgb):
         rgb, nseg = ctx.saved_tensors
         tree = ctx.tree
-        Ln = tree.n_leaves
-        gs = torch.zeros(Ln, dtype=torch.float32, device=rgb.device)
-        gh = torch.zeros((Ln, 3, tree.K), dtype=torch.float32, device=rgb.device)
-        tree.backward(ctx.rays, rgb, nseg, grad_rgb.contiguous().float(), gs, gh, bg=ctx.bg, t_stop=ctx.t_stop,
-                      leaf_count=ctx.cnt, records=ctx.rec)
-        ctx.cnt = ctx.rec = None
-        return gs, gh, None, None, None, None, None, None, None
+        g = grad_rgb.contiguous().float()
+        if ctx.optimizer is not None:
+            ctx.optimizer.backward_step(ctx.rays, rgb, nseg, g, ctx.bg, ctx.t_stop, ctx.cnt, ctx.rec)
+            gs = gh = None
+        else:
+            Ln = tree.n_leaves
+            gs = torch.zeros(Ln, dtype=torch.float32, device=rgb.device)
+            gh = torch.zeros((Ln, 3, tree.K), dtype=torch.float32, device=rgb.device)
+            tree.backward(ctx.rays, rgb, nseg, g, gs, gh, bg=ctx.bg, t_stop=ctx.t_stop, leaf_count=ctx.cnt,
+                          records=ctx.rec)
+        tree._release_records(ctx.rec)
+        ctx.cnt = ctx.rec = ctx.optimizer = None
+        return gs, gh, None, None, None, None, None, None, None, None
+
+
+class MSELoss(torch.autograd.Function):
+    """Mean squared error of pred [n, 3] against target rows (Alg. 1's loss),
+    loss and gradient from one kernel (dot_mse_loss); the loss is a float64
+    device scalar."""
+
+    @staticmethod
+    def forward(ctx, pred, target, target_idx=None):
+        loss, grad = mse_loss(pred, target, target_idx)
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        (grad,) = ctx.saved_tensors
+        return grad * grad_loss.to(grad.dtype), None, None
+
+
+def mse_loss_autograd(pred, target, target_idx=None):
+    return MSELoss.apply(pred, target, target_idx)
 
 
 def render_autograd(tree, sigma, sh, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4, signal=None, signal_mode="max",
-                    record_segments=96):
-    return DotRender.apply(sigma, sh, tree, rays, bg, t_stop, signal, signal_mode, record_segments)
+                    record_segments=96, optimizer=None):
+    return DotRender.apply(sigma, sh, tree, rays, bg, t_stop, signal, signal_mode, record_segments, optimizer)

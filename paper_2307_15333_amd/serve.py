@@ -20,7 +20,9 @@ While work is queued or running the loop polls (no sleep), so completions and
 arrivals are seen within one event query; when idle it sleeps until `spin_s`
 before the next arrival.
 
-Latency = completion time - arrival time (host clock, event-polled).  The
+Latency = completion time - arrival time (host clock, event-polled).  Each
+launch is bracketed by two timing events; the union of those intervals over
+the run gives the fraction of the wall time the GPU spent in launches.  The
 image a request receives is independent of the batch it was packed into: every
 pixel runs the same per-ray code on the same tree and camera.
 """
@@ -67,7 +69,7 @@ class Request:
 
 class Server:
     def __init__(self, trees, out_budget_bytes=2 << 30, max_active=64, max_tiles=65536, max_inflight=2,
-                 device="cuda", spin_s=3e-4):
+                 device="cuda", spin_s=3e-4, streams=1):
         self.trees = trees
         self.lib = L.load()
         self.device = torch.device(device)
@@ -78,15 +80,22 @@ class Server:
         self.spin_s = float(spin_s)
         self.used = 0
         self.max_used = 0
-        self.ws_bytes = 0
-        self.ws = None
+        # launches go round-robin over `streams` streams (default priority), each
+        # with its own job-table workspace, so a batch can start while the
+        # previous one drains; with one stream they run back to back
+        self.streams = [torch.cuda.current_stream(self.device)] if streams <= 1 else \
+            [torch.cuda.Stream(self.device) for _ in range(streams)]
+        self.ws = [None] * len(self.streams)
+        self.ws_bytes = [0] * len(self.streams)
+        self._next_stream = 0
 
-    def _workspace(self, n_jobs):
+    def _workspace(self, n_jobs, k=0):
         need = int(self.lib.dot_render_jobs_workspace(n_jobs))
-        if need > self.ws_bytes:
-            self.ws = torch.empty(need * 2, dtype=torch.uint8, device=self.device)
-            self.ws_bytes = need * 2
-        return self.ws
+        if need > self.ws_bytes[k]:
+            with torch.cuda.stream(self.streams[k]):
+                self.ws[k] = torch.empty(need * 2, dtype=torch.uint8, device=self.device)
+            self.ws_bytes[k] = need * 2
+        return self.ws[k]
 
     def _admit(self, req, now):
         req.n_tiles = ((req.width + 7) // 8) * ((req.height + 7) // 8)
@@ -99,8 +108,8 @@ class Server:
         self.used += req.out_bytes
         self.max_used = max(self.max_used, self.used)
 
-    def launch(self, batch):
-        """batch: list of (request, tile_begin, tile_count) -> one persistent launch."""
+    def launch(self, batch, k=0):
+        """batch: list of (request, tile_begin, tile_count) -> one persistent launch on stream k."""
         n = len(batch)
         jobs = (L.dot_render_job * n)()
         for i, (r, b, c) in enumerate(batch):
@@ -113,9 +122,12 @@ class Server:
             for a in range(3):
                 j.bg[a] = float(r.bg[a])
             j.t_stop = float(r.t_stop)
-        ws = self._workspace(n)
-        L.check(self.lib.dot_render_jobs(jobs, n, C.c_void_p(ws.data_ptr()), C.c_size_t(self.ws_bytes),
-                                         core._stream()))
+        ws = self._workspace(n, k)
+        if self.streams[k] != torch.cuda.current_stream(self.device):
+            # the cameras were uploaded on the current stream at admission
+            self.streams[k].wait_stream(torch.cuda.current_stream(self.device))
+        L.check(self.lib.dot_render_jobs(jobs, n, C.c_void_p(ws.data_ptr()), C.c_size_t(self.ws_bytes[k]),
+                                         C.c_void_p(self.streams[k].cuda_stream)))
 
     def run(self, requests, duration=None, warmup=0.0, keep_outputs=False, on_complete=None):
         """Serve `requests` (sorted by arrival) in real time.  Returns stats over
@@ -126,6 +138,11 @@ class Server:
         t0 = time.perf_counter()
         launches = 0
         tiles_launched = 0
+        reqs_launched = 0
+        spans = []
+        torch.cuda.synchronize(self.device)
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record()
         while pending or waiting or active or inflight:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
@@ -156,17 +173,24 @@ class Server:
                     if r.next_tile == r.n_tiles:
                         finishing.append(r)
                 if batch:
-                    self.launch(batch)
-                    ev = torch.cuda.Event()
-                    ev.record()
-                    inflight.append((ev, finishing))
+                    k = self._next_stream
+                    self._next_stream = (k + 1) % len(self.streams)
+                    st = self.streams[k]
+                    ev0 = torch.cuda.Event(enable_timing=True)
+                    ev0.record(st)
+                    self.launch(batch, k)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(st)
+                    inflight.append((ev, finishing, ev0))
                     launches += 1
                     tiles_launched += self.max_tiles - room
+                    reqs_launched += len(batch)
                     continue
             # 4. retire finished launches in order
             progressed = False
             while inflight and inflight[0][0].query():
-                _, fin = inflight.popleft()
+                ev, fin, ev0 = inflight.popleft()
+                spans.append((ref.elapsed_time(ev0), ref.elapsed_time(ev)))
                 t_done = time.perf_counter() - t0
                 for r in fin:
                     r.done = t_done
@@ -189,6 +213,12 @@ class Server:
             # completion or an arrival is seen within one event query
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # GPU busy time: the union of the launches' [start, end] intervals
+        busy_ms, end_ms = 0.0, -1.0
+        for a, b in sorted(spans):
+            if b > end_ms:
+                busy_ms += b - max(a, end_ms)
+                end_ms = b
         meas = [r for r in completed if r.arrival >= warmup]
         lat = np.array([r.done - r.arrival for r in meas]) * 1e3
         rays = sum(r.rays for r in meas)
@@ -202,6 +232,8 @@ class Server:
             "mrays_per_s": rays / span / 1e6 if span > 0 else None,
             "req_per_s": len(meas) / span if span > 0 else None,
             "wall_s": wall, "mean_tiles_per_launch": tiles_launched / max(launches, 1),
+            "mean_requests_per_launch": reqs_launched / max(launches, 1),
+            "gpu_busy_frac": busy_ms / 1e3 / wall if wall > 0 else None,
             "max_budget_used": self.max_used, "budget": self.budget,
         }
 

@@ -48,9 +48,9 @@ class TrainConfig:
     reinit: bool = False            # ablation: new leaves start at zero instead of fused values
     refine: bool = True
     fused: bool = True              # the optimiser step applied inside the adjoint's per-leaf reduction
-    # segments per ray the forward records for the adjoint's replay; a ray with more is re-traversed for the rest
-    # by a few long-running waves at the end of the adjoint, so the capacity covers the deepest rays (the buffer,
-    # n x capacity x 28 B, is address space: only the recorded slots are written)
+    # upper bound on the segments per ray the forward records for the adjoint's replay; each epoch's first batch
+    # sets the capacity to 5/4 of its longest ray (a ray with more is re-traversed for the rest by a few
+    # long-running waves at the end of the adjoint); the buffer holds n x capacity x 28 B of device memory
     record_segments: int = 256
     bg: tuple = (1.0, 1.0, 1.0)
     t_stop: float = 1e-4
@@ -88,6 +88,8 @@ class Trainer:
         self._ws = None
         self._pb = self._fw = self._grad = None     # per-batch buffers, reused while the batch size stays
         self._rec = None        # segment records of the current batch (forward -> adjoint)
+        self._rec_cap = None    # records per ray, from the longest ray of an epoch's first batch
+        self._size_records = True
         self._reset_optimizer()
 
     def _reset_optimizer(self):
@@ -113,12 +115,19 @@ class Trainer:
         mode = "sum" if c.signal == "sum" else "max"
         # the training forward also counts each leaf's segments and records the
         # composited segments, so the adjoint neither traverses nor refetches
-        need = core.Octree.records_bytes(idx.shape[0], c.record_segments)
-        if self._rec is None or self._rec.numel() < need:
+        # room for the longest ray seen at the first batch of the epoch (with a
+        # margin), at most record_segments; a longer ray is re-traversed for
+        # the rest of its segments
+        cap = c.record_segments if self._rec_cap is None else self._rec_cap
+        need = core.Octree.records_bytes(idx.shape[0], cap)
+        if self._rec is None or self._rec.numel() < need or self._rec.numel() > 2 * need:
             self._rec = torch.empty(need, dtype=torch.uint8, device=self.device)
         rgb, nseg, self._cnt = self.tree.render_train(rays, bg=c.bg, t_stop=c.t_stop, signal=signal, signal_mode=mode,
-                                                      leaf_count=self._cnt, records=self._rec, out=self._fw)
+                                                      leaf_count=self._cnt, records=self._rec[:need], out=self._fw)
         self._fw = (rgb, nseg)
+        if self._size_records:
+            self._size_records = False
+            self._rec_cap = min(c.record_segments, max(8, (int(nseg.max()) * 5 // 4 + 7) // 8 * 8))
         loss, grad = core.mse_loss(rgb, self.targets, ids, grad_out=self._grad)
         self._grad = grad
         self.opt_step += 1
@@ -127,11 +136,11 @@ class Trainer:
             if c.optimizer == "rmsprop":
                 self.tree.backward_rmsprop(rays, rgb, nseg, grad, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
                                            alpha=c.alpha, eps=c.eps, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt,
-                                           records=self._rec)
+                                           records=self._rec[:need])
             else:
                 self.tree.backward_adam(rays, rgb, nseg, grad, self.state, self.opt_step, lr_sigma=c.lr_sigma,
                                         lr_sh=c.lr_sh, beta1=c.beta1, beta2=c.beta2, eps=c.eps, bg=c.bg,
-                                        t_stop=c.t_stop, leaf_count=self._cnt, records=self._rec)
+                                        t_stop=c.t_stop, leaf_count=self._cnt, records=self._rec[:need])
             return loss
         if self.gs is None:
             t = self.tree
@@ -141,7 +150,7 @@ class Trainer:
             self.gs.zero_()
             self.gh.zero_()
         self.tree.backward(rays, rgb, nseg, grad, self.gs, self.gh, bg=c.bg, t_stop=c.t_stop, leaf_count=self._cnt,
-                           records=self._rec)
+                           records=self._rec[:need])
         if c.optimizer == "rmsprop":
             self.tree.rmsprop_step(self.gs, self.gh, self.state, lr_sigma=c.lr_sigma, lr_sh=c.lr_sh,
                                    alpha=c.alpha, eps=c.eps)
@@ -163,6 +172,7 @@ class Trainer:
             perm = torch.as_tensor(perm, dtype=torch.int64).to(self.device)
             if perm.shape[0] != self.n_rays:
                 raise ValueError("a permutation must cover every training ray")
+        self._size_records = True
         signal = None
         if refine_now and c.signal != "sigma":
             signal = torch.zeros(self.tree.n_leaves, dtype=torch.float32, device=self.device)

@@ -100,6 +100,55 @@ def test_autograd_function_mse(record_segments):
     tree.close()
 
 
+def test_autograd_mse_and_fused_adam_match_oracle():
+    """The config-4 step through autograd: DotRender (training forward with
+    records, kept by the tree and reused by the next forward) and MSELoss
+    (loss and gradient from one kernel), with Adam applied inside the adjoint
+    (FusedAdam): two steps on the same pixels against the oracle's render,
+    MSE, gradient and Adam in FP64 (eps 1e-4, as in the fused-Adam tests).
+    The loss of each step matches the oracle's; the planes after each step
+    match; no gradient reaches the plane views."""
+    from oracle import alg1 as A
+    core = _core()
+    s = synth.sphere_scene()
+    views = synth.training_views(n=4)
+    ci, pi = synth.pixel_batch(4, 64, 64, 6000, seed=5)
+    rays = core.Rays.pixels(views, ci, pi)
+    o, d = O.camera_rays(views, ci, pi)
+    target = np.random.default_rng(6).uniform(0.2, 0.8, size=(ci.shape[0], 3))
+    tgt = torch.as_tensor(target, dtype=torch.float32, device="cuda")
+    tree = core.Octree.from_scene(s)
+    sig_v, sh_v = tree.plane_views()
+    sigma, sh = sig_v.detach().requires_grad_(), sh_v.detach().requires_grad_()
+    opt = core.FusedAdam(tree, eps=1e-4)
+    th_s, th_h = s.sigma.astype(np.float64), s.sh.astype(np.float64)
+    m_s, v_s, m_h, v_h = np.zeros_like(th_s), np.zeros_like(th_s), np.zeros_like(th_h), np.zeros_like(th_h)
+    for step in (1, 2):
+        rgb = core.render_autograd(tree, sigma, sh, rays, t_stop=0.0, optimizer=opt)
+        loss = core.mse_loss_autograd(rgb, tgt)
+        loss.backward()
+        assert sigma.grad is None and sh.grad is None
+        T = O.OracleTree(s.child, th_s, th_h, s.degree)
+        ref = O.render(T, o, d, t_stop=0.0)["rgb"]
+        want_loss, g = A.mse_loss(ref, tgt.cpu().numpy().astype(np.float64))
+        assert float(loss) == pytest.approx(want_loss, rel=1e-5)
+        gs, gh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64), t_stop=0.0)
+        th_s, m_s, v_s = A.adam(th_s, gs, m_s, v_s, step, 0.1, 0.9, 0.999, 1e-4)
+        th_h, m_h, v_h = A.adam(th_h, gh, m_h, v_h, step, 0.01, 0.9, 0.999, 1e-4)
+        ex = tree.export()
+        np.testing.assert_allclose(ex["sigma"], th_s, rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(ex["sh"], th_h, rtol=1e-5, atol=1e-5)
+        th_s, th_h = ex["sigma"].astype(np.float64), ex["sh"].astype(np.float64)   # continue from the stored values
+    assert opt.step == 2
+    # MSELoss's gradient through a non-unit upstream gradient
+    pred = torch.rand((50, 3), device="cuda", requires_grad=True)
+    t2 = torch.rand((50, 3), device="cuda")
+    (3.0 * core.mse_loss_autograd(pred, t2)).backward()
+    np.testing.assert_allclose(pred.grad.cpu().numpy(), (6.0 * (pred - t2) / 150).detach().cpu().numpy(),
+                               rtol=1e-6, atol=1e-8)
+    tree.close()
+
+
 def test_adam_step_matches_oracle_adam():
     """dot_adam_step over three steps against the oracle's Adam in FP64 on the
     same FP32 gradients (lr 0.1 for sigma, 0.01 for SH)."""
