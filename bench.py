@@ -473,9 +473,12 @@ def serving_trees(core, synth, c2_scene):
     return [core.Octree.from_scene(x, "f16") for x in (s1a, s1b, c2_scene, s2b)]
 
 
-def serve_once(serve, trees, rate, seconds, seed=4, warm=2.0, **kw):
+def serve_once(serve, trees, rate, seconds, seed=4, warm=2.0, persistent=False, **kw):
     reqs = serve.poisson_requests(4, rate=rate, duration=warm + seconds, seed=seed)
-    srv = serve.Server(trees, out_budget_bytes=2 << 30, max_tiles=65536, **kw)
+    if persistent:
+        srv = serve.PersistentServer(trees, out_budget_bytes=2 << 30)
+    else:
+        srv = serve.Server(trees, out_budget_bytes=2 << 30, max_tiles=65536, **kw)
     st = srv.run(reqs, warmup=warm)
     offered = sum(r.rays for r in reqs if r.arrival >= warm) / seconds / 1e6
     out = {"rate_req_s": rate, "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
@@ -484,7 +487,8 @@ def serve_once(serve, trees, rate, seconds, seed=4, warm=2.0, **kw):
            "requests": st["requests"], "launches": st["launches"],
            "requests_per_launch": round(st["mean_requests_per_launch"], 2),
            "tiles_per_launch": round(st["mean_tiles_per_launch"], 1),
-           "gpu_busy_frac": round(st["gpu_busy_frac"], 3), "seconds": seconds}
+           "gpu_busy_frac": None if st["gpu_busy_frac"] is None else round(st["gpu_busy_frac"], 3),
+           "seconds": seconds, "mode": "persistent launch" if persistent else "launch per batch"}
     log(f"serving at {rate} req/s: {out}")
     return out
 
@@ -511,11 +515,14 @@ def serving_sweep(torch, core, synth, c2_scene, args):
     per load p50/p99 latency, throughput, requests and tiles per launch, and the
     fraction of the wall time the GPU spent in launches; launches on one stream
     (back to back) and round-robin over two streams (a batch can start while
-    the previous one drains)."""
+    the previous one drains); and the persistent launch that takes each
+    request's job as soon as it is admitted (dot_serve_*)."""
     from paper_2307_15333_amd import serve
     trees = serving_trees(core, synth, c2_scene)
+    rates = (200.0, 1000.0, 3000.0, 6000.0)
     out = {"sweep": [dict(serve_once(serve, trees, r, args.serve_seconds, streams=k), streams=k)
-                     for k in (1, 2) for r in (200.0, 1000.0, 3000.0, 6000.0)]}
+                     for k in (1, 2) for r in rates]}
+    out["persistent"] = [serve_once(serve, trees, r, args.serve_seconds, persistent=True) for r in rates]
     for t in trees:
         t.close()
     return out

@@ -48,7 +48,8 @@ enum {
     DOT_EINVAL = -1,       /* malformed argument or tree */
     DOT_ENOMEM = -2,       /* allocation failed */
     DOT_EHIP = -3,         /* HIP runtime error (message from hipGetErrorString) */
-    DOT_EUNSUPPORTED = -4  /* valid request the library does not support (e.g. training reduced-precision leaves) */
+    DOT_EUNSUPPORTED = -4, /* valid request the library does not support (e.g. training reduced-precision leaves) */
+    DOT_EBUSY = -5         /* a serving queue is full: retry once one of its jobs has completed */
 };
 
 /* leaf storage precision of the sigma and SH planes; arithmetic is FP32.
@@ -269,6 +270,23 @@ int dot_render_backward(dot_tree_t tree, const dot_rays *rays, const dot_render_
                         const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,
                         float *grad_sigma, float *grad_sh, const uint32_t *leaf_count, const void *records,
                         size_t records_bytes, void *stream);
+
+/*
+ * dot_render_backward_atomic -- the same adjoint (Sec. 3: the renderer is
+ *  fully differentiable) by re-traversal alone: each ray walks its nseg[r]
+ *  segments again, keeping only the prefix colour sum against the forward's
+ *  colour (no per-segment state), and at every step the lanes of a wavefront
+ *  that composite the same leaf sum their 1 + 3K terms across lanes (a
+ *  segmented reduction over runs of equal leaf id in lane order) before one
+ *  FP32 atomic per run and term into grad_sigma / grad_sh (accumulated, +=;
+ *  the caller zeroes them).  Needs no scratch and never synchronises the
+ *  stream, so it can be captured in a graph; arguments, layout and errors as
+ *  dot_render_backward without leaf_count and records.  Summation order, hence
+ *  the last bits, depends on scheduling.
+ */
+int dot_render_backward_atomic(dot_tree_t tree, const dot_rays *rays, const dot_render_opts *opts,
+                               const float *rgb_fwd, const int32_t *nseg, const float *grad_rgb,
+                               float *grad_sigma, float *grad_sh, void *stream);
 
 typedef struct {
     float prune_tau;     /* prune selection: signal <= tau (prune_le) or < tau */
@@ -516,6 +534,76 @@ size_t dot_render_jobs_workspace(int32_t n_jobs);
  */
 int dot_render_jobs(const dot_render_job *jobs, int32_t n_jobs, void *workspace, size_t workspace_bytes,
                     void *stream);
+
+/*
+ * Persistent serving queue: ONE launch that stays on the device and renders
+ * the jobs the host appends while it runs, so a request that arrives while
+ * others are on the GPU is admitted without waiting for a launch to end, and
+ * the tiles of all admitted requests are rendered by the same resident waves.
+ * The host writes each job into a ring in pinned, host-coherent memory and
+ * publishes it with a counter; one wave of the launch copies published jobs
+ * into device memory and hands their tiles to the other waves through a tile
+ * ring; the wave that renders a job's last tile writes the job's completion
+ * word back to host memory.  Every pixel is computed by the same per-ray code
+ * as dot_render (Eq. 1-2), so a job's image does not depend on what else is
+ * queued.  One queue serves trees of one storage type (the launch carries that
+ * type's registers), at most `max_jobs` jobs in flight and 2^19 tiles of
+ * unfinished jobs; images of at most 2^20 tiles.  The launch holds all but one
+ * workgroup slot per compute unit until it is closed: other device work can
+ * run beside it in the slot left free, but work that needs the whole GPU, or
+ * a host wait on such work, must not be issued while a queue is open.
+ */
+typedef struct dot_serve_queue *dot_serve_t;
+
+typedef struct {
+    dot_tree_t tree;         /* resident tree of the queue's storage type */
+    dot_camera cam;          /* by value */
+    float *rgb_out;          /* DEVICE float [height][width][3]; written when the job completes */
+    int32_t width, height;
+    int64_t tile_begin, tile_count;   /* 8x8 tiles [begin, begin + count) of the image, count >= 1 */
+    float bg[3];
+    float t_stop;
+} dot_serve_job;
+
+/*
+ * dot_serve_open -- allocate a queue (pinned host ring, device state) and
+ *  launch its kernel on `stream`, which it occupies until dot_serve_close.
+ *  storage: DOT_F32 / DOT_F16 / DOT_BF16 / DOT_PAL16; max_jobs in 1..4096.
+ *  max_seconds > 0: the launch ends by itself after that long (jobs still
+ *  queued are then never completed and dot_serve_done reports DOT_EHIP), so it
+ *  can never outlive a host that stopped serving.
+ *  Errors: DOT_EINVAL on bad arguments; DOT_ENOMEM / DOT_EHIP from the runtime.
+ */
+int dot_serve_open(int32_t storage, int32_t max_jobs, double max_seconds, void *stream, dot_serve_t *out);
+
+/*
+ * dot_serve_push -- append one job (host call, returns at once); *ticket
+ *  receives its number for dot_serve_done.  The camera is copied; the tree and
+ *  rgb_out must stay valid until the job completes.  Not thread-safe per queue.
+ *  Errors: DOT_EINVAL for a NULL tree/output, a tree of another storage type,
+ *  a bad size, tile range or t_stop; DOT_EBUSY when max_jobs jobs or 2^19
+ *  tiles are unfinished (nothing is queued; retry later); DOT_EHIP after the
+ *  launch ended (closed, or past max_seconds).
+ */
+int dot_serve_push(dot_serve_t q, const dot_serve_job *job, int64_t *ticket);
+
+/*
+ * dot_serve_done -- 1 when job `ticket` has been rendered (its rgb_out is
+ *  complete and visible to later device work), 0 while it is pending.
+ *  Errors: DOT_EINVAL for an unknown ticket; DOT_EHIP when the launch ended
+ *  before the job completed.
+ */
+int dot_serve_done(dot_serve_t q, int64_t ticket);
+
+/*
+ * dot_serve_close -- tell the launch that no job will follow, wait until it
+ *  has rendered every published job and ended, then free the queue.  The
+ *  launch ends by its own clock within 9/8 of max_seconds in any case; the
+ *  call waits at most 5/4 of max_seconds plus 10 s.
+ *  Errors: DOT_EHIP if the launch has not ended by then (the queue is then
+ *  left allocated).
+ */
+int dot_serve_close(dot_serve_t q);
 
 /*
  * dot_stream_read -- support kernel, not part of the method: reads `bytes`

@@ -11,7 +11,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdot.so")
 
-DOT_OK, DOT_EINVAL, DOT_ENOMEM, DOT_EHIP, DOT_EUNSUPPORTED = 0, -1, -2, -3, -4
+DOT_OK, DOT_EINVAL, DOT_ENOMEM, DOT_EHIP, DOT_EUNSUPPORTED, DOT_EBUSY = 0, -1, -2, -3, -4, -5
 DOT_F32, DOT_F16, DOT_BF16, DOT_PAL16 = 0, 1, 2, 3
 DOT_RAYS_CAMERAS, DOT_RAYS_PIXELS, DOT_RAYS_EXPLICIT = 0, 1, 2
 DOT_SIGNAL_MAX, DOT_SIGNAL_SUM = 0, 1
@@ -85,6 +85,12 @@ class dot_render_job(C.Structure):
                 ("bg", C.c_float * 3), ("t_stop", C.c_float)]
 
 
+class dot_serve_job(C.Structure):
+    _fields_ = [("tree", C.c_void_p), ("cam", dot_camera), ("rgb_out", C.c_void_p), ("width", C.c_int32),
+                ("height", C.c_int32), ("tile_begin", C.c_int64), ("tile_count", C.c_int64),
+                ("bg", C.c_float * 3), ("t_stop", C.c_float)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/dot.h
 SIGNATURES = {
     "dot_build": (C.c_int, [C.POINTER(dot_tree_desc), C.c_int32, C.POINTER(dot_allocator), C.c_void_p,
@@ -107,6 +113,9 @@ SIGNATURES = {
                                 C.c_void_p, C.POINTER(dot_adam_params), C.c_void_p]),
     "dot_rmsprop_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(dot_rmsprop_params), C.c_void_p]),
+    "dot_render_backward_atomic": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p]),
     "dot_render_backward_rmsprop": (C.c_int, [C.c_void_p, C.POINTER(dot_rays), C.POINTER(dot_render_opts),
                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.POINTER(dot_rmsprop_params), C.c_void_p, C.c_void_p, C.c_size_t,
@@ -130,6 +139,10 @@ SIGNATURES = {
                                    C.POINTER(C.c_int64), C.c_void_p]),
     "dot_render_jobs_workspace": (C.c_size_t, [C.c_int32]),
     "dot_render_jobs": (C.c_int, [C.POINTER(dot_render_job), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dot_serve_open": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "dot_serve_push": (C.c_int, [C.c_void_p, C.POINTER(dot_serve_job), C.POINTER(C.c_int64)]),
+    "dot_serve_done": (C.c_int, [C.c_void_p, C.c_int64]),
+    "dot_serve_close": (C.c_int, [C.c_void_p]),
     "dot_stream_read": (C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "dot_last_error": (C.c_char_p, []),
 }

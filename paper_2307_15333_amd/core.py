@@ -265,6 +265,14 @@ class Octree:
                                              _ptr(leaf_count), _ptr(records),
                                              C.c_size_t(records.numel() if records is not None else 0), _stream()))
 
+    def backward_atomic(self, rays, rgb, nseg, grad_rgb, grad_sigma, grad_sh, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
+        """The re-traversal adjoint with per-leaf sums across each wavefront before FP32 atomics (no scratch,
+        no synchronisation); accumulates into grad_sigma [L] and grad_sh [L, 3, K]."""
+        op = _opts(bg, t_stop)
+        L.check(self.lib.dot_render_backward_atomic(self.handle, C.byref(rays.struct), C.byref(op), _ptr(rgb),
+                                                    _ptr(nseg), _ptr(grad_rgb), _ptr(grad_sigma), _ptr(grad_sh),
+                                                    _stream()))
+
     def render_stats(self, rays, bg=(1.0, 1.0, 1.0), t_stop=1e-4):
         op = _opts(bg, t_stop)
         out = (C.c_int64 * 4)()

@@ -481,6 +481,32 @@ int dot_render_backward(dot_tree_t t, const dot_rays* rays, const dot_render_opt
     return DOT_OK;
 }
 
+int dot_render_backward_atomic(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts, const float* rgb_fwd,
+                               const int32_t* nseg, const float* grad_rgb, float* grad_sigma, float* grad_sh,
+                               void* stream) {
+    if (!t) return fail(DOT_EINVAL, "dot_render_backward_atomic: tree is NULL");
+    if (t->storage == DOT_PAL16)
+        return fail(DOT_EUNSUPPORTED, "dot_render_backward_atomic: a palette-compressed tree is not differentiable");
+    RayBatch rb;
+    int rc = make_batch(rays, rb, "dot_render_backward_atomic");
+    if (rc) return rc;
+    if (rb.n_rays > 0 && (!rgb_fwd || !nseg || !grad_rgb || !grad_sigma || !grad_sh))
+        return fail(DOT_EINVAL,
+                    "dot_render_backward_atomic: rgb_fwd, nseg, grad_rgb, grad_sigma and grad_sh are required");
+    BwdArgs a{};
+    float bg[3];
+    rc = fill_opts(opts, bg, a.thr, "dot_render_backward_atomic");
+    if (rc) return rc;
+    a.rgb_fwd = rgb_fwd;
+    a.nseg = nseg;
+    a.grad_rgb = grad_rgb;
+    a.grad_sigma = grad_sigma;
+    a.grad_sh = grad_sh;
+    hipError_t e = launch_render_bwd_wave(*t, rb, a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_render_backward_atomic: launch");
+    return DOT_OK;
+}
+
 int dot_render_backward_rmsprop(dot_tree_t t, const dot_rays* rays, const dot_render_opts* opts,
                                 const float* rgb_fwd, const int32_t* nseg, const float* grad_rgb, float* v_sigma,
                                 float* v_sh, const dot_rmsprop_params* params, const uint32_t* leaf_count,

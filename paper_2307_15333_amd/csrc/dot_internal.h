@@ -212,6 +212,8 @@ __device__ __forceinline__ void adam_update(float& theta, float& m, float& v, fl
 
 hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArgs& a, hipStream_t s);
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
+// re-traversal adjoint with wave-level per-leaf sums before the float atomics
+hipError_t launch_render_bwd_wave(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s, uint32_t* word = nullptr);
 hipError_t launch_encode_planes(int storage, const float* src, void* dst, int64_t rows, int src_cols,
                                 int dst_stride, hipStream_t s);

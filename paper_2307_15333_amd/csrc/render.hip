@@ -130,6 +130,141 @@ __global__ __launch_bounds__(BLOCK) void render_bwd_kernel(TreeView tv, RayBatch
 }
 
 // ---------------------------------------------------------------------------
+// Re-traversal adjoint with the lanes' terms summed per leaf inside the
+// wavefront before the float atomics.  At a traversal step the lanes that
+// composite a segment form runs of equal leaf id in lane order (neighbouring
+// pixels of a tile often cross the same leaf); a segmented reduction over
+// those runs (a Hillis-Steele scan toward each run's first lane, lane
+// shuffles over distances 1, 2, 4, ..., stopped at the first distance with no
+// partner) leaves each run's sum in its first lane, which alone issues the
+// 1 + 3K atomics (the SH terms one channel of K at a time).  Inactive lanes (finished rays, zero-length steps) and
+// segments with sigma <= 0 never join a run.  No scratch and no host
+// synchronisation.
+// ---------------------------------------------------------------------------
+// Sums v over the runs of equal key among the lanes calling it and leaves each
+// run's sum in its first lane; returns true in those lanes (key >= 0).
+template <int NV>
+__device__ __forceinline__ bool leaf_runs_sum(int key, float (&v)[NV]) {
+    const int lane = (int)__lane_id();
+    const uint64_t act = __ballot(1);
+    const int prev = __shfl_up(key, 1);
+    const bool prev_in = lane > 0 && ((act >> (lane - 1)) & 1ull) && prev == key;
+    const uint64_t heads = __ballot(!prev_in);
+    if (heads != act) {
+        // run number of each lane: the heads at or below it
+        const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const int run = __popcll(heads & le);
+        for (int s = 1; s < WAVE; s <<= 1) {
+            const int r2 = __shfl_down(run, s);
+            const bool ok = lane + s < WAVE && ((act >> (lane + s)) & 1ull) && r2 == run;
+            if (!__any(ok)) break;      // runs are contiguous: no partner at s, none farther
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const float w = __shfl_down(v[j], s);
+                if (ok) v[j] += w;
+            }
+        }
+    }
+    return !prev_in && key >= 0;
+}
+
+template <int DT, int DEG>
+struct BwdSegWave {
+    static constexpr int K = (DEG + 1) * (DEG + 1);
+    const TreeView& tv;
+    const BwdArgs& a;
+    float Y[K];
+    float S = 0.f, T = 1.f;
+    float C[3], g[3];
+    float P[3] = {0.f, 0.f, 0.f};
+    int n = 0, limit = 0;
+
+    __device__ BwdSegWave(const TreeView& tv_, const BwdArgs& a_) : tv(tv_), a(a_) {}
+
+    __device__ __forceinline__ bool operator()(int leaf, float delta) {
+        ++n;
+        const float sraw = load_sigma<DT>(tv.sigma, leaf);
+        // per lane: the density term and the SH factors f_ch (the SH terms are
+        // f_ch Y_k, formed one channel at a time to keep few values live)
+        float d[2] = {0.f, 0.f};        // dL/dsigma, and 1 if any SH term is non-zero
+        float f[3] = {0.f, 0.f, 0.f};
+        if (sraw > 0.f) {
+            const float tau = sraw * delta;
+            const float Sn = S + tau;
+            const float Tn = __expf(-Sn);
+            const float w = fmaxf(T - Tn, 0.f);
+            float row[3 * K];
+            load_sh_row<DT, 3 * K>(tv.sh, leaf, row);
+            float c[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float x = 0.f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) x = fmaf(row[ch * K + k], Y[k], x);
+                c[ch] = sigmoidf_(x);
+            }
+            float gs = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                P[ch] = fmaf(w, c[ch], P[ch]);
+                gs = fmaf(g[ch], Tn * c[ch] - (C[ch] - P[ch]), gs);
+            }
+            d[0] = gs * delta;
+            if (w > 0.f) {
+                d[1] = 1.f;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) f[ch] = g[ch] * w * c[ch] * (1.f - c[ch]);
+            }
+            S = Sn;
+            T = Tn;
+        }
+        const int key = sraw > 0.f ? leaf : -1;
+        const bool head = leaf_runs_sum<2>(key, d);
+        if (head) unsafeAtomicAdd(&a.grad_sigma[leaf], d[0]);
+        if (__any(head && d[1] > 0.f)) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float v[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[k] = f[ch] * Y[k];
+                leaf_runs_sum<K>(key, v);
+                if (head && d[1] > 0.f) {
+                    float* gh = a.grad_sh + (int64_t)leaf * (3 * K) + ch * K;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) unsafeAtomicAdd(&gh[k], v[k]);
+                }
+            }
+        }
+        return n < limit;
+    }
+};
+
+template <int DT, int DEG>
+__global__ __launch_bounds__(BLOCK) void render_bwd_wave_kernel(TreeView tv, RayBatch rb, BwdArgs a) {
+    __shared__ int stack_lds[LAT * BLOCK];
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int64_t nb = gridDim.x;
+    const int64_t tile = xcd_block(blockIdx.x, nb) * WAVES_PER_BLOCK + (tid >> 6);
+    if (tile >= rb.n_tiles) return;
+    Ray r;
+    int64_t rid;
+    if (!make_ray(rb, tile, lane, r, rid)) return;
+    BwdSegWave<DT, DEG> seg(tv, a);
+    seg.limit = a.nseg[rid];
+    if (seg.limit <= 0) return;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        seg.C[ch] = a.rgb_fwd[3 * rid + ch];
+        seg.g[ch] = a.grad_rgb[3 * rid + ch];
+    }
+    if (seg.g[0] == 0.f && seg.g[1] == 0.f && seg.g[2] == 0.f) return;
+    sh_basis<DEG>((float)r.dx, (float)r.dy, (float)r.dz, seg.Y);
+    int desc = 0;
+    traverse(tv, r, &stack_lds[tid], seg, desc);
+}
+
+// ---------------------------------------------------------------------------
 // Leaf-bucketed adjoint.  Many rays cross the same leaves, so pushing every
 // segment's 1 + 3K gradient terms with float atomics serialises on the hot
 // leaves.  Instead: (1) count the contributing segments of every leaf, (2)
@@ -877,6 +1012,29 @@ static hipError_t bwd_dispatch_deg(int deg, const TreeView& tv, const RayBatch& 
         default: hipLaunchKernelGGL((render_bwd_kernel<DT, 3>), grid, dim3(BLOCK), 0, s, tv, rb, a); break;
     }
     return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t bwd_wave_dispatch_deg(int deg, const TreeView& tv, const RayBatch& rb, const BwdArgs& a,
+                                        dim3 grid, hipStream_t s) {
+    switch (deg) {
+        case 0: hipLaunchKernelGGL((render_bwd_wave_kernel<DT, 0>), grid, dim3(BLOCK), 0, s, tv, rb, a); break;
+        case 1: hipLaunchKernelGGL((render_bwd_wave_kernel<DT, 1>), grid, dim3(BLOCK), 0, s, tv, rb, a); break;
+        case 2: hipLaunchKernelGGL((render_bwd_wave_kernel<DT, 2>), grid, dim3(BLOCK), 0, s, tv, rb, a); break;
+        default: hipLaunchKernelGGL((render_bwd_wave_kernel<DT, 3>), grid, dim3(BLOCK), 0, s, tv, rb, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_render_bwd_wave(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s) {
+    if (rb.n_tiles == 0) return hipSuccess;
+    const dim3 grid((unsigned)((rb.n_tiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
+    TreeView tv = t.view();
+    switch (t.storage) {
+        case DOT_F32: return bwd_wave_dispatch_deg<DOT_F32>(t.degree, tv, rb, a, grid, s);
+        case DOT_F16: return bwd_wave_dispatch_deg<DOT_F16>(t.degree, tv, rb, a, grid, s);
+        default: return bwd_wave_dispatch_deg<DOT_BF16>(t.degree, tv, rb, a, grid, s);
+    }
 }
 
 static hipError_t bwd_atomic(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, dim3 grid, hipStream_t s) {

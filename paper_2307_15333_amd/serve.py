@@ -57,6 +57,8 @@ class Request:
     cam_dev: torch.Tensor | None = None
     admitted: float = -1.0
     done: float = -1.0
+    ticket: int = -1
+    arena_off: int = -1
 
     @property
     def rays(self):
@@ -235,6 +237,190 @@ class Server:
             "mean_requests_per_launch": reqs_launched / max(launches, 1),
             "gpu_busy_frac": busy_ms / 1e3 / wall if wall > 0 else None,
             "max_budget_used": self.max_used, "budget": self.budget,
+        }
+
+
+class Queue:
+    """The persistent serving launch (dot_serve_*): one launch on its own stream
+    renders the jobs pushed while it runs."""
+
+    def __init__(self, storage="f16", max_jobs=1024, max_seconds=3600.0, device="cuda"):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)      # occupied by the launch until close()
+        h = C.c_void_p()
+        st = {**L.STORAGE, "pal16": L.DOT_PAL16}[storage]
+        L.check(self.lib.dot_serve_open(st, int(max_jobs), float(max_seconds),
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def push(self, tree, cam, rgb_out, width, height, tile_begin=0, tile_count=None, bg=(1.0, 1.0, 1.0),
+             t_stop=1e-4):
+        """Queue the tiles [tile_begin, tile_begin + tile_count) of one image; returns the
+        job's ticket, or None when the queue is full."""
+        n_tiles = ((width + 7) // 8) * ((height + 7) // 8)
+        j = L.dot_serve_job()
+        j.tree = tree.handle
+        j.cam = L.dot_camera.from_buffer_copy(np.ascontiguousarray(np.asarray(cam).reshape(1)).tobytes())
+        j.rgb_out = rgb_out.data_ptr()
+        j.width, j.height = int(width), int(height)
+        j.tile_begin = int(tile_begin)
+        j.tile_count = int(n_tiles - tile_begin if tile_count is None else tile_count)
+        for a in range(3):
+            j.bg[a] = float(bg[a])
+        j.t_stop = float(t_stop)
+        t = C.c_int64()
+        rc = self.lib.dot_serve_push(self.h, C.byref(j), C.byref(t))
+        if rc == L.DOT_EBUSY:
+            return None
+        L.check(rc)
+        return t.value
+
+    def done(self, ticket):
+        rc = self.lib.dot_serve_done(self.h, C.c_int64(ticket))
+        if rc < 0:
+            L.check(rc)
+        return rc == 1
+
+    def wait(self, ticket, timeout=5.0):
+        t0 = time.perf_counter()
+        while not self.done(ticket):
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"serving job {ticket} not done after {timeout} s")
+
+    def close(self):
+        if self.h:
+            L.check(self.lib.dot_serve_close(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PersistentServer:
+    """Continuous batching through the persistent launch: each admitted request
+    is pushed at once as one job (its whole image) into the running launch, so
+    its tiles are taken by waves that are free now, beside the tiles of the
+    requests already on the device; admission (slots, HBM budget for outputs)
+    and latency as in Server."""
+
+    def __init__(self, trees, out_budget_bytes=2 << 30, max_active=64, device="cuda", storage="f16",
+                 max_seconds=3600.0):
+        self.trees = trees
+        self.device = torch.device(device)
+        self.budget = int(out_budget_bytes)
+        self.max_active = int(max_active)
+        self.storage = storage
+        self.max_seconds = float(max_seconds)
+        self.used = 0
+
+    def run(self, requests, warmup=0.0, keep_outputs=False, on_complete=None):
+        """Serve `requests` in real time.  Outputs come from an arena of the
+        HBM budget, allocated before the launch and reused once a request has
+        completed (no allocator call while the launch holds the GPU); with
+        keep_outputs each request gets its own buffer instead, allocated before
+        the launch starts and valid after run() returns.  on_complete(r) is called on the host when r completes; it must
+        not issue device work, which would wait for the launch."""
+        arena = None if keep_outputs else torch.empty(self.budget, dtype=torch.uint8, device=self.device)
+        if keep_outputs:
+            # every request's own output, allocated before the launch holds the GPU
+            for r in requests:
+                r.out = torch.empty((r.height, r.width, 3), dtype=torch.float32, device=self.device)
+        free = [(0, self.budget)]          # free byte ranges of the arena, sorted
+
+        def alloc(nbytes):
+            nbytes = (nbytes + 255) & ~255
+            for i, (a, n) in enumerate(free):
+                if n >= nbytes:
+                    free[i:i + 1] = [(a + nbytes, n - nbytes)] if n > nbytes else []
+                    return a
+            return None
+
+        def release(a, nbytes):
+            nbytes = (nbytes + 255) & ~255
+            free.append((a, nbytes))
+            free.sort()
+            merged = []
+            for x, n in free:
+                if merged and merged[-1][0] + merged[-1][1] == x:
+                    merged[-1] = (merged[-1][0], merged[-1][1] + n)
+                else:
+                    merged.append((x, n))
+            free[:] = merged
+
+        q = Queue(self.storage, max_jobs=max(2 * self.max_active, 16), max_seconds=self.max_seconds,
+                  device=self.device)
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting, active, completed, rejected = deque(), [], [], []
+        t0 = time.perf_counter()
+        try:
+            while pending or waiting or active:
+                now = time.perf_counter() - t0
+                while pending and pending[0].arrival <= now:
+                    waiting.append(pending.popleft())
+                while waiting and len(active) < self.max_active:
+                    r = waiting[0]
+                    if r.out_bytes > self.budget:
+                        rejected.append(waiting.popleft())
+                        continue
+                    if self.used + r.out_bytes > self.budget:
+                        break
+                    r.n_tiles = ((r.width + 7) // 8) * ((r.height + 7) // 8)
+                    if not keep_outputs:
+                        off = alloc(r.out_bytes)
+                        if off is None:     # fragmented arena: wait for a completion
+                            break
+                        r.arena_off = off
+                        r.out = arena[off:off + r.out_bytes].view(torch.float32).view(r.height, r.width, 3)
+                    tk = q.push(self.trees[r.tree], r.cam, r.out, r.width, r.height, bg=r.bg, t_stop=r.t_stop)
+                    if tk is None:          # queue full: retry after a completion
+                        if not keep_outputs:
+                            release(r.arena_off, r.out_bytes)
+                        r.out = None
+                        break
+                    r.ticket = tk
+                    r.admitted = now
+                    self.used += r.out_bytes
+                    active.append(waiting.popleft())
+                still = []
+                for r in active:
+                    if q.done(r.ticket):
+                        r.done = time.perf_counter() - t0
+                        self.used -= r.out_bytes
+                        if on_complete is not None:
+                            on_complete(r)
+                        if not keep_outputs:
+                            release(r.arena_off, r.out_bytes)
+                            r.out = None
+                        completed.append(r)
+                    else:
+                        still.append(r)
+                active = still
+                if not active and not waiting and pending:
+                    dt = pending[0].arrival - (time.perf_counter() - t0)
+                    if dt > 3e-4:
+                        time.sleep(min(dt - 3e-4, 0.002))
+        finally:
+            q.close()
+        wall = time.perf_counter() - t0
+        meas = [r for r in completed if r.arrival >= warmup]
+        lat = np.array([r.done - r.arrival for r in meas]) * 1e3
+        rays = sum(r.rays for r in meas)
+        span = (max(r.done for r in meas) - min(r.arrival for r in meas)) if meas else 0.0
+        return {
+            "requests": len(meas), "rejected": len(rejected), "launches": 1,
+            "p50_ms": float(np.percentile(lat, 50)) if meas else None,
+            "p99_ms": float(np.percentile(lat, 99)) if meas else None,
+            "mean_ms": float(lat.mean()) if meas else None,
+            "max_ms": float(lat.max()) if meas else None,
+            "mrays_per_s": rays / span / 1e6 if span > 0 else None,
+            "req_per_s": len(meas) / span if span > 0 else None,
+            "wall_s": wall, "mean_tiles_per_launch": float(sum(r.n_tiles for r in completed)),
+            "mean_requests_per_launch": float(len(completed)), "gpu_busy_frac": None,
+            "budget": self.budget,
         }
 
 

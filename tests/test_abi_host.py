@@ -188,3 +188,20 @@ def test_noalloc_pixel_batch_argument_checks_need_no_device():
     assert lib.dot_pixel_batch_workspace(n, 800, 800, 100) > (16 << 20)
     assert lib.dot_pixel_batch_noalloc(fake, n, 800, 800, 100, fake, fake, None, None) == L.DOT_EINVAL
     assert b"scratch" in lib.dot_last_error()
+
+
+def test_serving_queue_argument_checks_need_no_device():
+    """The persistent serving queue refuses malformed arguments before it
+    allocates or launches anything."""
+    lib = L.load()
+    h = C.c_void_p()
+    assert lib.dot_serve_open(7, 16, 1.0, None, C.byref(h)) == L.DOT_EINVAL
+    assert lib.dot_serve_open(L.DOT_F16, 0, 1.0, None, C.byref(h)) == L.DOT_EINVAL
+    assert lib.dot_serve_open(L.DOT_F16, 5000, 1.0, None, C.byref(h)) == L.DOT_EINVAL
+    assert lib.dot_serve_open(L.DOT_F16, 16, 0.0, None, C.byref(h)) == L.DOT_EINVAL
+    assert lib.dot_serve_open(L.DOT_F16, 16, float("inf"), None, C.byref(h)) == L.DOT_EINVAL
+    assert lib.dot_serve_open(L.DOT_F16, 16, 1.0, None, None) == L.DOT_EINVAL
+    t = C.c_int64()
+    assert lib.dot_serve_push(None, None, C.byref(t)) == L.DOT_EINVAL
+    assert lib.dot_serve_done(None, 0) == L.DOT_EINVAL
+    assert lib.dot_serve_close(None) == L.DOT_OK

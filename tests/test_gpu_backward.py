@@ -100,6 +100,46 @@ def test_autograd_function_mse(record_segments):
     tree.close()
 
 
+@pytest.mark.parametrize("case", ["sphere_views", "random_explicit", "uniform_deg3"])
+def test_backward_atomic_matches_oracle(case):
+    """The re-traversal adjoint with per-leaf sums across each wavefront before
+    the FP32 atomics (dot_render_backward_atomic) against the oracle's
+    gradient: coherent pixel batches (many lanes on one leaf), incoherent
+    explicit rays (runs of one), and a depth-uniform degree-3 tree with sigma
+    > 0 everywhere (every segment contributes)."""
+    core = _core()
+    if case == "sphere_views":
+        s = synth.sphere_scene()
+        views = synth.training_views(n=9)
+        ci, pi = synth.pixel_batch(9, 64, 64, 8192, seed=1)
+        rays = core.Rays.pixels(views, ci, pi)
+        o, d = O.camera_rays(views, ci, pi)
+    elif case == "random_explicit":
+        s = synth.random_tree_scene(5, 2, seed=12, p_split=0.5)
+        o, d = synth.random_explicit_rays(3000, seed=13)
+        rays = core.Rays.explicit(o, d)
+        o, d = o.astype(np.float32).astype(np.float64), d.astype(np.float32).astype(np.float64)
+    else:
+        s = synth.uniform_scene(4, 3, 0.4, seed=14)
+        cams = synth.cameras([(35.0, 25.0, 3.0, 40, 32)])
+        rays = core.Rays.cameras(cams)
+        o, d = O.camera_rays(cams)
+    g = np.random.default_rng(15).normal(size=(o.shape[0], 3))
+    tree = core.Octree.from_scene(s)
+    rgb, ns = tree.render(rays, t_stop=0.0, nseg=True)
+    Ln, K = tree.n_leaves, tree.K
+    gs = torch.zeros(Ln, device="cuda")
+    gh = torch.zeros((Ln, 3, K), device="cuda")
+    tree.backward_atomic(rays, rgb, ns, torch.as_tensor(g, dtype=torch.float32, device="cuda"), gs, gh, t_stop=0.0)
+    torch.cuda.synchronize()
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    rs, rh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64), t_stop=0.0)
+    es, eh = _rel(gs.cpu().numpy(), rs), _rel(gh.cpu().numpy(), rh)
+    print(f"{case}: grad_sigma rel {es:.3e}, grad_sh rel {eh:.3e}")
+    assert es <= GTOL and eh <= GTOL
+    tree.close()
+
+
 def test_autograd_mse_and_fused_adam_match_oracle():
     """The config-4 step through autograd: DotRender (training forward with
     records, kept by the tree and reused by the next forward) and MSELoss

@@ -152,3 +152,139 @@ def test_batch_mixing_storage_types():
         np.testing.assert_allclose(r.out.cpu().numpy(), ref.cpu().numpy(), atol=1e-6, rtol=0)
     for t in ts:
         t.close()
+
+
+def test_launches_carry_several_requests_under_load(trees):
+    """Under an offered load beyond what the host issues launches for (small
+    images at 60,000 req/s, one launch in flight at a time), each launch
+    carries several requests that arrived while the previous one ran, and
+    every checked request still equals its image rendered alone."""
+    core, serve = _mods()
+    scenes, ts = trees
+    reqs = serve.poisson_requests(len(ts), rate=60000.0, duration=0.15, seed=14,
+                                  resolutions=[(128, 128), (256, 256), (333, 251)])
+    check = {}
+
+    def keep(r):
+        if r.rid % 11 == 0:
+            check[r.rid] = r.out.clone()
+
+    srv = serve.Server(ts, out_budget_bytes=256 << 20, max_tiles=8192, max_inflight=1)
+    st = srv.run(reqs, on_complete=keep)
+    print({k: st[k] for k in ("requests", "launches", "mean_requests_per_launch", "p50_ms", "p99_ms")})
+    assert st["requests"] == len(reqs)
+    assert st["mean_requests_per_launch"] >= 4.0
+    for r in reqs:
+        if r.rid in check:
+            ref = ts[r.tree].render(core.Rays.cameras(np.asarray(r.cam).reshape(1))).reshape(r.height, r.width, 3)
+            np.testing.assert_allclose(check[r.rid].cpu().numpy(), ref.cpu().numpy(), atol=1e-6, rtol=0)
+
+
+def _reference_images(core, ts, reqs):
+    return {r.rid: ts[r.tree].render(core.Rays.cameras(np.asarray(r.cam).reshape(1))).reshape(r.height, r.width, 3)
+            .cpu().numpy() for r in reqs}
+
+
+def test_persistent_queue_alone_equals_mix(trees):
+    """The persistent launch: a request rendered alone, then again while five
+    other requests (on the other trees) are queued with it and its own image
+    is pushed as two jobs in reverse tile order -- bitwise the same image,
+    equal to the batched launch's and within 1e-6 of dot_render's; the other
+    requests match dot_render too.  References are rendered before the queue
+    opens and results read after it closes (the open launch holds the GPU)."""
+    core, serve = _mods()
+    scenes, ts = trees
+    a = _req(serve, 0, 1, 128, 96, 30.0, 20.0)
+    others = [_req(serve, 1 + i, (i % 3) + (i % 3 >= 1), w, h, 50.0 * i, 10.0 - 5.0 * i)
+              for i, (w, h) in enumerate(((256, 256), (200, 120), (64, 64), (333, 251), (96, 160)))]
+    ref = _reference_images(core, ts, [a] + others)
+    srv = serve.Server(ts)
+    srv._admit(a, 0.0)
+    srv.launch([(a, 0, a.n_tiles)])
+    batched = a.out.cpu().numpy()
+    alone = torch.zeros((a.height, a.width, 3), device="cuda")
+    mixed = torch.zeros((a.height, a.width, 3), device="cuda")
+    outs = [torch.zeros((r.height, r.width, 3), device="cuda") for r in others]
+    torch.cuda.synchronize()
+    q = serve.Queue("f16", max_jobs=32, max_seconds=8.0)
+    try:
+        q.wait(q.push(ts[a.tree], a.cam, alone, a.width, a.height))
+        n = a.n_tiles
+        tickets = [q.push(ts[others[0].tree], others[0].cam, outs[0], others[0].width, others[0].height),
+                   q.push(ts[a.tree], a.cam, mixed, a.width, a.height, tile_begin=n // 2, tile_count=n - n // 2)]
+        for r, o in zip(others[1:], outs[1:]):
+            tickets.append(q.push(ts[r.tree], r.cam, o, r.width, r.height))
+        tickets.append(q.push(ts[a.tree], a.cam, mixed, a.width, a.height, tile_begin=0, tile_count=n // 2))
+        assert all(t is not None for t in tickets)
+        for t in tickets:
+            q.wait(t)
+    finally:
+        q.close()
+    al, mx = alone.cpu().numpy(), mixed.cpu().numpy()
+    assert np.array_equal(al, mx)
+    assert np.array_equal(al, batched)
+    np.testing.assert_allclose(al, ref[a.rid], atol=1e-6, rtol=0)
+    for r, o in zip(others, outs):
+        np.testing.assert_allclose(o.cpu().numpy(), ref[r.rid], atol=1e-6, rtol=0)
+
+
+def test_persistent_queue_limits_and_time_limit(trees):
+    """A queue refuses a tree of another storage type and a tile range outside
+    the image; it reports a full queue (2^19 tiles of unfinished jobs) without
+    queuing, and takes the job once the earlier one completed; a launch past
+    its time limit ends by itself and the queue then refuses new jobs."""
+    import time
+    from paper_2307_15333_amd import _lib as L
+    core, serve = _mods()
+    scenes, ts = trees
+    t32 = core.Octree.from_scene(scenes[0], "f32")
+    cam = synth.look_at_camera(20.0, 10.0, 4.0, 8192, 4096)
+    big = torch.empty((4096, 8192, 3), device="cuda")
+    small = torch.empty((8, 8, 3), device="cuda")
+    cam8 = synth.look_at_camera(20.0, 10.0, 4.0, 8, 8)
+    torch.cuda.synchronize()
+    q = serve.Queue("f16", max_jobs=4, max_seconds=8.0)
+    try:
+        with pytest.raises(L.DotError) as e:
+            q.push(t32, cam8, small, 8, 8)
+        assert e.value.code == L.DOT_EINVAL
+        with pytest.raises(L.DotError) as e:
+            q.push(ts[0], cam8, small, 8, 8, tile_begin=1, tile_count=1)
+        assert e.value.code == L.DOT_EINVAL
+        tb = q.push(ts[0], cam, big, 8192, 4096)          # 2^19 tiles
+        assert tb is not None
+        busy = q.push(ts[0], cam8, small, 8, 8)
+        q.wait(tb)
+        ts_ = q.push(ts[0], cam8, small, 8, 8) if busy is None else busy
+        assert ts_ is not None
+        q.wait(ts_)
+        print(f"full queue reported: {busy is None}")
+    finally:
+        q.close()
+    q = serve.Queue("f16", max_jobs=4, max_seconds=0.2)
+    try:
+        time.sleep(0.6)
+        with pytest.raises(L.DotError) as e:
+            q.push(ts[0], cam8, small, 8, 8)
+        assert e.value.code == L.DOT_EHIP
+    finally:
+        q.close()
+    t32.close()
+
+
+def test_persistent_server_poisson(trees):
+    """The persistent server under Poisson arrivals: every request completes,
+    and checked results equal the same requests rendered alone."""
+    core, serve = _mods()
+    scenes, ts = trees
+    reqs = serve.poisson_requests(len(ts), rate=3000.0, duration=0.4, seed=24,
+                                  resolutions=[(128, 128), (256, 256), (333, 251)])
+    ref = _reference_images(core, ts, [r for r in reqs if r.rid % 9 == 0])
+    torch.cuda.synchronize()
+    srv = serve.PersistentServer(ts, out_budget_bytes=256 << 20, max_seconds=8.0)
+    st = srv.run(reqs, keep_outputs=True)
+    print({k: st[k] for k in ("requests", "p50_ms", "p99_ms", "mrays_per_s")})
+    assert st["requests"] == len(reqs) and st["rejected"] == 0
+    for r in reqs:
+        if r.rid in ref:
+            np.testing.assert_allclose(r.out.cpu().numpy(), ref[r.rid], atol=1e-6, rtol=0)
