@@ -4,16 +4,25 @@
 // Host -> device: jobs are written into a ring of records in pinned,
 // host-coherent memory and published by a counter.  One wave of the launch
 // (workgroup 0, wave 0: the "feeder") polls that counter, copies each newly
-// published job into a device job table and writes one tile-ring entry per
-// tile of the job (job slot << 20 | tile index in the image), then advances
-// the device tile count `tail`.
+// published job into a device job table and writes its work items into the
+// tile rings, one ring per XCD, each receiving a contiguous eighth of the
+// job's tiles.  An item is a run of up to kMaxRun consecutive 8x8 tiles of one
+// job (job slot, first tile index in the image, run length in one 64-bit
+// entry); then the feeder advances the rings' published item counts `tail`.
 //
-// Workers (every other workgroup): a wave claims the next tile number with an
-// atomic on `next`, waits until the feeder has published it (or the queue is
-// stopped), reads the tile's entry and job, renders the tile with the same
-// per-ray code as dot_render, and counts the tile done for its job; the wave
-// that completes a job's last tile writes the job's number + 1 into the job's
-// completion word in host memory.
+// Workers (every other workgroup): a wave claims the next item of its XCD's
+// ring with an atomic on that ring's `next`, waits until the feeder has
+// published it (or the queue is stopped), reads the item and its job, renders
+// the run's tiles with the same per-ray code as dot_render, and counts them
+// done for the job; the wave that completes a job's last tile writes the
+// job's number + 1 into the job's completion word in host memory.
+//
+// Why runs: the count that makes a wave's pixels visible to the other XCDs is
+// a release at device scope, which writes back the wave's whole L2.  One per
+// 64-ray tile capped the launch near half of what relaunching reaches; a run
+// of several tiles pays it once.  Runs are sized per job so that a job still
+// spreads over about all the waves of the chip (a lone job's latency is one
+// run's render time).
 //
 // Exit: the host sets `stop` when no job will follow; the feeder then copies
 // what is left and raises the device stop flag, and a worker that finds its
@@ -35,11 +44,16 @@ namespace dot {
 
 namespace {
 
-constexpr int kTileRingBits = 20;
-constexpr uint64_t kTileRing = 1ull << kTileRingBits;   // tile-ring entries
-constexpr uint64_t kMaxOpenTiles = kTileRing / 2;       // tiles of unfinished jobs
-constexpr int64_t kMaxImageTiles = 1ll << 20;           // tile index field of an entry
+constexpr int kTileBits = 20;                           // tile index field of an entry
+constexpr uint32_t kTileMask = (1u << kTileBits) - 1u;
+constexpr int64_t kMaxImageTiles = 1ll << kTileBits;
 constexpr int kMaxJobs = 4096;                          // job slot field of an entry (12 bits)
+constexpr int kRings = 8;                               // one tile ring per XCD
+constexpr uint64_t kRing = 1ull << 18;                  // entries (runs) per ring
+constexpr uint64_t kMaxOpenTiles = 1ull << 19;          // tiles of unfinished jobs (all rings)
+constexpr int64_t kMaxRun = 8;                          // tiles per ring entry, at most
+constexpr int64_t kRunSpread = 2048;                    // a job is cut into at least this many runs
+constexpr int kSlotShift = 40;                          // entry: slot << 40 | run << 20 | first tile
 
 // One job as the workers read it (device job table) and as the host writes it
 // (pinned ring); copied word by word by the feeder.
@@ -70,12 +84,12 @@ struct alignas(128) Line64 {
 };
 
 struct ServeDevice {
-    Line64* next;            // tiles claimed by workers
-    Line64* tail;            // tiles published to the workers
+    Line64* next;            // [kRings] tiles claimed by workers, per ring
+    Line64* tail;            // [kRings] tiles published to the workers, per ring
     Line64* stop;            // feeder: leave once your tile is unpublished
     uint32_t* done;          // [max_jobs] tiles rendered per job slot
     ServeJob* jobs;          // [max_jobs] job table
-    uint32_t* ring;          // [kTileRing] tile entries
+    uint64_t* ring;          // [kRings][kRing] run entries
 };
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -99,11 +113,16 @@ __device__ __forceinline__ uint64_t poll_dev(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// the feeder: one wave
+// the feeder: one wave.  A job's tiles are cut into kRings contiguous
+// chunks, chunk x going to ring (seq + x) mod kRings, so every XCD renders a
+// contiguous part of every image (its L2 then holds neighbouring tiles) and
+// jobs of one tile still spread over the XCDs; each chunk is cut into runs of
+// `run` tiles (the last one shorter).
 __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevice& dv, int max_jobs,
                        uint64_t t0, uint64_t limit_ticks) {
     const int lane = threadIdx.x & (WAVE - 1);
-    uint64_t copied = 0, tail = 0;
+    uint64_t copied = 0;
+    uint64_t tail[kRings] = {};
     for (;;) {
         bool late = wall_clock64() - t0 > limit_ticks;
         const uint64_t pub = uniform64(poll_sys(&ctl->published));
@@ -118,14 +137,33 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
             int64_t count = (int64_t)uniform64(poll_sys(reinterpret_cast<const uint64_t*>(&hjobs[slot].tile_count)));
             // the host validated the range; a record read wrong must still not run away
             count = count < 0 ? 0 : (count > kMaxImageTiles ? kMaxImageTiles : count);
-            for (int64_t i = lane; i < count; i += WAVE)
-                __hip_atomic_store(&dv.ring[(tail + (uint64_t)i) & (kTileRing - 1)],
-                                   ((uint32_t)slot << kTileRingBits) | ((uint32_t)(begin + i) & (uint32_t)(kTileRing - 1)),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tail += (uint64_t)count;
+            const int64_t chunk = (count + kRings - 1) / kRings;
+            const int64_t run0 = count / kRunSpread;
+            const int64_t run = run0 < 1 ? 1 : (run0 > kMaxRun ? kMaxRun : run0);
+#pragma unroll
+            for (int x = 0; x < kRings; ++x) {
+                const int r = (int)((copied + (uint64_t)x) % kRings);
+                const int64_t a = (int64_t)x * chunk;
+                const int64_t n = a < count ? (count - a < chunk ? count - a : chunk) : 0;
+                const int64_t items = (n + run - 1) / run;
+                uint64_t* ring = dv.ring + (uint64_t)r * kRing;
+                for (int64_t i = lane; i < items; i += WAVE) {
+                    const int64_t first = i * run;
+                    const int64_t len = n - first < run ? n - first : run;
+                    const uint64_t e = ((uint64_t)slot << kSlotShift) | ((uint64_t)len << kTileBits) |
+                                       ((uint64_t)(begin + a + first) & kTileMask);
+                    __hip_atomic_store(&ring[(tail[r] + (uint64_t)i) & (kRing - 1)], e, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+                tail[r] += (uint64_t)items;
+            }
             ++copied;
-            // the job record and its entries before the tile count that covers them
-            if (lane == 0) __hip_atomic_store(&dv.tail->v, tail, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // the job record and its entries before the counts that cover them:
+            // one release fence, then the eight counts
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                for (int r = 0; r < kRings; ++r)
+                    __hip_atomic_store(&dv.tail[r].v, tail[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             late = wall_clock64() - t0 > limit_ticks;
         }
         const bool stop = __builtin_amdgcn_readfirstlane(poll_sys32(&ctl->stop)) != 0u;
@@ -185,28 +223,41 @@ __global__ __launch_bounds__(BLOCK) void serve_loop_kernel(ServeHostCtl* ctl, co
         if ((tid >> 6) == 0) feeder(ctl, hjobs, dv, max_jobs, t0, limit_ticks);
         return;
     }
+    // workgroups are dispatched round-robin over the XCDs: this one takes its
+    // tiles from its XCD's ring
+    const int x = (int)(blockIdx.x % kRings);
+    uint64_t* const ring = dv.ring + (uint64_t)x * kRing;
+    // the run being rendered: job slot, next tile, tiles left, run length
+    int slot = 0;
+    int64_t tile = 0, left = 0, len = 0;
     for (;;) {
-        uint64_t t = 0;
-        if (lane == 0) t = atomicAdd(reinterpret_cast<unsigned long long*>(&dv.next->v), 1ull);
-        t = uniform64(t);
-        // wait until the feeder has published tile t; leave on the stop flag,
-        // or by this wave's own clock past the time limit (so the launch ends
-        // even if the feeder could not raise the flag)
-        for (;;) {
-            if (t < uniform64(poll_dev(&dv.tail->v))) break;
-            if (uniform64(poll_dev(&dv.stop->v)) != 0ull) return;
-            if (wall_clock64() - t0 > limit_ticks + limit_ticks / 8) return;
-            __builtin_amdgcn_s_sleep(64);
+        if (left == 0) {
+            uint64_t t = 0;
+            if (lane == 0) t = atomicAdd(reinterpret_cast<unsigned long long*>(&dv.next[x].v), 1ull);
+            t = uniform64(t);
+            // wait until the feeder has published entry t of this ring; leave on
+            // the stop flag, or by this wave's own clock past the time limit (so
+            // the launch ends even if the feeder could not raise the flag)
+            for (;;) {
+                if (t < uniform64(poll_dev(&dv.tail[x].v))) break;
+                if (uniform64(poll_dev(&dv.stop->v)) != 0ull) return;
+                if (wall_clock64() - t0 > limit_ticks + limit_ticks / 8) return;
+                __builtin_amdgcn_s_sleep(64);
+            }
+            // the entry and the job record are read only after the count that
+            // published them was seen (their loads are coherent, so no cache
+            // needs invalidating; this keeps the compiler from moving them earlier)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            const uint64_t e = uniform64(__hip_atomic_load(&ring[t & (kRing - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            slot = (int)(e >> kSlotShift);
+            tile = (int64_t)(e & kTileMask);
+            len = (int64_t)((e >> kTileBits) & kTileMask);
+            // cannot happen for a published entry; never index past the table
+            if (slot >= max_jobs || len < 1 || len > kMaxRun) continue;
+            left = len;
         }
-        // the entry and the job record are read only after the tile count that
-        // published them was seen (their loads are coherent, so no cache needs
-        // invalidating; this keeps the compiler from moving them earlier)
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        const uint32_t e = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(&dv.ring[t & (kTileRing - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        const int slot = (int)(e >> kTileRingBits);
-        const int64_t tile = (int64_t)(e & (uint32_t)(kTileRing - 1));
-        if (slot >= max_jobs) continue;     // cannot happen for a published tile; never index past the table
+        // the job record is read again for every tile: kept in registers across
+        // the run it would raise the kernel's register count and cut occupancy
         const ServeJob j = read_job(dv.jobs + slot);
         switch (j.degree) {
             case 0: serve_tile<DT, 0>(j, tile, lane, &stack_lds[tid]); break;
@@ -214,10 +265,12 @@ __global__ __launch_bounds__(BLOCK) void serve_loop_kernel(ServeHostCtl* ctl, co
             case 2: serve_tile<DT, 2>(j, tile, lane, &stack_lds[tid]); break;
             default: serve_tile<DT, 3>(j, tile, lane, &stack_lds[tid]); break;
         }
-        // the tile's pixels before its count (one release per tile); the job's
+        ++tile;
+        if (--left > 0) continue;
+        // the run's pixels before its count (one release per run); the job's
         // last tile publishes the job to the host
         if (lane == 0) {
-            const uint32_t c = __hip_atomic_fetch_add(&dv.done[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            const uint32_t c = __hip_atomic_fetch_add(&dv.done[slot], (uint32_t)len, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + (uint32_t)len;
             if ((int64_t)c == j.tile_count) {
                 __hip_atomic_store(&dv.done[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __atomic_thread_fence(__ATOMIC_SEQ_CST);
@@ -314,10 +367,10 @@ int dot_serve_open(int32_t storage, int32_t max_jobs, double max_seconds, void* 
     hipError_t e = hipHostMalloc((void**)&q->ctl, sizeof(ServeHostCtl), hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostMalloc((void**)&q->hjobs, sizeof(ServeJob) * (size_t)max_jobs, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostMalloc((void**)&q->hdone, sizeof(uint64_t) * (size_t)max_jobs, hipHostMallocCoherent);
-    const size_t lines = 3 * sizeof(Line64);
+    const size_t lines = (2 * kRings + 1) * sizeof(Line64);
     const size_t done_b = ((sizeof(uint32_t) * (size_t)max_jobs) + 255) & ~(size_t)255;
     const size_t jobs_b = ((sizeof(ServeJob) * (size_t)max_jobs) + 255) & ~(size_t)255;
-    const size_t total = lines + done_b + jobs_b + sizeof(uint32_t) * kTileRing;
+    const size_t total = lines + done_b + jobs_b + sizeof(uint64_t) * kRing * kRings;
     if (e == hipSuccess) e = hipMalloc(&q->dmem, total);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ended, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -329,11 +382,11 @@ int dot_serve_open(int32_t storage, int32_t max_jobs, double max_seconds, void* 
     std::memset(q->hdone, 0, sizeof(uint64_t) * (size_t)max_jobs);
     char* base = static_cast<char*>(q->dmem);
     q->dv.next = reinterpret_cast<Line64*>(base);
-    q->dv.tail = q->dv.next + 1;
-    q->dv.stop = q->dv.next + 2;
+    q->dv.tail = q->dv.next + kRings;
+    q->dv.stop = q->dv.next + 2 * kRings;
     q->dv.done = reinterpret_cast<uint32_t*>(base + lines);
     q->dv.jobs = reinterpret_cast<ServeJob*>(base + lines + done_b);
-    q->dv.ring = reinterpret_cast<uint32_t*>(base + lines + done_b + jobs_b);
+    q->dv.ring = reinterpret_cast<uint64_t*>(base + lines + done_b + jobs_b);
     int dev = 0, khz = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
