@@ -462,6 +462,21 @@ int dot_mse_loss(const float *pred, const float *target, const int64_t *target_i
                  float *grad_rgb_out, double *loss_out, void *stream);
 
 /*
+ * dot_mse_grad -- the gradient of dot_mse_loss times a factor that lives on
+ *  the device (the upstream gradient of the loss when the loss is itself
+ *  differentiated by a caller's chain rule, Sec. 3):
+ *      grad_rgb[r] = s * 2 (pred[r] - target[idx_r]) / (3n),   s = *scale
+ *  scale: DEVICE double [1], or NULL for s = 1 (then the gradient equals
+ *  dot_mse_loss's bit for bit); the product 2s/(3n) and the residual are
+ *  formed in FP64 and rounded once.  Other arguments as dot_mse_loss;
+ *  grad_rgb_out is required when n_rays > 0.
+ *  Errors: DOT_EINVAL on n_rays < 0, or a NULL pred/target/grad_rgb_out with
+ *  n_rays > 0.
+ */
+int dot_mse_grad(const float *pred, const float *target, const int64_t *target_idx, int64_t n_rays,
+                 const double *scale, float *grad_rgb_out, void *stream);
+
+/*
  * dot_quantize_sh -- compress the tree's SH coefficients into a palette (the
  *  compressed octrees of Sec. 4.1, quantised with Heckbert's median cut).
  *  Each leaf's SH row (3K values as stored) is a point; `bits` rounds each cut

@@ -504,20 +504,25 @@ class DotRender(torch.autograd.Function):
 
 
 class MSELoss(torch.autograd.Function):
-    """Mean squared error of pred [n, 3] against target rows (Alg. 1's loss),
-    loss and gradient from one kernel (dot_mse_loss); the loss is a float64
-    device scalar."""
+    """Mean squared error of pred [n, 3] against target rows (Alg. 1's loss);
+    the loss is a float64 device scalar (dot_mse_loss).  The backward is one
+    kernel (dot_mse_grad) that scales the gradient by the upstream gradient
+    where it lies on the device, so no host value is read."""
 
     @staticmethod
     def forward(ctx, pred, target, target_idx=None):
-        loss, grad = mse_loss(pred, target, target_idx)
-        ctx.save_for_backward(grad)
+        loss, _ = mse_loss(pred, target, target_idx, grad=False)
+        ctx.save_for_backward(pred, target, target_idx)
         return loss
 
     @staticmethod
     def backward(ctx, grad_loss):
-        (grad,) = ctx.saved_tensors
-        return grad * grad_loss.to(grad.dtype), None, None
+        pred, target, target_idx = ctx.saved_tensors
+        scale = grad_loss.detach().to(torch.float64).contiguous()
+        g = torch.empty_like(pred)
+        L.check(L.load().dot_mse_grad(_ptr(pred), _ptr(target), _ptr(target_idx), C.c_int64(pred.shape[0]),
+                                      _ptr(scale), _ptr(g), _stream()))
+        return g, None, None
 
 
 def mse_loss_autograd(pred, target, target_idx=None):

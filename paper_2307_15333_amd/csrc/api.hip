@@ -176,6 +176,7 @@ static void release(dot_tree* t) {
     t->links = nullptr;
     if (t->host_rb) (void)hipHostFree(t->host_rb);
     t->host_rb = nullptr;
+    drop_notes(*t);
     t->child = nullptr;
     t->sigma = nullptr;
     t->sh = nullptr;
@@ -427,9 +428,11 @@ int dot_render_train(dot_tree_t t, const dot_rays* rays, const dot_render_opts* 
     rc = records_for(records, records_bytes, rb.n_rays, a.rec, "dot_render_train");
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_fill_u32(leaf_count_out, 2 * t->n_leaves, s, a.rec.a ? a.rec.overflow : nullptr);
+    // the records header's overflow count and row total start at zero
+    hipError_t e = launch_fill_u32(leaf_count_out, 2 * t->n_leaves, s, a.rec.a ? a.rec.overflow : nullptr, 2);
     if (e == hipSuccess) e = launch_render_fwd(*t, rb, a, s);
     if (e != hipSuccess) return hip_fail(e, "dot_render_train: launch");
+    if (a.rec.a && rb.n_rays > 0) note_forward(*t, a.rec, leaf_count_out, rb.n_rays, s);
     return DOT_OK;
 }
 
@@ -691,9 +694,21 @@ int dot_mse_loss(const float* pred, const float* target, const int64_t* target_i
                  float* grad_rgb_out, double* loss_out, void* stream) {
     if (n_rays < 0) return fail(DOT_EINVAL, "dot_mse_loss: n_rays < 0");
     if (n_rays > 0 && (!pred || !target)) return fail(DOT_EINVAL, "dot_mse_loss: NULL prediction or target");
-    hipError_t e = launch_mse(pred, target, target_idx, n_rays, grad_rgb_out, loss_out,
+    hipError_t e = launch_mse(pred, target, target_idx, n_rays, nullptr, grad_rgb_out, loss_out,
                               static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_mse_loss: launch");
+    return DOT_OK;
+}
+
+int dot_mse_grad(const float* pred, const float* target, const int64_t* target_idx, int64_t n_rays,
+                 const double* scale, float* grad_rgb_out, void* stream) {
+    if (n_rays < 0) return fail(DOT_EINVAL, "dot_mse_grad: n_rays < 0");
+    if (n_rays > 0 && (!pred || !target || !grad_rgb_out))
+        return fail(DOT_EINVAL, "dot_mse_grad: NULL prediction, target or gradient");
+    if (n_rays == 0) return DOT_OK;
+    hipError_t e = launch_mse(pred, target, target_idx, n_rays, scale, grad_rgb_out, nullptr,
+                              static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_mse_grad: launch");
     return DOT_OK;
 }
 

@@ -80,6 +80,20 @@ struct dot_tree {
     // pinned host words the adjoint reads back (allocated on first use; one
     // adjoint at a time per tree, like every other call that uses its scratch)
     mutable uint32_t* host_rb = nullptr;
+    // What each recent training forward that recorded hands its adjoint: the
+    // batch's bucket-row total and overflow count, copied into pinned memory
+    // behind an event by the forward, so the adjoint reads them without
+    // stopping the stream.  Keyed by the records and counts buffers.
+    struct FwdNote {
+        const void* rec = nullptr;
+        const uint32_t* counts = nullptr;
+        int64_t n_rays = 0, n_leaves = 0;   // n_leaves: a refinement in between invalidates the note
+        hipEvent_t ev = nullptr;
+    };
+    static constexpr int kNotes = 4;
+    mutable FwdNote notes[kNotes];
+    mutable uint32_t* note_words = nullptr;   // pinned [kNotes][2]: overflow, total
+    mutable int note_next = 0;
 
     dot::TreeView view() const {
         dot::TreeView v;
@@ -145,6 +159,7 @@ struct SegRecords {
     uint32_t* slot = nullptr;     // [cap][n]: bucket slot of the record's row
     int32_t* count = nullptr;     // [n]: records of the ray
     uint32_t* overflow = nullptr; // [1]: rays with more than `cap` records
+    uint32_t* total = nullptr;    // [1]: segments with sigma > 0 of the batch (= bucket rows of its adjoint)
     int32_t* olist = nullptr;     // [n]: ids of those rays (first `overflow` entries)
     int64_t n = 0;                // rays the buffer holds (the slot stride)
     int cap = 0;                  // records per ray
@@ -214,7 +229,13 @@ hipError_t launch_render_fwd(const dot_tree& t, const RayBatch& rb, const FwdArg
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
 // re-traversal adjoint with wave-level per-leaf sums before the float atomics
 hipError_t launch_render_bwd_wave(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s);
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s, uint32_t* word = nullptr);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s, uint32_t* word = nullptr, int n_words = 1);
+// training forward that recorded: queue the copy of its row total and overflow
+// count for the adjoint (no effect when that cannot be set up: the adjoint then
+// reads them back itself); the adjoint's lookup (null when there is none)
+void note_forward(const dot_tree& t, const SegRecords& rec, const uint32_t* counts, int64_t n_rays, hipStream_t s);
+const uint32_t* find_note(const dot_tree& t, const void* rec, const uint32_t* counts, int64_t n_rays, hipEvent_t* ev);
+void drop_notes(const dot_tree& t);
 hipError_t launch_encode_planes(int storage, const float* src, void* dst, int64_t rows, int src_cols,
                                 int dst_stride, hipStream_t s);
 hipError_t launch_decode_planes(int storage, const void* src, float* dst, int64_t rows, int dst_cols,
@@ -233,8 +254,8 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum
 hipError_t launch_rmsprop(const dot_tree& t, const float* gs, const float* gh, float* vs, float* vh,
                           const dot_rmsprop_params& p, hipStream_t s);
 hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s);
-hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx, int64_t n, float* grad,
-                      double* loss, hipStream_t s);
+hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx, int64_t n, const double* gmul,
+                      float* grad, double* loss, hipStream_t s);
 size_t pixel_batch_workspace_bytes(int64_t n, int32_t W, int32_t H, int32_t n_cams);
 hipError_t launch_pixel_batch(const int64_t* ids, int64_t n, int32_t W, int32_t H, int32_t n_cams, int32_t* cam_out,
                               int32_t* pix_out, int64_t* id_out, void* ws, hipStream_t s);

@@ -194,9 +194,11 @@ constexpr int MSE_BLOCKS = 256;
 
 __global__ __launch_bounds__(MSE_THREADS) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
                                                   const int64_t* __restrict__ idx, int64_t n, double gscale,
-                                                  float* __restrict__ grad, double* __restrict__ loss, double lscale) {
+                                                  const double* __restrict__ gmul, float* __restrict__ grad,
+                                                  double* __restrict__ loss, double lscale) {
     __shared__ double part[MSE_THREADS / WAVE];
     double acc = 0.0;
+    if (gmul) gscale *= *gmul;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t t = idx ? idx[r] : r;
 #pragma unroll
@@ -217,8 +219,8 @@ __global__ __launch_bounds__(MSE_THREADS) void mse_kernel(const float* __restric
     }
 }
 
-hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx, int64_t n, float* grad,
-                      double* loss, hipStream_t s) {
+hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx, int64_t n, const double* gmul,
+                      float* grad, double* loss, hipStream_t s) {
     if (loss) {
         hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(1), 0, s, loss);
         hipError_t e = hipGetLastError();
@@ -228,8 +230,8 @@ hipError_t launch_mse(const float* pred, const float* target, const int64_t* idx
     int64_t g = (n + MSE_THREADS - 1) / MSE_THREADS;
     if (g > MSE_BLOCKS) g = MSE_BLOCKS;
     const double gscale = 2.0 / (3.0 * (double)n);
-    hipLaunchKernelGGL(mse_kernel, dim3((unsigned)g), dim3(MSE_THREADS), 0, s, pred, target, idx, n, gscale, grad,
-                       loss, 1.0 / (3.0 * (double)n));
+    hipLaunchKernelGGL(mse_kernel, dim3((unsigned)g), dim3(MSE_THREADS), 0, s, pred, target, idx, n, gscale, gmul,
+                       grad, loss, 1.0 / (3.0 * (double)n));
     return hipGetLastError();
 }
 

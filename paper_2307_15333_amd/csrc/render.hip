@@ -30,6 +30,9 @@ __global__ __launch_bounds__(BLOCK) void render_fwd_kernel(TreeView tv, RayBatch
             seg.flush_slot();
             a.rec.count[rid] = seg.nrec;
             if (seg.nrec > a.rec.cap) a.rec.olist[atomicAdd(a.rec.overflow, 1u)] = (int32_t)rid;
+            // every segment counted above is one bucket row (one atomic per wave
+            // after the compiler's wave reduction of a same-address add)
+            atomicAdd(a.rec.total, (uint32_t)seg.nrec);
         }
     }
     if (a.rgb) {
@@ -593,6 +596,7 @@ SegRecords seg_records_view(void* base, int64_t n, size_t bytes) {
     if (cap == 0) return r;
     char* p = static_cast<char*>(base);
     r.overflow = reinterpret_cast<uint32_t*>(p);
+    r.total = r.overflow + 1;
     p += 256;
     r.count = reinterpret_cast<int32_t*>(p);
     p += up256((size_t)n * 4);
@@ -950,16 +954,17 @@ static void launch_reduce_wave(const dot_tree& t, const BwdArgs& a, const uint32
 static constexpr uint32_t kWaveRowsPerLeaf = 32;
 
 // p[0, n) = 0, and *word = 0 when given (one launch for an array and a counter)
-__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t* word) {
-    if (word && blockIdx.x == 0 && threadIdx.x == 0) *word = 0u;
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t* word, int n_words) {
+    if (word && blockIdx.x == 0 && (int)threadIdx.x < n_words) word[threadIdx.x] = 0u;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
 }
 
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s, uint32_t* word) {
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s, uint32_t* word, int n_words) {
     if (n <= 0 && !word) return hipSuccess;
     const int64_t g = std::max<int64_t>((n + 255) / 256, 1);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>(g, 65536)), dim3(256), 0, s, p, n, word);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>(g, 65536)), dim3(256), 0, s, p, n, word,
+                       n_words < 1 ? 1 : (n_words > 256 ? 256 : n_words));
     return hipGetLastError();
 }
 
@@ -1090,7 +1095,7 @@ static hipError_t bwd_fused_dense(const dot_tree& t, const RayBatch& rb, const B
     a.grad_sh = g + t.n_leaves;
     const int64_t n = t.n_leaves * (1 + nv);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s,
-                       reinterpret_cast<uint32_t*>(g), n, nullptr);
+                       reinterpret_cast<uint32_t*>(g), n, nullptr, 1);
     hipError_t e = rb.n_tiles ? bwd_atomic(t, rb, a, grid, s) : hipGetLastError();
     if (e == hipSuccess)
         e = a.adam ? launch_adam(t, a.grad_sigma, a.grad_sh, a.m_sigma, a.v_sigma, a.m_sh, a.v_sh, *a.adam, s)
@@ -1128,6 +1133,64 @@ static void launch_bwd_fused(const dot_tree& t, const BwdArgs& a, const uint32_t
     else
         hipLaunchKernelGGL((bwd_fused_kernel<DEG, OPT_RMSPROP, 1>), g, b, 0, s, L, offset, base0, count, cursor, rows,
                            sg, sh, t.sh_stride, o);
+}
+
+void note_forward(const dot_tree& t, const SegRecords& rec, const uint32_t* counts, int64_t n_rays, hipStream_t s) {
+    if (!t.note_words) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, sizeof(uint32_t) * 2 * dot_tree::kNotes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        t.note_words = static_cast<uint32_t*>(h);
+    }
+    const int i = t.note_next;
+    t.note_next = (i + 1) % dot_tree::kNotes;
+    dot_tree::FwdNote& nt = t.notes[i];
+    // the slot's previous copy must have landed before it is written again
+    if (nt.rec && nt.ev && hipEventSynchronize(nt.ev) != hipSuccess) (void)hipGetLastError();
+    nt.rec = nullptr;
+    if (!nt.ev && hipEventCreateWithFlags(&nt.ev, hipEventDisableTiming) != hipSuccess) {
+        nt.ev = nullptr;
+        (void)hipGetLastError();
+        return;
+    }
+    if (hipMemcpyAsync(t.note_words + 2 * i, rec.overflow, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(nt.ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    nt.rec = rec.overflow;
+    nt.counts = counts;
+    nt.n_rays = n_rays;
+    nt.n_leaves = t.n_leaves;
+}
+
+const uint32_t* find_note(const dot_tree& t, const void* rec, const uint32_t* counts, int64_t n_rays, hipEvent_t* ev) {
+    if (!t.note_words) return nullptr;
+    // the most recent forward into these buffers
+    for (int k = 1; k <= dot_tree::kNotes; ++k) {
+        const int i = (t.note_next - k + dot_tree::kNotes) % dot_tree::kNotes;
+        const dot_tree::FwdNote& nt = t.notes[i];
+        if (nt.rec == rec && nt.counts == counts && nt.n_rays == n_rays && nt.n_leaves == t.n_leaves && nt.ev) {
+            *ev = nt.ev;
+            return t.note_words + 2 * i;
+        }
+    }
+    return nullptr;
+}
+
+void drop_notes(const dot_tree& t) {
+    for (auto& nt : t.notes) {
+        if (nt.ev) {
+            (void)hipEventSynchronize(nt.ev);
+            (void)hipEventDestroy(nt.ev);
+        }
+        nt = dot_tree::FwdNote{};
+    }
+    if (t.note_words) (void)hipHostFree(t.note_words);
+    t.note_words = nullptr;
+    t.note_next = 0;
 }
 
 hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArgs& a, hipStream_t s) {
@@ -1174,8 +1237,8 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     }
     unsigned fg = (unsigned)std::min<int64_t>((L + 255) / 256, 65536);
     if (!a.leaf_count) {
-        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L, nullptr);
-        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count_own, L, nullptr);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, cursor, L, nullptr, 1);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, s, count_own, L, nullptr, 1);
         switch (t.storage) {
             case DOT_F32: hipLaunchKernelGGL(bwd_count_kernel<DOT_F32>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
             case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
@@ -1187,19 +1250,33 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
                            L, a.rec.a ? a.rec.overflow : nullptr, tot + 1);
     }
     hipError_t e = scan_u32(total, offset, L, bsum, tot, s);
-    // the row total and the overflow count in one copy into pinned memory, one wait
-    if (e == hipSuccess && !t.host_rb) {
-        void* h = nullptr;
-        e = hipHostMalloc(&h, 16, hipHostMallocDefault);
-        if (e == hipSuccess) t.host_rb = static_cast<uint32_t*>(h);
+    // The row total and the overflow count: from the note of the forward that
+    // recorded (its copy, queued behind that forward, is waited for by its event:
+    // the stream keeps running), else in one copy into pinned memory and one wait.
+    hipEvent_t note_ev = nullptr;
+    const uint32_t* note = replay ? find_note(t, a.rec.overflow, a.leaf_count, rb.n_rays, &note_ev) : nullptr;
+    uint32_t m = 0, overflow = 0;
+    if (note) {
+        if (e == hipSuccess) e = hipEventSynchronize(note_ev);
+        overflow = note[0];
+        m = note[1];
+    } else {
+        if (e == hipSuccess && !t.host_rb) {
+            void* h = nullptr;
+            e = hipHostMalloc(&h, 16, hipHostMallocDefault);
+            if (e == hipSuccess) t.host_rb = static_cast<uint32_t*>(h);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(t.host_rb, tot, a.rec.a ? 8 : 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) {
+            m = t.host_rb[0];
+            overflow = a.rec.a ? t.host_rb[1] : 0u;
+        }
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(t.host_rb, tot, a.rec.a ? 8 : 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         drop();
         return e;
     }
-    const uint32_t m = t.host_rb[0], overflow = a.rec.a ? t.host_rb[1] : 0u;
     float* rows = nullptr;
     if ((double)m * rs * 4 <= kBucketBytesMax) rows = static_cast<float*>(t.alloc.get((size_t)std::max<uint32_t>(m, 1) * rs * 4));
     if (!rows) {

@@ -21,14 +21,20 @@
 // a release at device scope, which writes back the wave's whole L2.  One per
 // 64-ray tile capped the launch near half of what relaunching reaches; a run
 // of several tiles pays it once.  Runs are sized per job so that a job still
-// spreads over about all the waves of the chip (a lone job's latency is one
-// run's render time).
+// spreads over about all the waves of the chip.
+//
+// Polls are device-coherent loads, served beyond the L2; waves that find no
+// work back off (up to about 13 us between polls) so that thousands of idle
+// waves do not keep one memory channel busy under the waves that render, and
+// the stop flag rides in the top bit of each ring's published count so that a
+// poll is one load.
 //
 // Exit: the host sets `stop` when no job will follow; the feeder then copies
-// what is left and raises the device stop flag, and a worker that finds its
-// claimed tile unpublished while the stop flag is up leaves.  The feeder also
-// raises it once the launch has run for the queue's time limit, so every wave
-// leaves whatever the host does.
+// what is left and sets the stop bit of every ring's published count, and a
+// worker that finds its claimed entry unpublished with the stop bit set
+// leaves.  The feeder also sets it once the launch has run for the queue's
+// time limit, and a waiting worker leaves by its own clock after 9/8 of it, so
+// every wave leaves whatever the host does.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -53,6 +59,8 @@ constexpr uint64_t kRing = 1ull << 18;                  // entries (runs) per ri
 constexpr uint64_t kMaxOpenTiles = 1ull << 19;          // tiles of unfinished jobs (all rings)
 constexpr int64_t kMaxRun = 8;                          // tiles per ring entry, at most
 constexpr int64_t kRunSpread = 2048;                    // a job is cut into at least this many runs
+constexpr uint64_t kStopBit = 1ull << 63;               // in a ring's published count: no entry will follow
+constexpr int kMaxNaps = 4;                             // idle backoff: up to 4 x 127 x 64 clocks between polls
 constexpr int kSlotShift = 40;                          // entry: slot << 40 | run << 20 | first tile
 
 // One job as the workers read it (device job table) and as the host writes it
@@ -84,9 +92,8 @@ struct alignas(128) Line64 {
 };
 
 struct ServeDevice {
-    Line64* next;            // [kRings] tiles claimed by workers, per ring
-    Line64* tail;            // [kRings] tiles published to the workers, per ring
-    Line64* stop;            // feeder: leave once your tile is unpublished
+    Line64* next;            // [kRings] entries claimed by workers, per ring
+    Line64* tail;            // [kRings] entries published to the workers, per ring (| kStopBit at the end)
     uint32_t* done;          // [max_jobs] tiles rendered per job slot
     ServeJob* jobs;          // [max_jobs] job table
     uint64_t* ring;          // [kRings][kRing] run entries
@@ -117,7 +124,8 @@ __device__ __forceinline__ uint64_t poll_dev(const uint64_t* p) {
 // chunks, chunk x going to ring (seq + x) mod kRings, so every XCD renders a
 // contiguous part of every image (its L2 then holds neighbouring tiles) and
 // jobs of one tile still spread over the XCDs; each chunk is cut into runs of
-// `run` tiles (the last one shorter).
+// `run` tiles (the last one shorter): the job's tile count / kRunSpread,
+// clamped to 1..kMaxRun, so a job still spreads over about all the waves.
 __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevice& dv, int max_jobs,
                        uint64_t t0, uint64_t limit_ticks) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -169,7 +177,8 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
         const bool stop = __builtin_amdgcn_readfirstlane(poll_sys32(&ctl->stop)) != 0u;
         if ((stop && copied == uniform64(poll_sys(&ctl->published))) || late) {
             if (lane == 0) {
-                __hip_atomic_store(&dv.stop->v, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                for (int r = 0; r < kRings; ++r)
+                    __hip_atomic_store(&dv.tail[r].v, tail[r] | kStopBit, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 if (late) __hip_atomic_store(&ctl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(&ctl->ended, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
@@ -236,13 +245,14 @@ __global__ __launch_bounds__(BLOCK) void serve_loop_kernel(ServeHostCtl* ctl, co
             if (lane == 0) t = atomicAdd(reinterpret_cast<unsigned long long*>(&dv.next[x].v), 1ull);
             t = uniform64(t);
             // wait until the feeder has published entry t of this ring; leave on
-            // the stop flag, or by this wave's own clock past the time limit (so
-            // the launch ends even if the feeder could not raise the flag)
-            for (;;) {
-                if (t < uniform64(poll_dev(&dv.tail[x].v))) break;
-                if (uniform64(poll_dev(&dv.stop->v)) != 0ull) return;
+            // the stop bit, or by this wave's own clock past the time limit (so
+            // the launch ends even if the feeder could not set the bit)
+            for (int naps = 1;; naps = naps < kMaxNaps ? naps + 1 : kMaxNaps) {
+                const uint64_t v = uniform64(poll_dev(&dv.tail[x].v));
+                if (t < (v & ~kStopBit)) break;
+                if (v & kStopBit) return;
                 if (wall_clock64() - t0 > limit_ticks + limit_ticks / 8) return;
-                __builtin_amdgcn_s_sleep(64);
+                for (int k = 0; k < naps; ++k) __builtin_amdgcn_s_sleep(127);
             }
             // the entry and the job record are read only after the count that
             // published them was seen (their loads are coherent, so no cache
@@ -367,7 +377,7 @@ int dot_serve_open(int32_t storage, int32_t max_jobs, double max_seconds, void* 
     hipError_t e = hipHostMalloc((void**)&q->ctl, sizeof(ServeHostCtl), hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostMalloc((void**)&q->hjobs, sizeof(ServeJob) * (size_t)max_jobs, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostMalloc((void**)&q->hdone, sizeof(uint64_t) * (size_t)max_jobs, hipHostMallocCoherent);
-    const size_t lines = (2 * kRings + 1) * sizeof(Line64);
+    const size_t lines = 2 * kRings * sizeof(Line64);
     const size_t done_b = ((sizeof(uint32_t) * (size_t)max_jobs) + 255) & ~(size_t)255;
     const size_t jobs_b = ((sizeof(ServeJob) * (size_t)max_jobs) + 255) & ~(size_t)255;
     const size_t total = lines + done_b + jobs_b + sizeof(uint64_t) * kRing * kRings;
@@ -383,7 +393,6 @@ int dot_serve_open(int32_t storage, int32_t max_jobs, double max_seconds, void* 
     char* base = static_cast<char*>(q->dmem);
     q->dv.next = reinterpret_cast<Line64*>(base);
     q->dv.tail = q->dv.next + kRings;
-    q->dv.stop = q->dv.next + 2 * kRings;
     q->dv.done = reinterpret_cast<uint32_t*>(base + lines);
     q->dv.jobs = reinterpret_cast<ServeJob*>(base + lines + done_b);
     q->dv.ring = reinterpret_cast<uint64_t*>(base + lines + done_b + jobs_b);

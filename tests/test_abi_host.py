@@ -160,6 +160,9 @@ def test_batch_and_loss_argument_checks_need_no_device():
     lib = L.load()
     assert lib.dot_mse_loss(None, None, None, -1, None, None, None) == L.DOT_EINVAL
     assert lib.dot_mse_loss(None, None, None, 5, None, None, None) == L.DOT_EINVAL
+    assert lib.dot_mse_grad(None, None, None, -1, None, None, None) == L.DOT_EINVAL
+    assert lib.dot_mse_grad(None, None, None, 5, None, None, None) == L.DOT_EINVAL
+    assert lib.dot_mse_grad(None, None, None, 0, None, None, None) == L.DOT_OK
     assert lib.dot_pixel_batch(None, -1, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
     assert lib.dot_pixel_batch(None, 4, 0, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
     assert lib.dot_pixel_batch(None, 4, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL

@@ -323,6 +323,74 @@ def test_backward_replaying_forward_records(scene_kind, max_segments):
     t2.close()
 
 
+def test_adjoint_takes_row_total_from_the_forward_that_recorded():
+    """The training forward that records leaves its batch's bucket-row total
+    (every segment with sigma > 0) and its overflow count in the records
+    header, and the adjoint takes them from a copy queued behind that forward
+    (matched by the records and counts buffers).  Checked: the header against
+    the per-leaf counts and the per-ray record counts; two forwards into two
+    buffer pairs, adjoints in reverse order; a fifth forward that evicts the
+    first pair's note (that adjoint then reads the total back itself); and a
+    buffer pair written by two batches in turn (the adjoint follows the
+    later).  Every gradient against the oracle's."""
+    core = _core()
+    s = synth.random_tree_scene(5, 2, seed=95, p_split=0.5)
+    views = synth.random_sphere_cameras(5, 3.5, 24, 24, seed=96)
+    tree = core.Octree.from_scene(s)
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    Ln, K = tree.n_leaves, tree.K
+    batches = []
+    for k in range(2):
+        ci, pi = synth.pixel_batch(5, 24, 24, 2000, seed=97 + k)
+        g = np.random.default_rng(99 + k).normal(size=(ci.shape[0], 3))
+        batches.append((ci, pi, core.Rays.pixels(views, ci, pi), g))
+
+    def oracle(b):
+        ci, pi, _, g = batches[b]
+        o, d = O.camera_rays(views, ci, pi)
+        return O.backward(T, o, d, g.astype(np.float32).astype(np.float64), t_stop=0.0)
+
+    def forward(b, rec, cnt=None):
+        return tree.render_train(batches[b][2], t_stop=0.0, records=rec, leaf_count=cnt)
+
+    def adjoint(b, fw, rec, cnt):
+        rgb, ns, _ = fw
+        gs, gh = torch.zeros(Ln, device="cuda"), torch.zeros((Ln, 3, K), device="cuda")
+        gt = torch.as_tensor(batches[b][3], dtype=torch.float32, device="cuda")
+        tree.backward(batches[b][2], rgb, ns, gt, gs, gh, t_stop=0.0, leaf_count=cnt, records=rec)
+        torch.cuda.synchronize()
+        rs, rh = oracle(b)
+        es, eh = _rel(gs.cpu().numpy(), rs), _rel(gh.cpu().numpy(), rh)
+        assert es <= GTOL and eh <= GTOL, (b, es, eh)
+
+    cap = 4   # small: both count regions and the overflow list are used
+    mk = lambda b: torch.empty(core.Octree.records_bytes(batches[b][2].n_rays, cap), dtype=torch.uint8, device="cuda")
+    rec_a, rec_b = mk(0), mk(1)
+    fa = forward(0, rec_a)
+    fb = forward(1, rec_b)
+    torch.cuda.synchronize()
+    for fw, rec, b in ((fa, rec_a, 0), (fb, rec_b, 1)):
+        n = batches[b][2].n_rays
+        hdr = rec[:8].view(torch.int32).cpu().numpy()
+        per_ray = rec[256:256 + 4 * n].view(torch.int32).cpu().numpy()    # records header, then per-ray counts
+        assert int(hdr[1]) == int(fw[2].to(torch.int64).sum().item())      # row total = all counted segments
+        assert int(hdr[1]) == int(per_ray.astype(np.int64).sum())
+        assert int(hdr[0]) == int((per_ray > cap).sum()) > 0               # rays past 4 records
+    adjoint(1, fb, rec_b, fb[2])
+    adjoint(0, fa, rec_a, fa[2])
+    # four more forwards into other buffers evict batch 0's note
+    extra = [mk(0) for _ in range(4)]
+    for r in extra:
+        forward(0, r)
+    adjoint(0, fa, rec_a, fa[2])
+    # one buffer pair, batch 1 then batch 0 (same size) into it: the adjoint follows batch 0
+    rec_c = mk(1)
+    f1 = forward(1, rec_c)
+    f0 = forward(0, rec_c, f1[2])
+    adjoint(0, f0, rec_c, f0[2])
+    tree.close()
+
+
 def test_backward_counts_of_recording_forward_without_records():
     """A training forward that recorded, then an adjoint given its counts but
     not its records: every ray is re-traversed and each leaf's bucket holds

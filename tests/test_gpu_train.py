@@ -69,6 +69,37 @@ def test_mse_loss_matches_oracle():
         assert g2 is None and l2.item() == pytest.approx(ref_l, rel=1e-12, abs=0)
 
 
+def test_mse_grad_scaled_by_a_device_factor():
+    """dot_mse_grad: the oracle's MSE gradient times an FP64 factor read on the
+    device (one FP32 rounding); with no factor it equals dot_mse_loss's
+    gradient bit for bit; through the autograd Function, d(k * loss) = k g."""
+    import ctypes as C
+    from paper_2307_15333_amd import _lib as L
+    core = _core()
+    rng = np.random.default_rng(1)
+    n, m = 70001, 9000
+    pred = rng.uniform(-1, 2, size=(n, 3)).astype(np.float32)
+    tgt = rng.uniform(0, 1, size=(m, 3)).astype(np.float32)
+    idx = rng.integers(0, m, size=n).astype(np.int64)
+    p_d, t_d, i_d = (torch.as_tensor(x, device="cuda") for x in (pred, tgt, idx))
+    _, ref_g = A.mse_loss(pred.astype(np.float64), tgt[idx].astype(np.float64))
+    _, g_loss = core.mse_loss(p_d, t_d, i_d)
+    ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    for s in (None, 3.0, -0.25, 1e-3):
+        sc = None if s is None else torch.tensor(s, dtype=torch.float64, device="cuda")
+        g = torch.empty_like(p_d)
+        L.check(L.load().dot_mse_grad(ptr(p_d), ptr(t_d), ptr(i_d), C.c_int64(n), ptr(sc), ptr(g), None))
+        torch.cuda.synchronize()
+        if s is None:
+            assert torch.equal(g, g_loss)
+        else:
+            np.testing.assert_allclose(g.cpu().numpy(), s * ref_g, rtol=6e-8, atol=0)
+    # through autograd: the upstream gradient of k * loss is k
+    x = p_d.clone().requires_grad_()
+    (2.5 * core.mse_loss_autograd(x, t_d, i_d)).backward()
+    np.testing.assert_allclose(x.grad.cpu().numpy(), 2.5 * ref_g, rtol=6e-8, atol=0)
+
+
 def _tile_shift(n, total):
     # documented rule: the smallest tile edge 2^s (8 <= 2^s <= 128) holding ~16 rays of the batch
     s = 3
