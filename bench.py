@@ -609,10 +609,12 @@ def train_step(torch, core, synth, args):
         p_sig, p_sh = sigma.detach().requires_grad_(), sh.detach().requires_grad_()     # alias the planes
         opt = None if dense else core.FusedAdam(tree)
         state = tree.adam_state() if dense else None
-        st = {"ws": None, "k": 0}
+        st = {"ws": None, "k": 0, "pb": None}
 
         def step():
-            cam, pix, ids, st["ws"] = core.pixel_batch(idx, W, H, len(views), st["ws"])
+            # the batch's buffers are kept from one step to the next, as the training driver keeps them
+            cam, pix, ids, st["ws"] = core.pixel_batch(idx, W, H, len(views), st["ws"], out=st["pb"])
+            st["pb"] = (cam, pix, ids)
             rays = core.Rays.pixels_device(cams_raw, len(views), cam, pix)
             if dense:
                 rgb = core.render_autograd(tree, p_sig, p_sh, rays)

@@ -44,6 +44,61 @@ void Alloc::put(void* p) const {
         (void)hipFree(p);
 }
 
+}  // namespace dot
+
+// A kept block serves a request on its stream when it is large enough and not
+// more than twice the request (or 64 KiB); a new block gets 1/8 headroom (requests that
+// vary from step to step, like the adjoint's rows, then reuse it).
+void* dot_tree::scratch_get(size_t bytes, hipStream_t s) const {
+    if (bytes == 0) bytes = 16;
+    size_t best = scratch_free.size();
+    for (size_t i = 0; i < scratch_free.size(); ++i) {
+        const ScratchBlock& b = scratch_free[i];
+        if (b.s == s && b.cap >= bytes && b.cap <= std::max<size_t>(2 * bytes, 1 << 16) &&
+            (best == scratch_free.size() || b.cap < scratch_free[best].cap))
+            best = i;
+    }
+    if (best < scratch_free.size()) {
+        const ScratchBlock b = scratch_free[best];
+        scratch_free.erase(scratch_free.begin() + (std::ptrdiff_t)best);
+        scratch_live.push_back(b);
+        return b.p;
+    }
+    const size_t cap = (bytes + bytes / 8 + 4095) & ~(size_t)4095;
+    void* p = alloc.get(cap);
+    if (!p) return nullptr;
+    scratch_live.push_back({p, cap, s});
+    return p;
+}
+
+void dot_tree::scratch_put(void* p, hipStream_t s) const {
+    if (!p) return;
+    for (size_t i = 0; i < scratch_live.size(); ++i) {
+        if (scratch_live[i].p != p) continue;
+        ScratchBlock b = scratch_live[i];
+        scratch_live.erase(scratch_live.begin() + (std::ptrdiff_t)i);
+        b.s = s;
+        scratch_free.push_back(b);
+        // drop the oldest kept blocks beyond the limit (stream order still
+        // covers them: the allocator's own reuse follows the caller's stream)
+        while (scratch_free.size() > kScratchKept) {
+            alloc.put(scratch_free.front().p);
+            scratch_free.erase(scratch_free.begin());
+        }
+        return;
+    }
+    alloc.put(p);   // not a scratch block
+}
+
+void dot_tree::scratch_clear() const {
+    for (const ScratchBlock& b : scratch_free) alloc.put(b.p);
+    for (const ScratchBlock& b : scratch_live) alloc.put(b.p);
+    scratch_free.clear();
+    scratch_live.clear();
+}
+
+namespace dot {
+
 // ---------------------------------------------------------------------------
 // host-side validation of the canonical tree; fills leaf depths
 // ---------------------------------------------------------------------------
@@ -177,6 +232,7 @@ static void release(dot_tree* t) {
     if (t->host_rb) (void)hipHostFree(t->host_rb);
     t->host_rb = nullptr;
     drop_notes(*t);
+    t->scratch_clear();
     t->child = nullptr;
     t->sigma = nullptr;
     t->sh = nullptr;

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -94,6 +96,21 @@ struct dot_tree {
     mutable FwdNote notes[kNotes];
     mutable uint32_t* note_words = nullptr;   // pinned [kNotes][2]: overflow, total
     mutable int note_next = 0;
+    // Scratch of the per-step calls (the adjoint's buckets and scans), kept
+    // for the next call on the same stream instead of going back to the
+    // allocator after every call (with a caller's allocator that is a call
+    // into the caller per block).  A block is reused only on the stream it was
+    // last used on, so stream order protects it; at most kScratchKept are kept.
+    struct ScratchBlock {
+        void* p;
+        size_t cap;
+        hipStream_t s;
+    };
+    static constexpr size_t kScratchKept = 12;
+    mutable std::vector<ScratchBlock> scratch_free, scratch_live;
+    void* scratch_get(size_t bytes, hipStream_t s) const;
+    void scratch_put(void* p, hipStream_t s) const;
+    void scratch_clear() const;
 
     dot::TreeView view() const {
         dot::TreeView v;

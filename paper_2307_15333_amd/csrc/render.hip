@@ -1212,20 +1212,20 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
     // all rows of a leaf's bucket, which feeds the scan.
     const bool replay = a.leaf_count && a.rec.a;
     const uint32_t* base0 = replay ? a.leaf_count : nullptr;
-    uint32_t* count_own = a.leaf_count ? nullptr : static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
-    uint32_t* total = a.leaf_count ? static_cast<uint32_t*>(t.alloc.get((size_t)L * 4)) : count_own;
+    uint32_t* count_own = a.leaf_count ? nullptr : static_cast<uint32_t*>(t.scratch_get((size_t)L * 4, s));
+    uint32_t* total = a.leaf_count ? static_cast<uint32_t*>(t.scratch_get((size_t)L * 4, s)) : count_own;
     const uint32_t* count = replay ? a.leaf_count + L : total;
-    uint32_t* offset = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
-    uint32_t* cursor = static_cast<uint32_t*>(t.alloc.get((size_t)L * 4));
-    uint32_t* bsum = static_cast<uint32_t*>(t.alloc.get((size_t)scan_scratch_elems(L) * 4));
-    uint32_t* tot = static_cast<uint32_t*>(t.alloc.get(16));
+    uint32_t* offset = static_cast<uint32_t*>(t.scratch_get((size_t)L * 4, s));
+    uint32_t* cursor = static_cast<uint32_t*>(t.scratch_get((size_t)L * 4, s));
+    uint32_t* bsum = static_cast<uint32_t*>(t.scratch_get((size_t)scan_scratch_elems(L) * 4, s));
+    uint32_t* tot = static_cast<uint32_t*>(t.scratch_get(16, s));
     auto drop = [&]() {
-        t.alloc.put(count_own);
-        if (a.leaf_count) t.alloc.put(total);
-        t.alloc.put(offset);
-        t.alloc.put(cursor);
-        t.alloc.put(bsum);
-        t.alloc.put(tot);
+        t.scratch_put(count_own, s);
+        if (a.leaf_count) t.scratch_put(total, s);
+        t.scratch_put(offset, s);
+        t.scratch_put(cursor, s);
+        t.scratch_put(bsum, s);
+        t.scratch_put(tot, s);
     };
     // Bucket offsets and the row total are 32-bit: a batch whose contributing
     // segments (at most max_steps per ray) could reach 2^32 takes the atomic
@@ -1278,7 +1278,7 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         return e;
     }
     float* rows = nullptr;
-    if ((double)m * rs * 4 <= kBucketBytesMax) rows = static_cast<float*>(t.alloc.get((size_t)std::max<uint32_t>(m, 1) * rs * 4));
+    if ((double)m * rs * 4 <= kBucketBytesMax) rows = static_cast<float*>(t.scratch_get((size_t)std::max<uint32_t>(m, 1) * rs * 4, s));
     if (!rows) {
         drop();
         return fused ? bwd_fused_dense(t, rb, a, grid, s) : bwd_atomic(t, rb, a, grid, s);
@@ -1333,7 +1333,7 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         default: hipLaunchKernelGGL(bwd_reduce_kernel<3>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
     }
     e = hipGetLastError();
-    t.alloc.put(rows);
+    t.scratch_put(rows, s);
     drop();
     return e;
 }

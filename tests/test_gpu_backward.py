@@ -391,6 +391,45 @@ def test_adjoint_takes_row_total_from_the_forward_that_recorded():
     tree.close()
 
 
+def test_adjoint_scratch_reused_across_calls_and_streams():
+    """The adjoint keeps its scratch blocks per tree for the next call on the
+    same stream: a sequence of batches of growing and shrinking size, on the
+    default stream and on a side stream, each equals the adjoint of a fresh
+    tree on the same batch."""
+    core = _core()
+    s = synth.random_tree_scene(5, 2, seed=111, p_split=0.5)
+    views = synth.random_sphere_cameras(5, 3.5, 24, 24, seed=112)
+    tree = core.Octree.from_scene(s)
+    Ln, K = tree.n_leaves, tree.K
+    side = torch.cuda.Stream()
+
+    def adjoint(tr, n, seed):
+        ci, pi = synth.pixel_batch(5, 24, 24, n, seed=seed)
+        rays = core.Rays.pixels(views, ci, pi)
+        rgb, ns = tr.render(rays, t_stop=0.0, nseg=True)
+        g = torch.as_tensor(np.random.default_rng(seed).normal(size=(n, 3)), dtype=torch.float32, device="cuda")
+        gs, gh = torch.zeros(Ln, device="cuda"), torch.zeros((Ln, 3, K), device="cuda")
+        tr.backward(rays, rgb, ns, g, gs, gh, t_stop=0.0)
+        return gs, gh
+
+    for k, (n, on_side) in enumerate(((1000, False), (2800, False), (300, False), (2800, True), (1500, True),
+                                      (2800, False))):
+        if on_side:
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                gs, gh = adjoint(tree, n, 120 + k)
+            torch.cuda.current_stream().wait_stream(side)
+        else:
+            gs, gh = adjoint(tree, n, 120 + k)
+        fresh = core.Octree.from_scene(s)
+        rs, rh = adjoint(fresh, n, 120 + k)
+        torch.cuda.synchronize()
+        fresh.close()
+        assert _rel(gs.cpu().numpy(), rs.cpu().numpy()) <= 1e-5, (n, on_side)
+        assert _rel(gh.cpu().numpy(), rh.cpu().numpy()) <= 1e-5, (n, on_side)
+    tree.close()
+
+
 def test_backward_counts_of_recording_forward_without_records():
     """A training forward that recorded, then an adjoint given its counts but
     not its records: every ray is re-traversed and each leaf's bucket holds
