@@ -268,6 +268,11 @@ inline void adam_bias_corrections(const dot_adam_params& p, float& bc1, float& b
 // needs scan_scratch_elems(n) elements
 int64_t scan_scratch_elems(int64_t n);
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s);
+// small arrays (one workgroup): exclusive scan of a + b into out and its total
+// into *tot, also c = a + b, z = 0 and *w_dst = *w_src (when w_src); false
+// (nothing launched) when n is too large for one workgroup
+bool scan_u32_sum2(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t* z, uint32_t* out, int64_t n,
+                   uint32_t* tot, const uint32_t* w_src, uint32_t* w_dst, hipStream_t s, hipError_t* err);
 hipError_t launch_rmsprop(const dot_tree& t, const float* gs, const float* gh, float* vs, float* vh,
                           const dot_rmsprop_params& p, hipStream_t s);
 hipError_t launch_sigma_signal(const dot_tree& t, float* out, hipStream_t s);

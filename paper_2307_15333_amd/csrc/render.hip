@@ -1244,12 +1244,18 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
             case DOT_F16: hipLaunchKernelGGL(bwd_count_kernel<DOT_F16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
             default: hipLaunchKernelGGL(bwd_count_kernel<DOT_BF16>, grid, dim3(BLOCK), 0, s, tv, rb, a, count_own); break;
         }
-    } else {
-        // tot[1] = the forward's overflow count (zero without records)
-        hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, a.leaf_count, a.leaf_count + L, total, cursor,
-                           L, a.rec.a ? a.rec.overflow : nullptr, tot + 1);
     }
-    hipError_t e = scan_u32(total, offset, L, bsum, tot, s);
+    hipError_t e = hipSuccess;
+    // tot[1] = the forward's overflow count (zero without records); small trees
+    // sum the two count regions, clear the cursors and scan in one launch
+    if (!a.leaf_count ||
+        !scan_u32_sum2(a.leaf_count, a.leaf_count + L, total, cursor, offset, L, tot, a.rec.a ? a.rec.overflow : nullptr,
+                       tot + 1, s, &e)) {
+        if (a.leaf_count)
+            hipLaunchKernelGGL(add_u32_kernel, dim3(fg), dim3(256), 0, s, a.leaf_count, a.leaf_count + L, total, cursor,
+                               L, a.rec.a ? a.rec.overflow : nullptr, tot + 1);
+        e = scan_u32(total, offset, L, bsum, tot, s);
+    }
     // The row total and the overflow count: from the note of the forward that
     // recorded (its copy, queued behind that forward, is waited for by its event:
     // the stream keeps running), else in one copy into pinned memory and one wait.

@@ -117,6 +117,21 @@ __device__ __forceinline__ void store_run(uint32_t* __restrict__ out, int64_t ba
     }
 }
 
+// a thread's SCAN_ITEMS consecutive values, stored as they are
+template <bool VEC>
+__device__ __forceinline__ void store_vals(uint32_t* __restrict__ out, int64_t base, int64_t n,
+                                           const uint32_t (&v)[SCAN_ITEMS]) {
+    if (VEC && base + SCAN_ITEMS <= n) {
+        uint4* p = reinterpret_cast<uint4*>(out + base);
+#pragma unroll
+        for (int q = 0; q < SCAN_ITEMS / 4; ++q) p[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j)
+            if (base + j < n) out[base + j] = v[j];
+    }
+}
+
 template <bool VEC>
 __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ bsum,
                              uint32_t* __restrict__ out) {
@@ -152,9 +167,51 @@ __global__ __launch_bounds__(SINGLE_TPB) void k_scan_single(const uint32_t* __re
     if (threadIdx.x == 0) *tot = carry;
 }
 
+// the same over a + b (a bucket's two count regions), also writing the sum
+// to c and zeroing z (the bucket cursors); the first thread copies *w_src to
+// *w_dst (a word the host may read back with the total)
+template <bool VEC>
+__global__ __launch_bounds__(SINGLE_TPB) void k_scan_single_sum2(const uint32_t* __restrict__ a,
+                                                                 const uint32_t* __restrict__ b, int64_t n,
+                                                                 uint32_t* __restrict__ c, uint32_t* __restrict__ z,
+                                                                 uint32_t* __restrict__ out, uint32_t* __restrict__ tot,
+                                                                 const uint32_t* __restrict__ w_src,
+                                                                 uint32_t* __restrict__ w_dst) {
+    if (w_src && threadIdx.x == 0) *w_dst = *w_src;
+    uint32_t carry = 0;
+    const uint32_t zero[SCAN_ITEMS] = {};
+    for (int64_t t0 = 0; t0 < n; t0 += SINGLE_TILE) {
+        const int64_t base = t0 + (int64_t)threadIdx.x * SCAN_ITEMS;
+        uint32_t v[SCAN_ITEMS], w[SCAN_ITEMS];
+        const uint32_t acc = load_run<VEC>(a, base, n, v) + load_run<VEC>(b, base, n, w);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) v[j] += w[j];
+        store_vals<VEC>(c, base, n, v);
+        store_vals<VEC>(z, base, n, zero);
+        uint32_t total;
+        const uint32_t off = block_exclusive_scan<SINGLE_TPB>(acc, total) + carry;
+        store_run<VEC>(out, base, n, v, off);
+        carry += total;
+    }
+    if (threadIdx.x == 0) *tot = carry;
+}
+
 }  // namespace
 
 int64_t scan_scratch_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+bool scan_u32_sum2(const uint32_t* a, const uint32_t* b, uint32_t* c, uint32_t* z, uint32_t* out, int64_t n,
+                   uint32_t* tot, const uint32_t* w_src, uint32_t* w_dst, hipStream_t s, hipError_t* err) {
+    if (n <= 0 || n > SCAN_SINGLE_MAX) return false;
+    const bool vec = ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c) |
+                       reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_scan_single_sum2<true>, dim3(1), dim3(SINGLE_TPB), 0, s, a, b, n, c, z, out, tot, w_src, w_dst);
+    else
+        hipLaunchKernelGGL(k_scan_single_sum2<false>, dim3(1), dim3(SINGLE_TPB), 0, s, a, b, n, c, z, out, tot, w_src, w_dst);
+    *err = hipGetLastError();
+    return true;
+}
 
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* bsum, uint32_t* tot, hipStream_t s) {
     if (n == 0) return hipSuccess;
