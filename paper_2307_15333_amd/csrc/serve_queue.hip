@@ -17,11 +17,14 @@
 // done for the job; the wave that completes a job's last tile writes the
 // job's number + 1 into the job's completion word in host memory.
 //
-// Why runs: the count that makes a wave's pixels visible to the other XCDs is
-// a release at device scope, which writes back the wave's whole L2.  One per
-// 64-ray tile capped the launch near half of what relaunching reaches; a run
-// of several tiles pays it once.  Runs are sized per job so that a job still
-// spreads over about all the waves of the chip.
+// Publication without L2 writebacks: a release at device scope writes back
+// the issuing XCD's whole L2, and one per 64-ray tile capped the launch near
+// half of what relaunching reaches.  The pixels are instead written with
+// device-scope (written-through) stores, and a wave waits for its stores to
+// complete before it counts the tiles done; only the job's last tile issues a
+// release (system scope, for the host).  Runs of several tiles save claims: a
+// lone job is cut into about four runs per wave (its tail, the last round of
+// runs, stays short); under load, runs grow to kMaxRun tiles.
 //
 // Polls are device-coherent loads, served beyond the L2; waves that find no
 // work back off (up to about 13 us between polls) so that thousands of idle
@@ -58,7 +61,7 @@ constexpr int kRings = 8;                               // one tile ring per XCD
 constexpr uint64_t kRing = 1ull << 18;                  // entries (runs) per ring
 constexpr uint64_t kMaxOpenTiles = 1ull << 19;          // tiles of unfinished jobs (all rings)
 constexpr int64_t kMaxRun = 8;                          // tiles per ring entry, at most
-constexpr int64_t kRunSpread = 2048;                    // a job is cut into at least this many runs
+constexpr int64_t kMinRun = 1;                          // tiles per ring entry, at least
 constexpr uint64_t kStopBit = 1ull << 63;               // in a ring's published count: no entry will follow
 constexpr int kMaxNaps = 4;                             // idle backoff: up to 4 x 127 x 64 clocks between polls
 constexpr int kSlotShift = 40;                          // entry: slot << 40 | run << 20 | first tile
@@ -124,10 +127,10 @@ __device__ __forceinline__ uint64_t poll_dev(const uint64_t* p) {
 // chunks, chunk x going to ring (seq + x) mod kRings, so every XCD renders a
 // contiguous part of every image (its L2 then holds neighbouring tiles) and
 // jobs of one tile still spread over the XCDs; each chunk is cut into runs of
-// `run` tiles (the last one shorter): the job's tile count / kRunSpread,
-// clamped to 1..kMaxRun, so a job still spreads over about all the waves.
+// `run` tiles (the last one shorter), sized from the chunk and the waves of
+// an XCD and lengthened while entries wait unclaimed.
 __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevice& dv, int max_jobs,
-                       uint64_t t0, uint64_t limit_ticks) {
+                       uint64_t t0, uint64_t limit_ticks, int64_t workers) {
     const int lane = threadIdx.x & (WAVE - 1);
     uint64_t copied = 0;
     uint64_t tail[kRings] = {};
@@ -146,8 +149,16 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
             // the host validated the range; a record read wrong must still not run away
             count = count < 0 ? 0 : (count > kMaxImageTiles ? kMaxImageTiles : count);
             const int64_t chunk = (count + kRings - 1) / kRings;
-            const int64_t run0 = count / kRunSpread;
-            const int64_t run = run0 < 1 ? 1 : (run0 > kMaxRun ? kMaxRun : run0);
+            // run length: about a quarter of the chunk's share per wave of the
+            // XCD (so a lone job's tail is a fraction of its time), and longer
+            // as entries wait unclaimed (pend: published minus claimed, over
+            // all rings; negative while waves wait), which saves claims
+            int64_t pend = 0;
+            for (int r = 0; r < kRings; ++r) pend += (int64_t)(tail[r] - uniform64(poll_dev(&dv.next[r].v)));
+            const int64_t ring_waves = workers / kRings > 0 ? workers / kRings : 1;
+            int64_t run = chunk / (4 * ring_waves);
+            if (pend > 0) run += pend * kMaxRun / (workers > 0 ? workers : 1);
+            run = run < kMinRun ? kMinRun : (run > kMaxRun ? kMaxRun : run);
 #pragma unroll
             for (int x = 0; x < kRings; ++x) {
                 const int r = (int)((copied + (uint64_t)x) % kRings);
@@ -215,10 +226,12 @@ __device__ __forceinline__ void serve_tile(const ServeJob& j, int64_t t, int lan
     sh_basis<DEG>((float)r.dx, (float)r.dy, (float)r.dz, seg.Y);
     int desc = 0;
     traverse(j.tv, r, stk, seg, desc);
+    // device-scope stores: written through to where every XCD (and a copy
+    // engine) sees them, so completing them is all the publication needs
     float* o = j.rgb + 3 * ((int64_t)v * j.width + u);
-    o[0] = fmaf(seg.T, j.bg[0], seg.C[0]);
-    o[1] = fmaf(seg.T, j.bg[1], seg.C[1]);
-    o[2] = fmaf(seg.T, j.bg[2], seg.C[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        __hip_atomic_store(o + c, fmaf(seg.T, j.bg[c], seg.C[c]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int DT>
@@ -229,7 +242,7 @@ __global__ __launch_bounds__(BLOCK) void serve_loop_kernel(ServeHostCtl* ctl, co
     const int lane = tid & (WAVE - 1);
     const uint64_t t0 = wall_clock64();
     if (blockIdx.x == 0) {
-        if ((tid >> 6) == 0) feeder(ctl, hjobs, dv, max_jobs, t0, limit_ticks);
+        if ((tid >> 6) == 0) feeder(ctl, hjobs, dv, max_jobs, t0, limit_ticks, (int64_t)(gridDim.x - 1) * (BLOCK / WAVE));
         return;
     }
     // workgroups are dispatched round-robin over the XCDs: this one takes its
@@ -277,10 +290,16 @@ __global__ __launch_bounds__(BLOCK) void serve_loop_kernel(ServeHostCtl* ctl, co
         }
         ++tile;
         if (--left > 0) continue;
-        // the run's pixels before its count (one release per run); the job's
-        // last tile publishes the job to the host
+        // the run's pixels before its count: they are device-coherent stores,
+        // so waiting for this wave's stores to complete orders them before the
+        // count (a release here would also write back the XCD's whole L2,
+        // which bounded the launch); the job's last tile publishes the job to
+        // the host with a system-scope release
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (lane == 0) {
-            const uint32_t c = __hip_atomic_fetch_add(&dv.done[slot], (uint32_t)len, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + (uint32_t)len;
+            const uint32_t c = __hip_atomic_fetch_add(&dv.done[slot], (uint32_t)len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + (uint32_t)len;
             if ((int64_t)c == j.tile_count) {
                 __hip_atomic_store(&dv.done[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __atomic_thread_fence(__ATOMIC_SEQ_CST);

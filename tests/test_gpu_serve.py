@@ -228,6 +228,50 @@ def test_persistent_queue_alone_equals_mix(trees):
         np.testing.assert_allclose(o.cpu().numpy(), ref[r.rid], atol=1e-6, rtol=0)
 
 
+def test_persistent_results_readable_while_the_launch_runs(trees):
+    """A job's image is complete and visible to other device work as soon as
+    its completion word says so, while the launch keeps running: each image
+    is copied out on a side stream right after its job completes (jobs pushed
+    one at a time and in bursts, poisoned outputs first) and equals the image
+    dot_render gives."""
+    core, serve = _mods()
+    scenes, ts = trees
+    sizes = ((128, 96), (256, 256), (64, 64), (333, 251), (200, 120), (96, 160), (512, 384), (8, 8))
+    reqs = [_req(serve, i, i % 4, w, h, 37.0 * i, 25.0 - 7.0 * i) for i, (w, h) in enumerate(sizes)]
+    ref = _reference_images(core, ts, reqs)
+    outs = [torch.full((r.height, r.width, 3), -7.0, device="cuda") for r in reqs]
+    hosts = [torch.empty((r.height, r.width, 3), pin_memory=True) for r in reqs]
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    q = serve.Queue("f16", max_jobs=32, max_seconds=20.0)
+
+    def read(i):
+        with torch.cuda.stream(side):
+            hosts[i].copy_(outs[i], non_blocking=True)
+        side.synchronize()
+        np.testing.assert_allclose(hosts[i].numpy(), ref[reqs[i].rid], atol=1e-6, rtol=0)
+
+    try:
+        for i in range(3):                       # one at a time
+            r = reqs[i]
+            q.wait(q.push(ts[r.tree], r.cam, outs[i], r.width, r.height))
+            read(i)
+        burst = {}
+        for i in range(3, len(reqs)):            # a burst, read as each completes
+            r = reqs[i]
+            burst[i] = q.push(ts[r.tree], r.cam, outs[i], r.width, r.height)
+        import time
+        t0 = time.perf_counter()
+        while burst:
+            assert time.perf_counter() - t0 < 10.0, f"jobs {sorted(burst)} not done"
+            for i, tk in list(burst.items()):
+                if q.done(tk):
+                    read(i)
+                    del burst[i]
+    finally:
+        q.close()
+
+
 def test_persistent_queue_limits_and_time_limit(trees):
     """A queue refuses a tree of another storage type and a tile range outside
     the image; it reports a full queue (2^19 tiles of unfinished jobs) without
