@@ -4,11 +4,12 @@
 // Host -> device: jobs are written into a ring of records in pinned,
 // host-coherent memory and published by a counter.  One wave of the launch
 // (workgroup 0, wave 0: the "feeder") polls that counter, copies each newly
-// published job into a device job table and writes its work items into the
-// tile rings, one ring per XCD, each receiving a contiguous eighth of the
-// job's tiles.  An item is a run of up to kMaxRun consecutive 8x8 tiles of one
-// job (job slot, first tile index in the image, run length in one 64-bit
-// entry); then the feeder advances the rings' published item counts `tail`.
+// published job into a device job table and schedules its work items into
+// the tile rings, one ring per XCD, each receiving a contiguous eighth of the
+// job's tiles, a share at a time beside the other jobs in flight.  An item is
+// a run of up to kMaxRun consecutive 8x8 tiles of one job (job slot, first
+// tile index in the image, run length in one 64-bit entry); the feeder
+// advances the rings' published item counts `tail`.
 //
 // Workers (every other workgroup): a wave claims the next item of its XCD's
 // ring with an atomic on that ring's `next`, waits until the feeder has
@@ -22,9 +23,9 @@
 // half of what relaunching reaches.  The pixels are instead written with
 // device-scope (written-through) stores, and a wave waits for its stores to
 // complete before it counts the tiles done; only the job's last tile issues a
-// release (system scope, for the host).  Runs of several tiles save claims: a
-// lone job is cut into about four runs per wave (its tail, the last round of
-// runs, stays short); under load, runs grow to kMaxRun tiles.
+// release (system scope, for the host).  Runs of several tiles save claims:
+// a job is cut into about four runs per wave of an XCD (a lone job's tail, its
+// last round of runs, stays short).
 //
 // Polls are device-coherent loads, served beyond the L2; waves that find no
 // work back off (up to about 13 us between polls) so that thousands of idle
@@ -123,70 +124,144 @@ __device__ __forceinline__ uint64_t poll_dev(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// the feeder: one wave.  A job's tiles are cut into kRings contiguous
-// chunks, chunk x going to ring (seq + x) mod kRings, so every XCD renders a
-// contiguous part of every image (its L2 then holds neighbouring tiles) and
-// jobs of one tile still spread over the XCDs; each chunk is cut into runs of
-// `run` tiles (the last one shorter), sized from the chunk and the waves of
-// an XCD and lengthened while entries wait unclaimed.
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// exclusive prefix sum over the wave's lanes, and the wave's total
+__device__ __forceinline__ int64_t wave_excl_sum(int64_t v, int lane, int64_t& total) {
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, WAVE);
+        if (lane >= o) x += y;
+    }
+    total = readlane64(x, WAVE - 1);
+    return x - v;
+}
+
+// tiles of chunk x of a job of `count` tiles cut into chunks of `chunk`
+__device__ __forceinline__ int64_t chunk_len(int64_t count, int64_t chunk, int x) {
+    const int64_t a = (int64_t)x * chunk;
+    return a >= count ? 0 : (count - a < chunk ? count - a : chunk);
+}
+
+// The feeder: one wave, and a scheduler.  Each lane holds one job being
+// published (up to 64 at once, admitted in order); the job's tiles are cut
+// into kRings contiguous chunks, chunk x going to the ring of XCD
+// (job number + x) mod kRings, so every XCD renders a contiguous part of every
+// image (its L2 then holds neighbouring tiles), and each chunk into runs of
+// `run` tiles.  A ring is topped up only when fewer entries wait in it than
+// the XCD has waves, to twice that, the room shared evenly among the jobs that
+// still have tiles for it: a request that arrives behind a large one starts
+// after about two rounds of entries instead of after the whole large image.
+// `cur` (LDS, [64][kRings]): tiles of each of the lane's chunks published.
 __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevice& dv, int max_jobs,
-                       uint64_t t0, uint64_t limit_ticks, int64_t workers) {
+                       uint64_t t0, uint64_t limit_ticks, int64_t workers, int* cur_lds) {
     const int lane = threadIdx.x & (WAVE - 1);
+    int* cur = cur_lds + lane * kRings;
+    const int64_t ring_waves = workers / kRings > 0 ? workers / kRings : 1;
+    const int64_t low = ring_waves, high = 2 * ring_waves;
     uint64_t copied = 0;
     uint64_t tail[kRings] = {};
+    int slot = -1, ring0 = 0;              // this lane's job (slot < 0: none)
+    int64_t begin = 0, count = 0, chunk = 0, run = 1;
     for (;;) {
-        bool late = wall_clock64() - t0 > limit_ticks;
+        const bool late = wall_clock64() - t0 > limit_ticks;
+        bool moved = false;
+        // admit published jobs while a lane is free: copy the record into the
+        // device table, and the free lane takes the job
         const uint64_t pub = uniform64(poll_sys(&ctl->published));
         while (copied < pub && !late) {
-            const int slot = (int)(copied % (uint64_t)max_jobs);
-            const uint32_t* src = reinterpret_cast<const uint32_t*>(hjobs + slot);
-            uint32_t* dst = reinterpret_cast<uint32_t*>(dv.jobs + slot);
+            const uint64_t free_lanes = __ballot(slot < 0);
+            if (free_lanes == 0) break;
+            const int fl = __ffsll((unsigned long long)free_lanes) - 1;
+            const int js = (int)(copied % (uint64_t)max_jobs);
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(hjobs + js);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(dv.jobs + js);
             for (int w = lane; w < kJobWords; w += WAVE)
                 __hip_atomic_store(dst + w, __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int64_t begin = (int64_t)uniform64(poll_sys(reinterpret_cast<const uint64_t*>(&hjobs[slot].tile_begin)));
-            int64_t count = (int64_t)uniform64(poll_sys(reinterpret_cast<const uint64_t*>(&hjobs[slot].tile_count)));
+            const int64_t b0 = (int64_t)uniform64(poll_sys(reinterpret_cast<const uint64_t*>(&hjobs[js].tile_begin)));
+            int64_t c0 = (int64_t)uniform64(poll_sys(reinterpret_cast<const uint64_t*>(&hjobs[js].tile_count)));
             // the host validated the range; a record read wrong must still not run away
-            count = count < 0 ? 0 : (count > kMaxImageTiles ? kMaxImageTiles : count);
-            const int64_t chunk = (count + kRings - 1) / kRings;
-            // run length: about a quarter of the chunk's share per wave of the
-            // XCD (so a lone job's tail is a fraction of its time), and longer
-            // as entries wait unclaimed (pend: published minus claimed, over
-            // all rings; negative while waves wait), which saves claims
-            int64_t pend = 0;
-            for (int r = 0; r < kRings; ++r) pend += (int64_t)(tail[r] - uniform64(poll_dev(&dv.next[r].v)));
-            const int64_t ring_waves = workers / kRings > 0 ? workers / kRings : 1;
-            int64_t run = chunk / (4 * ring_waves);
-            if (pend > 0) run += pend * kMaxRun / (workers > 0 ? workers : 1);
-            run = run < kMinRun ? kMinRun : (run > kMaxRun ? kMaxRun : run);
-#pragma unroll
-            for (int x = 0; x < kRings; ++x) {
-                const int r = (int)((copied + (uint64_t)x) % kRings);
-                const int64_t a = (int64_t)x * chunk;
-                const int64_t n = a < count ? (count - a < chunk ? count - a : chunk) : 0;
-                const int64_t items = (n + run - 1) / run;
-                uint64_t* ring = dv.ring + (uint64_t)r * kRing;
-                for (int64_t i = lane; i < items; i += WAVE) {
-                    const int64_t first = i * run;
-                    const int64_t len = n - first < run ? n - first : run;
-                    const uint64_t e = ((uint64_t)slot << kSlotShift) | ((uint64_t)len << kTileBits) |
-                                       ((uint64_t)(begin + a + first) & kTileMask);
-                    __hip_atomic_store(&ring[(tail[r] + (uint64_t)i) & (kRing - 1)], e, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                }
-                tail[r] += (uint64_t)items;
+            c0 = c0 < 0 ? 0 : (c0 > kMaxImageTiles ? kMaxImageTiles : c0);
+            if (lane == fl) {
+                slot = js;
+                ring0 = (int)(copied % kRings);
+                begin = b0;
+                count = c0;
+                chunk = (c0 + kRings - 1) / kRings;
+                // about four runs per wave of the XCD for a lone job, so that
+                // its last round of runs is short
+                run = chunk / (4 * ring_waves);
+                run = run < kMinRun ? kMinRun : (run > kMaxRun ? kMaxRun : run);
+                for (int x = 0; x < kRings; ++x) cur[x] = 0;
             }
             ++copied;
-            // the job record and its entries before the counts that cover them:
+            moved = true;
+        }
+        // the claim counters of the 8 rings, read in parallel
+        const int64_t nx = lane < kRings ? (int64_t)poll_dev(&dv.next[lane].v) : 0;
+#pragma unroll
+        for (int r = 0; r < kRings; ++r) {
+            int64_t backlog = (int64_t)(tail[r] - (uint64_t)readlane64(nx, r));
+            if (backlog >= low) continue;
+            const int x = (r - ring0) & (kRings - 1);       // this lane's chunk for ring r
+            const int64_t len_x = slot < 0 ? 0 : chunk_len(count, chunk, x);
+            int64_t done_x = slot < 0 ? 0 : cur[x];
+            const int64_t base = begin + (int64_t)x * chunk;
+            for (int round = 0; round < 4 && backlog < high; ++round) {
+                const int64_t left = (len_x - done_x + run - 1) / run;     // entries this lane still has
+                const uint64_t act = __ballot(left > 0);
+                if (act == 0) break;
+                const int64_t nact = __popcll(act);
+                const int64_t share = (high - backlog + nact - 1) / nact;
+                const int64_t n = left < share ? left : share;
+                int64_t total = 0;
+                const int64_t off = wave_excl_sum(n, lane, total);
+                // the entries of each job in turn, written by the whole wave
+                uint64_t* ring = dv.ring + (uint64_t)r * kRing;
+                for (uint64_t m = act; m; m &= m - 1) {
+                    const int j = __ffsll((unsigned long long)m) - 1;
+                    const int64_t nj = readlane64(n, j), oj = readlane64(off, j), dj = readlane64(done_x, j);
+                    const int64_t lj = readlane64(len_x, j), bj = readlane64(base, j), rj = readlane64(run, j);
+                    const uint64_t sj = (uint64_t)__builtin_amdgcn_readlane(slot, j);
+                    for (int64_t i = lane; i < nj; i += WAVE) {
+                        const int64_t f = dj + i * rj;
+                        const int64_t len = lj - f < rj ? lj - f : rj;
+                        const uint64_t e = (sj << kSlotShift) | ((uint64_t)len << kTileBits) | ((uint64_t)(bj + f) & kTileMask);
+                        __hip_atomic_store(&ring[(tail[r] + (uint64_t)(oj + i)) & (kRing - 1)], e, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                done_x += n * run;
+                if (done_x > len_x) done_x = len_x;
+                tail[r] += (uint64_t)total;
+                backlog += total;
+                moved = true;
+            }
+            if (slot >= 0) cur[x] = (int)done_x;
+        }
+        // a lane whose job is published in full is free for the next one
+        if (slot >= 0) {
+            bool all = true;
+            for (int x = 0; x < kRings; ++x) all = all && cur[x] >= chunk_len(count, chunk, x);
+            if (all) slot = -1;
+        }
+        if (moved) {
+            // the job records and entries before the counts that cover them:
             // one release fence, then the eight counts
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (lane == 0)
                 for (int r = 0; r < kRings; ++r)
                     __hip_atomic_store(&dv.tail[r].v, tail[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            late = wall_clock64() - t0 > limit_ticks;
         }
         const bool stop = __builtin_amdgcn_readfirstlane(poll_sys32(&ctl->stop)) != 0u;
-        if ((stop && copied == uniform64(poll_sys(&ctl->published))) || late) {
+        const bool drained = __ballot(slot >= 0) == 0 && copied == uniform64(poll_sys(&ctl->published));
+        if ((stop && drained) || late) {
             if (lane == 0) {
                 for (int r = 0; r < kRings; ++r)
                     __hip_atomic_store(&dv.tail[r].v, tail[r] | kStopBit, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -195,7 +270,7 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
             }
             return;
         }
-        __builtin_amdgcn_s_sleep(32);
+        if (!moved) __builtin_amdgcn_s_sleep(32);
     }
 }
 
@@ -237,12 +312,14 @@ __device__ __forceinline__ void serve_tile(const ServeJob& j, int64_t t, int lan
 template <int DT>
 __global__ __launch_bounds__(BLOCK) void serve_loop_kernel(ServeHostCtl* ctl, const ServeJob* hjobs, uint64_t* hdone,
                                                            ServeDevice dv, int max_jobs, uint64_t limit_ticks) {
-    __shared__ int stack_lds[LAT * BLOCK];
+    __shared__ int stack_lds[LAT * BLOCK];   // the walk's ancestor stacks; the feeder's chunk cursors
+    static_assert(LAT * BLOCK >= WAVE * kRings, "feeder cursors fit in the stack array");
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const uint64_t t0 = wall_clock64();
     if (blockIdx.x == 0) {
-        if ((tid >> 6) == 0) feeder(ctl, hjobs, dv, max_jobs, t0, limit_ticks, (int64_t)(gridDim.x - 1) * (BLOCK / WAVE));
+        if ((tid >> 6) == 0)
+            feeder(ctl, hjobs, dv, max_jobs, t0, limit_ticks, (int64_t)(gridDim.x - 1) * (BLOCK / WAVE), stack_lds);
         return;
     }
     // workgroups are dispatched round-robin over the XCDs: this one takes its
