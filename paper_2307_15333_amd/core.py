@@ -518,7 +518,7 @@ class MSELoss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_loss):
         pred, target, target_idx = ctx.saved_tensors
-        scale = grad_loss.detach().to(torch.float64).contiguous()
+        scale = grad_loss if grad_loss.dtype == torch.float64 else grad_loss.to(torch.float64)   # one element
         g = torch.empty_like(pred)
         L.check(L.load().dot_mse_grad(_ptr(pred), _ptr(target), _ptr(target_idx), C.c_int64(pred.shape[0]),
                                       _ptr(scale), _ptr(g), _stream()))
