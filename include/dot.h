@@ -72,8 +72,13 @@ enum { DOT_SIGNAL_MAX = 0, DOT_SIGNAL_SUM = 1 };
 typedef struct dot_tree *dot_tree_t;
 
 /* Device-memory allocator used for every allocation a tree makes (its planes,
- * refinement scratch, upload staging).  NULL = hipMalloc/hipFree.  alloc
- * returns NULL on failure (the call then fails with DOT_ENOMEM). */
+ * refinement scratch, upload staging, the adjoint's buckets).  NULL =
+ * hipMalloc/hipFree.  alloc returns NULL on failure (the call then fails with
+ * DOT_ENOMEM).  A block may be freed while work queued on the call's stream
+ * still uses it (stream-ordered reuse, as a caching allocator on that stream
+ * provides); the adjoint's scratch is kept by the tree between calls on one
+ * stream and only goes back to the allocator beyond a small number of blocks
+ * or at dot_free. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *ctx);
     void (*free)(void *ptr, void *ctx);
@@ -249,10 +254,16 @@ int dot_accumulate_signal(dot_tree_t tree, const dot_rays *rays, const dot_rende
  *  compact gradient row -- dsigma, g_ch w c_ch (1 - c_ch) and the ray
  *  direction -- into its leaf's bucket, then per-leaf sums that expand the SH
  *  outer product), which needs device scratch of 32 B (16 B at degree 0) per
- *  contributing segment from the tree's allocator and synchronises `stream`
- *  once to size it (the size is read back through a 16-byte pinned host
- *  buffer the tree allocates on first use and keeps until dot_free, so the
- *  adjoints of one tree must not run concurrently); beyond 8 GiB of
+ *  contributing segment from the tree's allocator.  Sizing it needs the
+ *  batch's row total on the host: with the records of a dot_render_train call
+ *  that recorded (matched by its records and counts buffers, among the tree's
+ *  last four such calls) the call waits only for that forward's copy of its
+ *  row total, queued behind it; otherwise it synchronises `stream` once after
+ *  its own scan (the words come back through pinned host buffers the tree
+ *  allocates on first use and keeps until dot_free).  Scratch blocks return
+ *  to a per-tree cache for the next call on the same stream (at most twelve
+ *  blocks, freed through the allocator beyond that and at dot_free), so the
+ *  adjoints of one tree must not run concurrently; beyond 8 GiB of
  *  scratch, or if it cannot be allocated, the terms go straight to the
  *  arrays with FP32 atomics; the same happens when n_rays times the tree's
  *  bound on segments per ray (3 * 2^max_depth + 64) reaches 2^32, since
@@ -557,9 +568,13 @@ int dot_render_jobs(const dot_render_job *jobs, int32_t n_jobs, void *workspace,
  * the tiles of all admitted requests are rendered by the same resident waves.
  * The host writes each job into a ring in pinned, host-coherent memory and
  * publishes it with a counter; one wave of the launch copies published jobs
- * into device memory and hands their tiles to the other waves through a tile
- * ring; the wave that renders a job's last tile writes the job's completion
- * word back to host memory.  Every pixel is computed by the same per-ray code
+ * into device memory and schedules their tiles onto one tile ring per XCD, a
+ * share at a time beside the other jobs in flight (so a small request is not
+ * queued behind every tile of a large one); the wave that renders a job's
+ * last tile writes the job's completion word back to host memory, after the
+ * job's pixels are visible to other device work (a copy on another stream may
+ * read the image as soon as dot_serve_done reports it, while the launch runs).
+ * Every pixel is computed by the same per-ray code
  * as dot_render (Eq. 1-2), so a job's image does not depend on what else is
  * queued.  One queue serves trees of one storage type (the launch carries that
  * type's registers), at most `max_jobs` jobs in flight and 2^19 tiles of
@@ -604,7 +619,8 @@ int dot_serve_push(dot_serve_t q, const dot_serve_job *job, int64_t *ticket);
 
 /*
  * dot_serve_done -- 1 when job `ticket` has been rendered (its rgb_out is
- *  complete and visible to later device work), 0 while it is pending.
+ *  complete and visible to device work issued after this call, on any stream,
+ *  also while the launch keeps running), 0 while it is pending.
  *  Errors: DOT_EINVAL for an unknown ticket; DOT_EHIP when the launch ended
  *  before the job completed.
  */
