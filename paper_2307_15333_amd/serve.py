@@ -322,8 +322,10 @@ class PersistentServer:
         HBM budget, allocated before the launch and reused once a request has
         completed (no allocator call while the launch holds the GPU); with
         keep_outputs each request gets its own buffer instead, allocated before
-        the launch starts and valid after run() returns.  on_complete(r) is called on the host when r completes; it must
-        not issue device work, which would wait for the launch."""
+        the launch starts and valid after run() returns.  on_complete(r) is called on the host when r completes:
+        r.out is then whole and may be read by device work on a stream other than the queue's (a copy into host
+        memory, say; work on the queue's stream would wait for the launch to end).  With the arena that work must
+        have finished when on_complete returns, since r's region is then reused."""
         arena = None if keep_outputs else torch.empty(self.budget, dtype=torch.uint8, device=self.device)
         if keep_outputs:
             # every request's own output, allocated before the launch holds the GPU
