@@ -194,6 +194,7 @@ def main():
     traffic = read_traffic()
     tb = None if traffic is None else traffic["hbm_bytes_per_launch"]
     achievable = stream_read_gbps(torch, L, lib)
+    gather = gather_rows_gbps(torch, L, lib)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
                 "kernel": "render_fwd_kernel<F32,deg3> (plain render, no signal)", "kernel_ms": round(kt * 1e3, 4),
@@ -213,7 +214,9 @@ def main():
                 "cache_inclusive_units": {"segments": stats["segments"], "sh_fetches": stats["sh_fetches"]},
                 "other_bytes_per_launch": {"child_and_link_reads": stats["index_reads"] * 4, "rgb": n_rays * 12,
                                            "total": int(other)},
-                "achievable_read_GBps": round(achievable, 1)}
+                "achievable_read_GBps": round(achievable, 1),
+                "achievable_gather_rows": gather,
+                "traffic_over_gather_ceiling": None if tb is None else round(tb / kt / 1e9 / gather["line_GBps"], 3)}
     log(f"render kernel {kt * 1e3:.3f} ms; compulsory {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM "
         f"peak); cache-inclusive leaf bytes {leaf_bytes / kt / 1e9:.1f} GB/s; segments/ray "
         f"{stats['segments'] / n_rays:.2f}")
@@ -264,6 +267,34 @@ def stream_read_gbps(torch, L, lib):
     gbps = nbytes / kt / 1e9
     log(f"stream read: {gbps:.1f} GB/s achievable ({gbps / HBM_PEAK_GBS:.1%} of the 8 TB/s peak)")
     return gbps
+
+
+def gather_rows_gbps(torch, L, lib):
+    """The leaf-fetch pattern without its dependences: dot_gather_rows reads
+    16M random 192-byte rows (each lane a whole row) of a 3 GiB buffer; a row
+    at a 192-byte stride spans exactly two 128-byte lines."""
+    import ctypes as C
+    from paper_2307_15333_amd import core
+    n_rows = 1 << 24
+    buf = torch.empty(n_rows * 192, dtype=torch.uint8, device="cuda")
+    buf.fill_(1)
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    threads = cus * 4 * 256
+    reads = max(1, n_rows // threads) * threads          # what the launch reads (a whole number per thread)
+
+    def fn():
+        L.check(lib.dot_gather_rows(C.c_void_p(buf.data_ptr()), C.c_int64(n_rows), C.c_int64(n_rows),
+                                    C.c_void_p(sink.data_ptr()), core._stream()))
+
+    kt = time_kernel(fn, 10, torch)
+    del buf
+    out = {"rows_per_s_G": round(reads / kt / 1e9, 2), "row_GBps": round(reads * 192 / kt / 1e9, 1),
+           "line_GBps": round(reads * 256 / kt / 1e9, 1),
+           "note": "random 192 B rows, one per lane per step, over 3 GiB (2 lines of 128 B per row)"}
+    log(f"gather rows: {out['rows_per_s_G']} G rows/s = {out['row_GBps']} GB/s of row bytes, "
+        f"{out['line_GBps']} GB/s of lines")
+    return out
 
 
 def fused_signal_forms(torch, tree, rays, signal, rgb, fused_step, args):

@@ -645,6 +645,21 @@ int dot_serve_close(dot_serve_t q);
  */
 int dot_stream_read(const void *buf, size_t bytes, float *sink, void *stream);
 
+/*
+ * dot_gather_rows -- support kernel, not part of the method: reads about
+ *  `reads` rows of 192 bytes (the FP32 SH row of a leaf), each lane a whole
+ *  row per step, at positions spread over the first n_rows rows of the DEVICE
+ *  buffer `buf` by a 64-bit mixing hash; the achievable rate of the
+ *  renderer's leaf-fetch pattern without its dependences (the ceiling beside
+ *  dot_stream_read's).  The number of rows read is rounded to a multiple of
+ *  the launch's threads (at least one per thread); the caller times the call.
+ *  buf: DEVICE, at least n_rows * 192 bytes, 16-byte aligned; n_rows a power
+ *  of two; sink: DEVICE float, receives a value only to keep the loads live.
+ *  Errors: DOT_EINVAL on a NULL or unaligned buffer or n_rows not a power of
+ *  two.
+ */
+int dot_gather_rows(const void *buf, int64_t n_rows, int64_t reads, float *sink, void *stream);
+
 /* dot_last_error -- message of the last failure on this thread ("" if none). */
 const char *dot_last_error(void);
 

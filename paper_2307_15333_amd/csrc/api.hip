@@ -11,6 +11,9 @@
 
 namespace dot {
 
+// the gather probe's launcher (probe.hip)
+hipError_t launch_gather_rows(const void* buf, int64_t n_rows_pow2, int64_t reads, float* sink, hipStream_t s);
+
 static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
@@ -817,6 +820,15 @@ int dot_stream_read(const void* buf, size_t bytes, float* sink, void* stream) {
     if (reinterpret_cast<uintptr_t>(buf) % 16 != 0) return fail(DOT_EINVAL, "dot_stream_read: buffer not 16-byte aligned");
     hipError_t e = launch_stream_read(buf, bytes, sink, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_stream_read: launch");
+    return DOT_OK;
+}
+
+int dot_gather_rows(const void* buf, int64_t n_rows, int64_t reads, float* sink, void* stream) {
+    if (n_rows <= 0 || (n_rows & (n_rows - 1)) != 0) return fail(DOT_EINVAL, "dot_gather_rows: n_rows must be a power of two");
+    if (!buf || !sink) return fail(DOT_EINVAL, "dot_gather_rows: NULL buffer or sink");
+    if (reinterpret_cast<uintptr_t>(buf) % 16 != 0) return fail(DOT_EINVAL, "dot_gather_rows: buffer not 16-byte aligned");
+    const hipError_t e = dot::launch_gather_rows(buf, n_rows, reads, sink, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_gather_rows: launch");
     return DOT_OK;
 }
 

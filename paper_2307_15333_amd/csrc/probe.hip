@@ -35,7 +35,51 @@ __global__ __launch_bounds__(256) void k_stream_read(const v4u* __restrict__ p, 
     if ((threadIdx.x & 63) == 0 && acc == 0x7fc00001u) atomicAdd(sink, 1.f);   // practically never taken
 }
 
+// Gather probe: every lane reads whole 192-byte rows (twelve 16-byte loads,
+// the FP32 SH row of a leaf) at positions spread over the buffer by a 64-bit
+// mixing function (the splitmix64 finalizer of Steele, Lea and Flood), the
+// access pattern of the renderer's leaf fetches without its dependences.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(const v4u* __restrict__ p, uint64_t row_mask, int64_t trips,
+                                                    float* __restrict__ sink) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (int64_t t = 0; t < trips; ++t) {
+        const uint64_t r = mix64(tid * (uint64_t)trips + (uint64_t)t) & row_mask;
+        v4u v[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) v[q] = p[r * 12 + q];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) acc ^= v[q].x ^ v[q].y ^ v[q].z ^ v[q].w;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0 && acc == 0x7fc00001u) atomicAdd(sink, 1.f);   // practically never taken
+}
+
 }  // namespace
+
+hipError_t launch_gather_rows(const void* buf, int64_t n_rows_pow2, int64_t reads, float* sink, hipStream_t s) {
+    if (n_rows_pow2 <= 0 || reads <= 0) return hipSuccess;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    // four workgroups of 256 per CU (the rate is flat from 2 to 16), each
+    // thread taking reads / threads rows in turn
+    const int64_t threads = (int64_t)cus * 4 * 256;
+    const int64_t trips = std::max<int64_t>(1, reads / threads);
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)(cus * 4)), dim3(256), 0, s, static_cast<const v4u*>(buf),
+                       (uint64_t)(n_rows_pow2 - 1), trips, sink);
+    return hipGetLastError();
+}
 
 hipError_t launch_stream_read(const void* buf, size_t bytes, float* sink, hipStream_t s) {
     const int64_t n16 = (int64_t)(bytes / 16);

@@ -34,6 +34,15 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared()) <= exported
 
 
+def test_library_leaves_none_of_its_own_symbols_undefined():
+    """Every symbol the library needs from outside is a versioned one of the C/C++ or HIP runtime (or weak): a
+    launcher declared with the wrong linkage would show up here unversioned, and fail only when first called."""
+    out = subprocess.check_output(["nm", "-D", "--undefined-only", L.LIB_PATH]).decode()
+    own = [ln.split()[-1] for ln in out.splitlines()
+           if ln.split() and ln.split()[0] == "U" and "@" not in ln.split()[-1]]
+    assert own == [], own
+
+
 def _build(child, sigma, sh, degree=0, n_internal=None, n_leaves=None, storage=L.DOT_F32, bbox=2.0):
     lib = L.load()
     child = np.ascontiguousarray(child, np.int32)
@@ -163,6 +172,9 @@ def test_batch_and_loss_argument_checks_need_no_device():
     assert lib.dot_mse_grad(None, None, None, -1, None, None, None) == L.DOT_EINVAL
     assert lib.dot_mse_grad(None, None, None, 5, None, None, None) == L.DOT_EINVAL
     assert lib.dot_mse_grad(None, None, None, 0, None, None, None) == L.DOT_OK
+    assert lib.dot_gather_rows(None, 3, 10, None, None) == L.DOT_EINVAL
+    assert b"power of two" in lib.dot_last_error()
+    assert lib.dot_gather_rows(None, 4, 10, None, None) == L.DOT_EINVAL
     assert lib.dot_pixel_batch(None, -1, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
     assert lib.dot_pixel_batch(None, 4, 0, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
     assert lib.dot_pixel_batch(None, 4, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL

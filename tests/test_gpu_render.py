@@ -266,3 +266,11 @@ def test_stream_read_probe():
     torch.cuda.synchronize()
     assert lib.dot_stream_read(C.c_void_p(buf.data_ptr() + 4), C.c_size_t(64), C.c_void_p(sink.data_ptr()),
                                None) == L.DOT_EINVAL
+    # the gather probe over the same 16 MiB (2^16 rows of 192 B fit in 12 MiB), small and odd read counts
+    L.check(lib.dot_gather_rows(C.c_void_p(buf.data_ptr()), C.c_int64(1 << 16), C.c_int64(1 << 20),
+                                C.c_void_p(sink.data_ptr()), None))
+    L.check(lib.dot_gather_rows(C.c_void_p(buf.data_ptr()), C.c_int64(1), C.c_int64(5), C.c_void_p(sink.data_ptr()),
+                                None))
+    torch.cuda.synchronize()
+    assert lib.dot_gather_rows(C.c_void_p(buf.data_ptr()), C.c_int64(3), C.c_int64(5), C.c_void_p(sink.data_ptr()),
+                               None) == L.DOT_EINVAL
