@@ -154,9 +154,12 @@ __device__ __forceinline__ int64_t chunk_len(int64_t count, int64_t chunk, int x
 // (job number + x) mod kRings, so every XCD renders a contiguous part of every
 // image (its L2 then holds neighbouring tiles), and each chunk into runs of
 // `run` tiles.  A ring is topped up only when fewer entries wait in it than
-// the XCD has waves, to twice that, the room shared evenly among the jobs that
-// still have tiles for it: a request that arrives behind a large one starts
-// after about two rounds of entries instead of after the whole large image.
+// the XCD has waves, to twice that.  Jobs with few entries left for the ring
+// (at most one per wave of the XCD) get all of them first, and the rest of the
+// room goes to the larger jobs in admission order: a small request that
+// arrives behind a large one starts after about two rounds of entries instead
+// of after the whole large image, and two large ones finish one after the
+// other instead of both late.
 // `cur` (LDS, [64][kRings]): tiles of each of the lane's chunks published.
 __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevice& dv, int max_jobs,
                        uint64_t t0, uint64_t limit_ticks, int64_t workers, int* cur_lds) {
@@ -167,6 +170,7 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
     uint64_t copied = 0;
     uint64_t tail[kRings] = {};
     int slot = -1, ring0 = 0;              // this lane's job (slot < 0: none)
+    uint64_t seq = 0;                      // its admission number
     int64_t begin = 0, count = 0, chunk = 0, run = 1;
     for (;;) {
         const bool late = wall_clock64() - t0 > limit_ticks;
@@ -190,6 +194,7 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
             c0 = c0 < 0 ? 0 : (c0 > kMaxImageTiles ? kMaxImageTiles : c0);
             if (lane == fl) {
                 slot = js;
+                seq = copied;
                 ring0 = (int)(copied % kRings);
                 begin = b0;
                 count = c0;
@@ -217,9 +222,20 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
                 const int64_t left = (len_x - done_x + run - 1) / run;     // entries this lane still has
                 const uint64_t act = __ballot(left > 0);
                 if (act == 0) break;
-                const int64_t nact = __popcll(act);
-                const int64_t share = (high - backlog + nact - 1) / nact;
-                const int64_t n = left < share ? left : share;
+                // jobs with at most a wave's worth of entries per wave of the XCD left for
+                // this ring take all of them first; the rest of the room goes to the other
+                // jobs in admission order (the oldest first, as far as it reaches)
+                const int64_t room = high - backlog;
+                const bool small = left > 0 && left <= ring_waves;
+                int64_t small_total = 0;
+                const int64_t small_before = wave_excl_sum(small ? left : 0, lane, small_total);
+                int64_t older = 0;          // entries of the large jobs admitted before this one
+                for (uint64_t m = __ballot(left > 0 && !small); m; m &= m - 1) {
+                    const int j = __ffsll((unsigned long long)m) - 1;
+                    if ((uint64_t)readlane64((int64_t)seq, j) < seq) older += readlane64(left, j);
+                }
+                int64_t n = small ? room - small_before : room - small_total - older;
+                n = n < 0 ? 0 : (n > left ? left : n);
                 int64_t total = 0;
                 const int64_t off = wave_excl_sum(n, lane, total);
                 // the entries of each job in turn, written by the whole wave

@@ -272,6 +272,38 @@ def test_persistent_results_readable_while_the_launch_runs(trees):
         q.close()
 
 
+def test_persistent_small_request_overtakes_a_large_one(trees):
+    """The feeder gives jobs with few entries left all of them before the room
+    goes to larger jobs: an 8x8 request pushed right after a 4096x4096 one
+    (262,144 tiles) completes while the large one is still rendering, and both
+    images equal dot_render's."""
+    import time
+    core, serve = _mods()
+    scenes, ts = trees
+    big = _req(serve, 0, 2, 4096, 4096, 20.0, 10.0)
+    tiny = _req(serve, 1, 0, 8, 8, 200.0, -20.0)
+    ref = _reference_images(core, ts, [big, tiny])
+    out_big = torch.zeros((big.height, big.width, 3), device="cuda")
+    out_tiny = torch.zeros((tiny.height, tiny.width, 3), device="cuda")
+    torch.cuda.synchronize()
+    q = serve.Queue("f16", max_jobs=8, max_seconds=20.0)
+    try:
+        tb = q.push(ts[big.tree], big.cam, out_big, big.width, big.height)
+        tt = q.push(ts[tiny.tree], tiny.cam, out_tiny, tiny.width, tiny.height)
+        t0 = time.perf_counter()
+        while not q.done(tt):
+            assert time.perf_counter() - t0 < 10.0
+        t_tiny = time.perf_counter() - t0
+        big_done_first = q.done(tb)
+        q.wait(tb, timeout=10.0)
+    finally:
+        q.close()
+    print(f"tiny done after {1e3 * t_tiny:.3f} ms (big done by then: {big_done_first})")
+    assert not big_done_first
+    np.testing.assert_allclose(out_tiny.cpu().numpy(), ref[tiny.rid], atol=1e-6, rtol=0)
+    np.testing.assert_allclose(out_big.cpu().numpy(), ref[big.rid], atol=1e-6, rtol=0)
+
+
 def test_persistent_queue_limits_and_time_limit(trees):
     """A queue refuses a tree of another storage type and a tile range outside
     the image; it reports a full queue (2^19 tiles of unfinished jobs) without
