@@ -4,10 +4,12 @@ Step = one forward render (Eq. 1-2) of the 800x800 x 8-camera workload
 (torus+box SDF octree of depth 9, 3.54M leaves, SH degree 3, FP32 leaves),
 inputs resident in HBM.  The JSON line also carries the roofline of the render
 kernel (compulsory bytes: every distinct leaf the frame composites fetched
-once), the same frame with the fused max-weight signal (its buffer cleared in
-every step), the FP64 CPU oracle as a baseline, and the other measured forms
-of the hot path (FP16/BF16/palette leaves, the differentiable training step,
-refinement, serving latency).
+once; beside them the counter traffic of the same launch kind and the two
+measured ceilings, streaming reads and random 192-byte row gathers), the same
+frame with the fused max-weight signal (its buffer cleared in every step), the
+FP64 CPU oracle as a baseline, and the other measured forms of the hot path
+(FP16/BF16/palette leaves, the differentiable training step, Alg. 1 epochs,
+refinement, serving latency on the persistent launch and on relaunches).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """

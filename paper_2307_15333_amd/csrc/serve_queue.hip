@@ -113,7 +113,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 // invalidation an acquire implies: thousands of waiting waves issuing
 // acquires would keep the L2 invalidating); the data a changed word publishes
 // is then read with relaxed atomic loads too, so no wave ever needs an
-// acquire.  Writers publish with release stores (one per job or per tile).
+// acquire.  The feeder publishes entries behind one release fence per round;
+// workers count runs after their device-scope stores complete, and only a
+// job's last run issues a release (system scope, for the host).
 __device__ __forceinline__ uint64_t poll_sys(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
