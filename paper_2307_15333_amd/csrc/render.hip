@@ -620,35 +620,30 @@ __device__ __forceinline__ uint32_t bucket_rows(int64_t l, const uint32_t* __res
     return (base0 ? base0[l] : 0u) + min(count[l], cursor[l]);
 }
 
-// Sum of one leaf's bucket: dsigma and, per channel, sum_rows a_ch Y_k(d_row).
+// One bucket row added to a leaf's sums: dsigma and, per channel, a_ch Y_k(d_row).
 template <int DEG>
-__device__ __forceinline__ bool bucket_sum(int64_t l, const uint32_t* __restrict__ offset,
-                                           const uint32_t* __restrict__ base0, const uint32_t* __restrict__ count,
-                                           const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
-                                           float& gs, float* acc) {
+__device__ __forceinline__ void bucket_add_row(const float4 h, const float4 q, float& gs, float* acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int RS = bwd_row_floats<DEG>();
-    const uint32_t m = bucket_rows(l, base0, count, cursor);
-    gs = 0.f;
+    float Y[K];
+    if constexpr (RS == 8)
+        sh_basis<DEG>(q.x, q.y, q.z, Y);
+    else
+        sh_basis<DEG>(0.f, 0.f, 1.f, Y);
+    gs += h.x;
+    const float a[3] = {h.y, h.z, h.w};
 #pragma unroll
-    for (int j = 0; j < 3 * K; ++j) acc[j] = 0.f;
-    if (m == 0) return false;
-    const float4* p = reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS);
-    constexpr int Q = RS / 4;     // float4 per row
-    constexpr int U = 4;          // rows whose loads are issued together
-    auto add_row = [&](const float4 h, const float4 q) {
-        float Y[K];
-        if constexpr (RS == 8)
-            sh_basis<DEG>(q.x, q.y, q.z, Y);
-        else
-            sh_basis<DEG>(0.f, 0.f, 1.f, Y);
-        gs += h.x;
-        const float a[3] = {h.y, h.z, h.w};
+    for (int ch = 0; ch < 3; ++ch)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc[ch * K + k] += a[ch] * Y[k];
-    };
+        for (int k = 0; k < K; ++k) acc[ch * K + k] += a[ch] * Y[k];
+}
+
+// Sum of the m rows at p taken by one thread (a light bucket), into gs/acc
+// (zeroed by the caller).
+template <int DEG>
+__device__ __forceinline__ void bucket_sum_thread(const float4* __restrict__ p, uint32_t m, float& gs, float* acc) {
+    constexpr int Q = bwd_row_floats<DEG>() / 4;     // float4 per row
+    constexpr int U = 4;                              // rows whose loads are issued together
     uint32_t r = 0;
     for (; r + U <= m; r += U) {
         float4 h[U], q[U];
@@ -658,54 +653,72 @@ __device__ __forceinline__ bool bucket_sum(int64_t l, const uint32_t* __restrict
             q[u] = Q == 2 ? p[(int64_t)(r + u) * Q + (Q - 1)] : h[u];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) add_row(h[u], q[u]);
+        for (int u = 0; u < U; ++u) bucket_add_row<DEG>(h[u], q[u], gs, acc);
     }
     for (; r < m; ++r) {
         const float4 h = p[(int64_t)r * Q];
-        add_row(h, Q == 2 ? p[(int64_t)r * Q + (Q - 1)] : h);
+        bucket_add_row<DEG>(h, Q == 2 ? p[(int64_t)r * Q + (Q - 1)] : h, gs, acc);
     }
-    return true;
 }
 
-// Bucket reductions: one thread per leaf sums its bucket into registers, then
-// the block stages the SH sums of its 256 leaves in LDS one channel at a time
-// (K floats per leaf, padded to K + 1 against bank conflicts; 17 KB at degree
-// 3, so several blocks stay resident per CU) and all threads walk that
-// channel's columns of the block's leaves, so loads and stores are coalesced
-// in K-float runs (a thread-per-leaf row of 3K floats would touch a new cache
-// line per lane and instruction).
-constexpr int RED_BLOCK = 256;
-
+// Sum of the m rows at p taken by a whole wave (called by all its lanes with
+// the same p and m): lanes stride over the rows (consecutive lanes read
+// consecutive rows), then a butterfly leaves the totals in every lane.
 template <int DEG>
-__global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const uint32_t* __restrict__ offset,
-                                                               const uint32_t* __restrict__ base0,
-                                                               const uint32_t* __restrict__ count,
-                                                               const uint32_t* __restrict__ cursor,
-                                                               const float* __restrict__ rows,
-                                                               float* __restrict__ gsig, float* __restrict__ gsh) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr int NV = 3 * K;
-    constexpr int KP = K + 1;
-    __shared__ float stage[RED_BLOCK * KP];
-    const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
-    const int64_t l = l0 + threadIdx.x;
-    float gs = 0.f, acc[NV];
+__device__ __forceinline__ void bucket_sum_wave(const float4* __restrict__ p, uint32_t m, float& gs, float* acc) {
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
+    constexpr int Q = bwd_row_floats<DEG>() / 4;
+    constexpr int U = 4;          // rows per lane whose loads are issued together
+    const int lane = threadIdx.x & (WAVE - 1);
+    gs = 0.f;
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.f;
-    if (l < L && bucket_sum<DEG>(l, offset, base0, count, cursor, rows, gs, acc)) gsig[l] += gs;
-    const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
+    uint32_t r = lane;
+    for (; r + (U - 1) * WAVE < m; r += U * WAVE) {
+        float4 h[U], q[U];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        if (ch) __syncthreads();
-#pragma unroll
-        for (int k = 0; k < K; ++k) stage[threadIdx.x * KP + k] = acc[ch * K + k];
-        __syncthreads();
-        for (int i = threadIdx.x; i < nl * K; i += RED_BLOCK) {
-            const int r = i / K, k = i - r * K;
-            const float v = stage[r * KP + k];
-            if (v != 0.f) gsh[(l0 + r) * NV + ch * K + k] += v;
+        for (int u = 0; u < U; ++u) {
+            h[u] = p[(int64_t)(r + u * WAVE) * Q];
+            q[u] = Q == 2 ? p[(int64_t)(r + u * WAVE) * Q + (Q - 1)] : h[u];
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) bucket_add_row<DEG>(h[u], q[u], gs, acc);
     }
+    for (; r < m; r += WAVE) {
+        const float4 h = p[(int64_t)r * Q];
+        bucket_add_row<DEG>(h, Q == 2 ? p[(int64_t)r * Q + (Q - 1)] : h, gs, acc);
+    }
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        gs += __shfl_xor(gs, off, WAVE);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] += __shfl_xor(acc[j], off, WAVE);
+    }
+}
+
+// Buckets of more rows than this are left out of the thread-per-leaf sums and
+// reduced at the end of the kernel by the whole wave of the thread that owns
+// the leaf: a thread-per-leaf sum would keep the block waiting on its longest
+// bucket (a few leaves of a large batch collect thousands of rows).
+constexpr uint32_t kLightRows = 32;
+
+// Rows of the bucket of leaf l (0 for l >= L) and, for a light bucket, its sums
+// (zero otherwise).
+template <int DEG>
+__device__ __forceinline__ uint32_t bucket_sum_light(int64_t l, int64_t L, const uint32_t* __restrict__ offset,
+                                                     const uint32_t* __restrict__ base0,
+                                                     const uint32_t* __restrict__ count,
+                                                     const uint32_t* __restrict__ cursor,
+                                                     const float* __restrict__ rows, float& gs, float* acc) {
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
+    constexpr int RS = bwd_row_floats<DEG>();
+    const uint32_t m = l < L ? bucket_rows(l, base0, count, cursor) : 0u;
+    gs = 0.f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.f;
+    if (m > 0 && m <= kLightRows)
+        bucket_sum_thread<DEG>(reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS), m, gs, acc);
+    return m;
 }
 
 // A fused optimiser step, by value: RMSProp (d1 = alpha) or Adam (d1, d2 =
@@ -736,13 +749,105 @@ __device__ __forceinline__ void fused_update(float* theta, int64_t ti, float* m,
     v[si] = vv;
 }
 
+// A leaf's bucket totals (held by every lane of the wave) applied by the wave:
+// lane k owns SH column k and lane 0 sigma.  A fused optimiser step updates
+// the leaf; otherwise the sums are added to the gradient arrays when the
+// bucket has rows.
+template <int DEG, int OPT>
+__device__ __forceinline__ void wave_leaf_apply(int64_t l, uint32_t m, float gs, const float* acc,
+                                                float* __restrict__ gsig, float* __restrict__ gsh,
+                                                float* __restrict__ sigma, float* __restrict__ sh, int stride,
+                                                const FusedOpt& o) {
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
+    static_assert(NV <= WAVE, "one lane per column");
+    const int lane = threadIdx.x & (WAVE - 1);
+    float mine = 0.f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        if (lane == j) mine = acc[j];
+    if constexpr (OPT != OPT_NONE) {
+        if (lane < NV) fused_update<OPT>(sh, l * stride + lane, o.m_sh, o.v_sh, l * NV + lane, mine, o.lr_sh, o);
+        if (lane == 0) fused_update<OPT>(sigma, l, o.m_sigma, o.v_sigma, l, gs, o.lr_sigma, o);
+    } else if (m > 0) {
+        if (lane < NV && mine != 0.f) gsh[l * NV + lane] += mine;
+        if (lane == 0) gsig[l] += gs;
+    }
+}
+
+// The heavy buckets among the wave's leaves (lane i owns leaf l_i, whose
+// bucket has m_i rows), one leaf at a time by all lanes.  Called by every
+// lane of the wave.
+template <int DEG, int OPT>
+__device__ __forceinline__ void wave_heavy_leaves(int64_t l, uint32_t m, const uint32_t* __restrict__ offset,
+                                                  const float* __restrict__ rows, float* __restrict__ gsig,
+                                                  float* __restrict__ gsh, float* __restrict__ sigma,
+                                                  float* __restrict__ sh, int stride, const FusedOpt& o) {
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
+    constexpr int RS = bwd_row_floats<DEG>();
+    uint64_t heavy = __ballot(m > kLightRows);
+    while (heavy) {
+        const int j = __ffsll((unsigned long long)heavy) - 1;
+        heavy &= heavy - 1;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)l, j);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)l >> 32), j);
+        const int64_t lj = (int64_t)(((uint64_t)hi << 32) | lo);
+        const uint32_t mj = (uint32_t)__builtin_amdgcn_readlane((int)m, j);
+        float gs, acc[NV];
+        bucket_sum_wave<DEG>(reinterpret_cast<const float4*>(rows + (int64_t)offset[lj] * RS), mj, gs, acc);
+        wave_leaf_apply<DEG, OPT>(lj, mj, gs, acc, gsig, gsh, sigma, sh, stride, o);
+    }
+}
+
+// Bucket reductions: one thread per leaf sums its bucket into registers, then
+// the block stages the SH sums of its 256 leaves in LDS one channel at a time
+// (K floats per leaf, padded to K + 1 against bank conflicts; 17 KB at degree
+// 3, so several blocks stay resident per CU) and all threads walk that
+// channel's columns of the block's leaves, so loads and stores are coalesced
+// in K-float runs (a thread-per-leaf row of 3K floats would touch a new cache
+// line per lane and instruction).  Heavy buckets are left out of that pass
+// (their leaves are neither read nor written) for bwd_heavy_kernel.
+constexpr int RED_BLOCK = 256;
+
+template <int DEG>
+__global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const uint32_t* __restrict__ offset,
+                                                               const uint32_t* __restrict__ base0,
+                                                               const uint32_t* __restrict__ count,
+                                                               const uint32_t* __restrict__ cursor,
+                                                               const float* __restrict__ rows,
+                                                               float* __restrict__ gsig, float* __restrict__ gsh) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int NV = 3 * K;
+    constexpr int KP = K + 1;
+    __shared__ float stage[RED_BLOCK * KP];
+    const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
+    const int64_t l = l0 + threadIdx.x;
+    float gs, acc[NV];
+    const uint32_t m = bucket_sum_light<DEG>(l, L, offset, base0, count, cursor, rows, gs, acc);
+    if (m > 0 && m <= kLightRows) gsig[l] += gs;
+    const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        if (ch) __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) stage[threadIdx.x * KP + k] = acc[ch * K + k];
+        __syncthreads();
+        // a heavy leaf's staged sums are zero: none of its columns is written here
+        for (int i = threadIdx.x; i < nl * K; i += RED_BLOCK) {
+            const int r = i / K, k = i - r * K;
+            const float v = stage[r * KP + k];
+            if (v != 0.f) gsh[(l0 + r) * NV + ch * K + k] += v;
+        }
+    }
+}
+
 // The optimiser step on channel ch of a block's nl leaves, whose SH sums sit
 // in stage (K per leaf, padded to KP).  Item i = (leaf r, run q) covers W
 // consecutive columns (W = 4: float4 accesses, when K % 4 == 0 and the planes
 // are 16-byte aligned).  hit[r] = 0 marks a leaf with an empty bucket (g = 0):
 // RMSProp then leaves its values exactly as they are (lr 0 / (sqrt(v) + eps)
 // = 0) and only decays the square average, so the values are neither read
-// nor written; Adam still moves such a leaf by its first moment.
+// nor written; Adam still moves such a leaf by its first moment.  hit[r] = 2
+// marks a heavy bucket, whose leaf bwd_heavy_kernel updates.
 template <int K, int W, int OPT>
 __device__ __forceinline__ void fused_channel(int64_t l0, int nl, int ch, const float* stage, const int* hit,
                                               float* __restrict__ sh, int stride, const FusedOpt& o) {
@@ -762,7 +867,7 @@ __device__ __forceinline__ void fused_channel(int64_t l0, int nl, int ch, const 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u * RED_BLOCK;
-            live[u] = i < ni;
+            live[u] = i < ni && hit[i / Q] != 2;
             full[u] = false;
             if (live[u]) {
                 const int r = i / Q, q = i - r * Q;
@@ -819,15 +924,16 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const u
     __shared__ int hit[RED_BLOCK];
     const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
     const int64_t l = l0 + threadIdx.x;
-    float gs = 0.f, acc[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) acc[j] = 0.f;
+    float gs, acc[NV];
+    const uint32_t m = bucket_sum_light<DEG>(l, L, offset, base0, count, cursor, rows, gs, acc);
+    const bool heavy = m > kLightRows;
     if (l < L) {
-        const bool h = bucket_sum<DEG>(l, offset, base0, count, cursor, rows, gs, acc);
-        hit[threadIdx.x] = h;
-        if (OPT == OPT_RMSPROP && !h) {
-            float th = 0.f, m = 0.f;          // g = 0: sigma stays, its square average decays
-            opt_apply<OPT>(th, m, o.v_sigma[l], 0.f, o.lr_sigma, o);
+        hit[threadIdx.x] = heavy ? 2 : (m > 0 ? 1 : 0);
+        if (heavy) {
+            // left to bwd_heavy_kernel
+        } else if (OPT == OPT_RMSPROP && m == 0) {
+            float th = 0.f, mm = 0.f;         // g = 0: sigma stays, its square average decays
+            opt_apply<OPT>(th, mm, o.v_sigma[l], 0.f, o.lr_sigma, o);
         } else {
             fused_update<OPT>(sigma, l, o.m_sigma, o.v_sigma, l, gs, o.lr_sigma, o);
         }
@@ -843,62 +949,42 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const u
     }
 }
 
-// Heavy buckets (many rows per leaf, e.g. a small tree under a large batch):
-// one wave per leaf, lanes stride over the rows, then a butterfly reduction of
-// the 1 + 3K sums across the wave; lane j then owns column j.  A fused OPT
-// updates every leaf, otherwise the sums are added to the gradient arrays.
+// Heavy buckets on average (many rows per leaf, e.g. a small tree under a
+// large batch): one wave per leaf for every leaf.
 template <int DEG, int OPT>
 __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_wave_kernel(
     int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ base0,
     const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
     float* __restrict__ gsig, float* __restrict__ gsh, float* __restrict__ sigma, float* __restrict__ sh, int stride,
     FusedOpt o) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr int NV = 3 * K;
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
     constexpr int RS = bwd_row_floats<DEG>();
-    constexpr int Q = RS / 4;
-    static_assert(NV <= WAVE, "one lane per column");
-    const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     for (int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; l < L; l += nw) {
         const uint32_t m = bucket_rows(l, base0, count, cursor);
-        const float4* p4 = reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS);
-        float gs = 0.f, acc[NV];
-#pragma unroll
-        for (int j = 0; j < NV; ++j) acc[j] = 0.f;
-        for (uint32_t r = lane; r < m; r += WAVE) {
-            const float4 h = p4[(int64_t)r * Q];
-            float Y[K];
-            if constexpr (RS == 8) {
-                const float4 q = p4[(int64_t)r * Q + 1];
-                sh_basis<DEG>(q.x, q.y, q.z, Y);
-            } else {
-                sh_basis<DEG>(0.f, 0.f, 1.f, Y);
-            }
-            gs += h.x;
-            const float a[3] = {h.y, h.z, h.w};
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch)
-#pragma unroll
-                for (int k = 0; k < K; ++k) acc[ch * K + k] += a[ch] * Y[k];
-        }
-#pragma unroll
-        for (int off = WAVE / 2; off > 0; off >>= 1) {
-            gs += __shfl_xor(gs, off, WAVE);
-#pragma unroll
-            for (int j = 0; j < NV; ++j) acc[j] += __shfl_xor(acc[j], off, WAVE);
-        }
-        float mine = 0.f;
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            if (lane == j) mine = acc[j];
-        if constexpr (OPT != OPT_NONE) {
-            if (lane < NV) fused_update<OPT>(sh, l * stride + lane, o.m_sh, o.v_sh, l * NV + lane, mine, o.lr_sh, o);
-            if (lane == 0) fused_update<OPT>(sigma, l, o.m_sigma, o.v_sigma, l, gs, o.lr_sigma, o);
-        } else if (m > 0) {
-            if (lane < NV && mine != 0.f) gsh[l * NV + lane] += mine;
-            if (lane == 0) gsig[l] += gs;
-        }
+        float gs, acc[NV];
+        bucket_sum_wave<DEG>(reinterpret_cast<const float4*>(rows + (int64_t)offset[l] * RS), m, gs, acc);
+        wave_leaf_apply<DEG, OPT>(l, m, gs, acc, gsig, gsh, sigma, sh, stride, o);
+    }
+}
+
+// The heavy buckets the block reductions leave out: wave w of nw takes the
+// leaves w + nw i, 64 at a time (lane j: i = b + j), so a run of adjacent
+// heavy leaves (neighbours in space collect rows together) spreads over
+// neighbouring waves instead of queueing in one.
+template <int DEG, int OPT>
+__global__ __launch_bounds__(RED_BLOCK) void bwd_heavy_kernel(
+    int64_t L, const uint32_t* __restrict__ offset, const uint32_t* __restrict__ base0,
+    const uint32_t* __restrict__ count, const uint32_t* __restrict__ cursor, const float* __restrict__ rows,
+    float* __restrict__ gsig, float* __restrict__ gsh, float* __restrict__ sigma, float* __restrict__ sh, int stride,
+    FusedOpt o) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    for (int64_t b = 0; w + nw * b < L; b += WAVE) {
+        const int64_t l = w + nw * (b + lane);
+        const uint32_t m = l < L ? bucket_rows(l, base0, count, cursor) : 0u;
+        wave_heavy_leaves<DEG, OPT>(l, m, offset, rows, gsig, gsh, sigma, sh, stride, o);
     }
 }
 
@@ -926,27 +1012,34 @@ static FusedOpt fused_opt(const BwdArgs& a) {
 
 static int opt_kind(const BwdArgs& a) { return a.adam ? OPT_ADAM : a.rms ? OPT_RMSPROP : OPT_NONE; }
 
-template <int DEG, int OPT>
-static void launch_reduce_wave_opt(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
-                                   const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
+// HEAVY: bwd_heavy_kernel (the buckets a block reduction left out), else
+// bwd_reduce_wave_kernel (every leaf)
+template <int DEG, int OPT, bool HEAVY>
+static void launch_wave_opt(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
+                            const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
     const int64_t L = t.n_leaves;
-    const unsigned g = (unsigned)std::min<int64_t>((L + RED_BLOCK / WAVE - 1) / (RED_BLOCK / WAVE), 1 << 16);
-    if constexpr (OPT == OPT_NONE)
-        hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, OPT>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0,
-                           count, cursor, rows, a.grad_sigma, a.grad_sh, nullptr, nullptr, 0, FusedOpt{});
+    const int64_t want = HEAVY ? (L + RED_BLOCK - 1) / RED_BLOCK : (L + RED_BLOCK / WAVE - 1) / (RED_BLOCK / WAVE);
+    const unsigned g = (unsigned)std::min<int64_t>(want, HEAVY ? 2048 : 1 << 16);
+    float* gsig = OPT == OPT_NONE ? a.grad_sigma : nullptr;
+    float* gsh = OPT == OPT_NONE ? a.grad_sh : nullptr;
+    float* sg = OPT == OPT_NONE ? nullptr : static_cast<float*>(t.sigma);
+    float* sh = OPT == OPT_NONE ? nullptr : static_cast<float*>(t.sh);
+    const FusedOpt o = OPT == OPT_NONE ? FusedOpt{} : fused_opt(a);
+    if constexpr (HEAVY)
+        hipLaunchKernelGGL((bwd_heavy_kernel<DEG, OPT>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0, count,
+                           cursor, rows, gsig, gsh, sg, sh, t.sh_stride, o);
     else
         hipLaunchKernelGGL((bwd_reduce_wave_kernel<DEG, OPT>), dim3(g), dim3(RED_BLOCK), 0, s, L, offset, base0,
-                           count, cursor, rows, nullptr, nullptr, static_cast<float*>(t.sigma),
-                           static_cast<float*>(t.sh), t.sh_stride, fused_opt(a));
+                           count, cursor, rows, gsig, gsh, sg, sh, t.sh_stride, o);
 }
 
-template <int DEG>
-static void launch_reduce_wave(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
-                               const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
+template <int DEG, bool HEAVY>
+static void launch_wave(const dot_tree& t, const BwdArgs& a, const uint32_t* offset, const uint32_t* base0,
+                        const uint32_t* count, const uint32_t* cursor, const float* rows, hipStream_t s) {
     switch (opt_kind(a)) {
-        case OPT_RMSPROP: launch_reduce_wave_opt<DEG, OPT_RMSPROP>(t, a, offset, base0, count, cursor, rows, s); break;
-        case OPT_ADAM: launch_reduce_wave_opt<DEG, OPT_ADAM>(t, a, offset, base0, count, cursor, rows, s); break;
-        default: launch_reduce_wave_opt<DEG, OPT_NONE>(t, a, offset, base0, count, cursor, rows, s); break;
+        case OPT_RMSPROP: launch_wave_opt<DEG, OPT_RMSPROP, HEAVY>(t, a, offset, base0, count, cursor, rows, s); break;
+        case OPT_ADAM: launch_wave_opt<DEG, OPT_ADAM, HEAVY>(t, a, offset, base0, count, cursor, rows, s); break;
+        default: launch_wave_opt<DEG, OPT_NONE, HEAVY>(t, a, offset, base0, count, cursor, rows, s); break;
     }
 }
 
@@ -1318,12 +1411,13 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         }
     }
     const unsigned rg = (unsigned)((L + RED_BLOCK - 1) / RED_BLOCK);
-    if ((uint64_t)m >= (uint64_t)kWaveRowsPerLeaf * (uint64_t)L) {
+    const bool wave_all = (uint64_t)m >= (uint64_t)kWaveRowsPerLeaf * (uint64_t)L;
+    if (wave_all) {
         switch (t.degree) {
-            case 0: launch_reduce_wave<0>(t, a, offset, base0, count, cursor, rows, s); break;
-            case 1: launch_reduce_wave<1>(t, a, offset, base0, count, cursor, rows, s); break;
-            case 2: launch_reduce_wave<2>(t, a, offset, base0, count, cursor, rows, s); break;
-            default: launch_reduce_wave<3>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 0: launch_wave<0, false>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 1: launch_wave<1, false>(t, a, offset, base0, count, cursor, rows, s); break;
+            case 2: launch_wave<2, false>(t, a, offset, base0, count, cursor, rows, s); break;
+            default: launch_wave<3, false>(t, a, offset, base0, count, cursor, rows, s); break;
         }
     } else if (fused) {
         switch (t.degree) {
@@ -1337,6 +1431,13 @@ hipError_t launch_render_bwd(const dot_tree& t, const RayBatch& rb, const BwdArg
         case 1: hipLaunchKernelGGL(bwd_reduce_kernel<1>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
         case 2: hipLaunchKernelGGL(bwd_reduce_kernel<2>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
         default: hipLaunchKernelGGL(bwd_reduce_kernel<3>, dim3(rg), dim3(RED_BLOCK), 0, s, L, offset, base0, count, cursor, rows, a.grad_sigma, a.grad_sh); break;
+    }
+    // the heavy buckets a block reduction left out
+    if (!wave_all) switch (t.degree) {
+        case 0: launch_wave<0, true>(t, a, offset, base0, count, cursor, rows, s); break;
+        case 1: launch_wave<1, true>(t, a, offset, base0, count, cursor, rows, s); break;
+        case 2: launch_wave<2, true>(t, a, offset, base0, count, cursor, rows, s); break;
+        default: launch_wave<3, true>(t, a, offset, base0, count, cursor, rows, s); break;
     }
     e = hipGetLastError();
     t.scratch_put(rows, s);

@@ -44,6 +44,10 @@ from paper_2307_15333_amd import synth
 pytestmark = pytest.mark.gpu
 
 
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
 def _core():
     from paper_2307_15333_amd import core
     return core
@@ -215,6 +219,62 @@ def test_fused_backward_rmsprop_matches_oracle(degree):
     ex2 = tree.export()
     np.testing.assert_array_equal(ex2["sigma"], ex["sigma"])
     np.testing.assert_array_equal(st["v_sigma"].cpu().numpy(), (v1 * np.float32(0.99)).cpu().numpy())
+    tree.close()
+
+
+@pytest.mark.parametrize("optimizer", ["none", "rmsprop", "adam"])
+def test_heavy_and_light_buckets_in_the_block_reduction(optimizer):
+    """The block reductions (chosen when a batch brings fewer than 32 rows per
+    leaf on average) sum buckets of up to 32 rows one thread per leaf and leave
+    larger ones to the wave of the leaf's thread.  A 64x64 view of the whole
+    sphere octree gives most leaves a few rows and another through a 4 degree
+    field gives the few leaves it sees hundreds.  Against the oracle:
+    the adjoint's gradients (its own counting pass), and the fused RMSProp /
+    Adam steps replaying the training forward's records (eps = 1e-4, as in the
+    fused tests above)."""
+    core = _core()
+    s = synth.sphere_scene()
+    cams = np.concatenate([synth.cameras([(30.0, 20.0, 4.0, 64, 64)]),
+                           np.atleast_1d(synth.look_at_camera(30.0, 20.0, 4.0, 64, 64, fov_deg=4.0))])
+    ci = np.repeat(np.arange(2, dtype=np.int32), 64 * 64)
+    pi = np.tile(np.arange(64 * 64, dtype=np.int32), 2)
+    n = ci.shape[0]
+    rays = core.Rays.pixels(cams, ci, pi)
+    o, d = O.camera_rays(cams, ci, pi)
+    g = np.random.default_rng(21).normal(size=(n, 3)) * 1e-3
+    g32 = torch.as_tensor(g, dtype=torch.float32, device="cuda")
+    tree = core.Octree.from_scene(s)
+    Ln = tree.n_leaves
+    rec = torch.empty(core.Octree.records_bytes(n, 96), dtype=torch.uint8, device="cuda")
+    rgb, ns, cnt = tree.render_train(rays, t_stop=0.0, records=rec)
+    m = cnt.sum(0).cpu().numpy().astype(np.int64)
+    assert (m > 32).sum() >= 16 and ((m > 0) & (m <= 32)).sum() >= 1000 and m.sum() < 32 * Ln
+    T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
+    rs, rh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64), t_stop=0.0)
+    if optimizer == "none":
+        gs = torch.zeros(Ln, device="cuda")
+        gh = torch.zeros((Ln, 3, tree.K), device="cuda")
+        tree.backward(rays, rgb, ns, g32, gs, gh, t_stop=0.0)
+        assert _rel(gs.cpu().numpy(), rs) <= 1e-4 and _rel(gh.cpu().numpy(), rh) <= 1e-4
+    elif optimizer == "rmsprop":
+        st = tree.rmsprop_state()
+        tree.backward_rmsprop(rays, rgb, ns, g32, st, eps=1e-4, t_stop=0.0, leaf_count=cnt, records=rec)
+        ex = tree.export()
+        ws, vs = A.rmsprop(s.sigma.astype(np.float64), rs, np.zeros_like(rs), 0.1, 0.99, 1e-4)
+        wh, vh = A.rmsprop(s.sh.astype(np.float64), rh, np.zeros_like(rh), 0.01, 0.99, 1e-4)
+        np.testing.assert_allclose(ex["sigma"], ws, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(ex["sh"], wh, rtol=1e-6, atol=1e-6)
+        assert_square_average(st["v_sigma"].cpu().numpy(), vs, rs, 0.99)
+        assert_square_average(st["v_sh"].cpu().numpy(), vh, rh, 0.99)
+    else:
+        st = tree.adam_state()
+        tree.backward_adam(rays, rgb, ns, g32, st, 1, eps=1e-4, t_stop=0.0, leaf_count=cnt, records=rec)
+        ex = tree.export()
+        zs, zh = np.zeros_like(rs), np.zeros_like(rh)
+        ws, _, _ = A.adam(s.sigma.astype(np.float64), rs, zs, zs, 1, 0.1, 0.9, 0.999, 1e-4)
+        wh, _, _ = A.adam(s.sh.astype(np.float64), rh, zh, zh, 1, 0.01, 0.9, 0.999, 1e-4)
+        np.testing.assert_allclose(ex["sigma"], ws, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(ex["sh"], wh, rtol=1e-6, atol=1e-6)
     tree.close()
 
 
