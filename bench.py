@@ -617,30 +617,41 @@ def train_step(torch, core, synth, args):
     Adam applied inside the adjoint by FusedAdam).  Beside it: the training
     driver's step (adjoint and Adam fused, no autograd), and the autograd step
     with dense gradients returned to autograd, PyTorch's MSE and a separate
-    Adam kernel."""
+    Adam kernel.  Each route: 3 warm-up steps, then the median of 5 runs of 20
+    steps (each run's mean step time is logged)."""
     from paper_2307_15333_amd import train as TR
     B = 1 << 18
     steps = 20
     W = H = 64
 
-    def timed(step_fn, n_warm=3):
+    def timed(step_fn, n_warm=3, reps=5):
+        # the median over `reps` runs of `steps` consecutive steps: the routes
+        # through autograd are bound by the host, where one stray pause (a
+        # garbage collection, another process) moves a 20-step mean by tens
+        # of microseconds; training continues from one run to the next
         for k in range(n_warm):
             step_fn()
         torch.cuda.synchronize()
-        losses = []
-        t = time.perf_counter()
-        for _ in range(steps):
-            losses.append(step_fn())
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / steps, float(losses[0]), float(losses[-1])
+        per, first, last = [], None, None
+        for _ in range(reps):
+            losses = []
+            t = time.perf_counter()
+            for _ in range(steps):
+                losses.append(step_fn())
+            torch.cuda.synchronize()
+            per.append((time.perf_counter() - t) / steps)
+            first = float(losses[0]) if first is None else first
+            last = float(losses[-1])
+        return float(np.median(per)), first, last, [round(x * 1e3, 3) for x in per]
 
     # the training driver
     tree, views, target = _train_setup(torch, core, synth)
     tr = TR.Trainer(tree, views, target, TR.TrainConfig(optimizer="adam", batch_rays=B, refine=False, seed=3))
     idx = tr.permutation()[:B]
-    dd, d0, d1 = timed(lambda: tr.step(idx))
+    dd, d0, d1, dreps = timed(lambda: tr.step(idx))
     tree.close()
-    log(f"train step (training driver): {dd * 1e3:.3f} ms, {B / dd / 1e6:.1f} Mrays/s, loss {d0:.3e} -> {d1:.3e}")
+    log(f"train step (training driver): {dd * 1e3:.3f} ms, {B / dd / 1e6:.1f} Mrays/s, loss {d0:.3e} -> {d1:.3e} "
+        f"(runs {dreps} ms)")
 
     def autograd_step_fn(dense):
         tree, views, target = _train_setup(torch, core, synth)
@@ -672,21 +683,21 @@ def train_step(torch, core, synth, args):
         return tree, step
 
     tree, fn = autograd_step_fn(False)
-    da, a0, a1 = timed(fn)
+    da, a0, a1, areps = timed(fn)
     tree.close()
     log(f"train step (autograd Function, MSELoss, Adam in the adjoint): {da * 1e3:.3f} ms, {B / da / 1e6:.1f} "
-        f"Mrays/s, loss {a0:.3e} -> {a1:.3e}")
+        f"Mrays/s, loss {a0:.3e} -> {a1:.3e} (runs {areps} ms)")
     tree, fn = autograd_step_fn(True)
-    dn, n0, n1 = timed(fn)
+    dn, n0, n1, nreps = timed(fn)
     tree.close()
     log(f"train step (autograd Function, dense gradients, torch MSE, dot_adam_step): {dn * 1e3:.3f} ms, "
-        f"{B / dn / 1e6:.1f} Mrays/s, loss {n0:.3e} -> {n1:.3e}")
+        f"{B / dn / 1e6:.1f} Mrays/s, loss {n0:.3e} -> {n1:.3e} (runs {nreps} ms)")
     return {"train_step_ms": round(da * 1e3, 3), "train_step_mrays": round(B / da / 1e6, 1),
-            "train_rays_per_step": B, "train_loss_first_last": [a0, a1],
+            "train_rays_per_step": B, "train_loss_first_last": [a0, a1], "train_step_runs_ms": areps,
             "train_step_note": "config 4 through the autograd Function (DotRender + MSELoss + loss.backward(), "
                                "Adam applied inside the adjoint)",
             "train_driver_step_ms": round(dd * 1e3, 3), "train_driver_step_mrays": round(B / dd / 1e6, 1),
-            "train_driver_loss_first_last": [d0, d1],
+            "train_driver_loss_first_last": [d0, d1], "train_driver_step_runs_ms": dreps,
             "train_autograd_over_driver": round(da / dd, 3),
             "train_step_autograd_dense_ms": round(dn * 1e3, 3),
             "train_step_autograd_dense_mrays": round(B / dn / 1e6, 1),

@@ -19,7 +19,15 @@ _NP_CAMERA = np.dtype([("c2w", np.float32, (12,)), ("fx", np.float32), ("fy", np
 assert _NP_CAMERA.itemsize == C.sizeof(L.dot_camera)
 
 
+# the current stream's handle without building a torch.cuda.Stream object (a
+# few microseconds a call, several calls a training step)
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+_cur_device = getattr(torch._C, "_cuda_getDevice", None)
+
+
 def _stream():
+    if _raw_stream is not None and _cur_device is not None:
+        return C.c_void_p(_raw_stream(_cur_device()))
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
