@@ -225,8 +225,8 @@ def test_fused_backward_rmsprop_matches_oracle(degree):
 @pytest.mark.parametrize("optimizer", ["none", "rmsprop", "adam"])
 def test_heavy_and_light_buckets_in_the_block_reduction(optimizer):
     """The block reductions (chosen when a batch brings fewer than 32 rows per
-    leaf on average) sum buckets of up to 32 rows one thread per leaf and leave
-    larger ones to the wave of the leaf's thread.  A 64x64 view of the whole
+    leaf on average) sum buckets of up to 64 rows one thread per leaf and leave
+    larger ones to a kernel that sums each by a wave.  A 64x64 view of the whole
     sphere octree gives most leaves a few rows and another through a 4 degree
     field gives the few leaves it sees hundreds.  Against the oracle:
     the adjoint's gradients (its own counting pass), and the fused RMSProp /
@@ -248,7 +248,7 @@ def test_heavy_and_light_buckets_in_the_block_reduction(optimizer):
     rec = torch.empty(core.Octree.records_bytes(n, 96), dtype=torch.uint8, device="cuda")
     rgb, ns, cnt = tree.render_train(rays, t_stop=0.0, records=rec)
     m = cnt.sum(0).cpu().numpy().astype(np.int64)
-    assert (m > 32).sum() >= 16 and ((m > 0) & (m <= 32)).sum() >= 1000 and m.sum() < 32 * Ln
+    assert (m > 64).sum() >= 16 and ((m > 0) & (m <= 64)).sum() >= 1000 and m.sum() < 32 * Ln
     T = O.OracleTree.from_scene(s, sigma=s.sigma.astype(np.float64))
     rs, rh = O.backward(T, o, d, g.astype(np.float32).astype(np.float64), t_stop=0.0)
     if optimizer == "none":
