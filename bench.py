@@ -370,6 +370,7 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
         log(f"render {storage}: plain {kp * 1e3:.3f} ms ({mp:.1f} Mrays/s), with fused signal {kf * 1e3:.3f} ms "
             f"({mf:.1f} Mrays/s)")
     res.update(palette_render(torch, core, scene, rays, base, args))
+    res["atomic_count"] = atomic_count_rate(torch)
     res.update(train_step(torch, core, synth, args))
     if args.alg1_epochs > 0:
         res.update(alg1_loop(torch, core, synth, scene, args))
@@ -378,6 +379,32 @@ def measure_extra(torch, core, synth, scene, cams, tree_f32, args):
     if not args.no_terrain:
         res.update(terrain_precision(torch, core, synth, args))
     return res
+
+
+def atomic_count_rate(torch):
+    """Device-wide 32-bit atomic increments per second (dot_atomic_count): 2^24
+    of them spread by a hash over 2^20 counters, over the 3,536,632 leaves of
+    the torus+box tree and over the 8,632 of the sphere tree, each with the
+    returned values unused and used (the training forward's counts and its
+    slot reservations)."""
+    import ctypes as C
+    from paper_2307_15333_amd import _lib as L, core
+    lib = L.load()
+    n = 1 << 24
+    out = {}
+    for label, k in (("2^20 counters", 1 << 20), ("3536632 counters", 3536632), ("8632 counters", 8632)):
+        cnt = torch.zeros(k, dtype=torch.int32, device="cuda")
+        r = {}
+        for ret in (0, 1):
+            def fn():
+                L.check(lib.dot_atomic_count(C.c_void_p(cnt.data_ptr()), C.c_uint32(k), C.c_int64(n), ret,
+                                             core._stream()))
+            r["returning" if ret else "plain"] = round(n / time_kernel(fn, 10, torch) / 1e9, 2)
+        out[label] = r
+    log(f"atomic increments, G/s (plain / returning): " +
+        ", ".join(f"{lb} {v['plain']} / {v['returning']}" for lb, v in out.items()))
+    out["unit"] = "G atomic increments/s"
+    return out
 
 
 def palette_render(torch, core, scene, rays, base_mrays, args):

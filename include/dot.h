@@ -660,6 +660,18 @@ int dot_stream_read(const void *buf, size_t bytes, float *sink, void *stream);
  */
 int dot_gather_rows(const void *buf, int64_t n_rows, int64_t reads, float *sink, void *stream);
 
+/*
+ * dot_atomic_count -- support kernel, not part of the method: n device-wide
+ *  32-bit atomic increments, the i-th to counter (64-bit mix of i) mod
+ *  n_counters of the DEVICE array `counters` (added to, not cleared); with
+ *  `returning` nonzero each increment's returned value is used.  The pattern
+ *  of the training forward's per-leaf segment counts (and its slot
+ *  reservations) without the rest of its work: the rate it cannot exceed.  The
+ *  caller times the call; afterwards the counters have grown by n in total.
+ *  Errors: DOT_EINVAL for n < 0, or n > 0 with NULL counters or n_counters 0.
+ */
+int dot_atomic_count(uint32_t *counters, uint32_t n_counters, int64_t n, int returning, void *stream);
+
 /* dot_last_error -- message of the last failure on this thread ("" if none). */
 const char *dot_last_error(void);
 

@@ -146,6 +146,7 @@ SIGNATURES = {
     "dot_serve_close": (C.c_int, [C.c_void_p]),
     "dot_stream_read": (C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "dot_gather_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "dot_atomic_count": (C.c_int, [C.c_void_p, C.c_uint32, C.c_int64, C.c_int, C.c_void_p]),
     "dot_last_error": (C.c_char_p, []),
 }
 

@@ -13,6 +13,7 @@ namespace dot {
 
 // the gather probe's launcher (probe.hip)
 hipError_t launch_gather_rows(const void* buf, int64_t n_rows_pow2, int64_t reads, float* sink, hipStream_t s);
+hipError_t launch_atomic_count(uint32_t* counters, uint32_t n_counters, int64_t n, bool returning, hipStream_t s);
 
 static thread_local std::string g_err;
 
@@ -829,6 +830,14 @@ int dot_gather_rows(const void* buf, int64_t n_rows, int64_t reads, float* sink,
     if (reinterpret_cast<uintptr_t>(buf) % 16 != 0) return fail(DOT_EINVAL, "dot_gather_rows: buffer not 16-byte aligned");
     const hipError_t e = dot::launch_gather_rows(buf, n_rows, reads, sink, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "dot_gather_rows: launch");
+    return DOT_OK;
+}
+
+int dot_atomic_count(uint32_t* counters, uint32_t n_counters, int64_t n, int returning, void* stream) {
+    if (n < 0) return fail(DOT_EINVAL, "dot_atomic_count: n < 0");
+    if (n > 0 && (!counters || n_counters == 0)) return fail(DOT_EINVAL, "dot_atomic_count: NULL or no counters");
+    const hipError_t e = dot::launch_atomic_count(counters, n_counters, n, returning != 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dot_atomic_count: launch");
     return DOT_OK;
 }
 

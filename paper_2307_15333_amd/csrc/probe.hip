@@ -1,5 +1,7 @@
-// Streaming-read probe: the achievable HBM read bandwidth of the device, the
-// ceiling that sits beside the 8 TB/s specification in the renderer's roofline.
+// Device probes: the achievable HBM read bandwidth (streaming and random
+// rows), the ceilings beside the 8 TB/s specification in the renderer's
+// roofline, and the device-wide atomic rate that bounds the training
+// forward's per-leaf counting.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,7 +64,38 @@ __global__ __launch_bounds__(256) void k_gather_rows(const v4u* __restrict__ p, 
     if ((threadIdx.x & 63) == 0 && acc == 0x7fc00001u) atomicAdd(sink, 1.f);   // practically never taken
 }
 
+// Atomic probe: n device-wide 32-bit increments, the i-th to counter
+// mix64(i) mod K, the access pattern of the training forward's per-leaf
+// segment counts without its other work; with `ret` the returned values are
+// folded into a register (as the forward's slot reservations use theirs).
+__global__ __launch_bounds__(256) void k_atomic_count(uint32_t* __restrict__ c, uint32_t K, int64_t n, int ret) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t k = (uint32_t)(mix64((uint64_t)i) % K);
+        if (ret)
+            acc += atomicAdd(&c[k], 1u);
+        else
+            atomicAdd(&c[k], 1u);
+    }
+    if (ret && acc == 0x7fc00001u) atomicAdd(&c[0], 0u);   // keeps the returned values live; adds nothing
+}
+
 }  // namespace
+
+hipError_t launch_atomic_count(uint32_t* counters, uint32_t n_counters, int64_t n, bool returning, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)cus * 8);
+    hipLaunchKernelGGL(k_atomic_count, dim3((unsigned)blocks), dim3(256), 0, s, counters, n_counters, n,
+                       returning ? 1 : 0);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather_rows(const void* buf, int64_t n_rows_pow2, int64_t reads, float* sink, hipStream_t s) {
     if (n_rows_pow2 <= 0 || reads <= 0) return hipSuccess;

@@ -175,6 +175,10 @@ def test_batch_and_loss_argument_checks_need_no_device():
     assert lib.dot_gather_rows(None, 3, 10, None, None) == L.DOT_EINVAL
     assert b"power of two" in lib.dot_last_error()
     assert lib.dot_gather_rows(None, 4, 10, None, None) == L.DOT_EINVAL
+    assert lib.dot_atomic_count(None, 8, -1, 0, None) == L.DOT_EINVAL
+    assert lib.dot_atomic_count(None, 8, 5, 1, None) == L.DOT_EINVAL
+    assert lib.dot_atomic_count(16, 0, 5, 0, None) == L.DOT_EINVAL
+    assert lib.dot_atomic_count(None, 0, 0, 0, None) == L.DOT_OK
     assert lib.dot_pixel_batch(None, -1, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
     assert lib.dot_pixel_batch(None, 4, 0, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL
     assert lib.dot_pixel_batch(None, 4, 4, 4, 1, None, None, None, None, 0, None) == L.DOT_EINVAL

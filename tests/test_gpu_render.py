@@ -274,3 +274,11 @@ def test_stream_read_probe():
     torch.cuda.synchronize()
     assert lib.dot_gather_rows(C.c_void_p(buf.data_ptr()), C.c_int64(3), C.c_int64(5), C.c_void_p(sink.data_ptr()),
                                None) == L.DOT_EINVAL
+    # the atomic probe: every increment lands (plain and returning), on few and on many counters
+    for k in (7, 1 << 16):
+        cnt = torch.zeros(k, dtype=torch.int32, device="cuda")
+        L.check(lib.dot_atomic_count(C.c_void_p(cnt.data_ptr()), C.c_uint32(k), C.c_int64(300001), 0, None))
+        L.check(lib.dot_atomic_count(C.c_void_p(cnt.data_ptr()), C.c_uint32(k), C.c_int64(200000), 1, None))
+        torch.cuda.synchronize()
+        c = cnt.cpu().numpy().astype(np.int64)
+        assert c.sum() == 500001 and (c >= 0).all() and (k > 1000 or (c > 0).all())

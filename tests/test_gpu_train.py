@@ -222,8 +222,8 @@ def test_fused_backward_rmsprop_matches_oracle(degree):
     tree.close()
 
 
-@pytest.mark.parametrize("optimizer", ["none", "rmsprop", "adam"])
-def test_heavy_and_light_buckets_in_the_block_reduction(optimizer):
+@pytest.mark.parametrize("optimizer,degree", [("none", 2), ("rmsprop", 2), ("adam", 2), ("none", 0), ("rmsprop", 3)])
+def test_heavy_and_light_buckets_in_the_block_reduction(optimizer, degree):
     """The block reductions (chosen when a batch brings fewer than 32 rows per
     leaf on average) sum buckets of up to 64 rows one thread per leaf and leave
     larger ones to a kernel that sums each by a wave.  A 64x64 view of the whole
@@ -231,9 +231,11 @@ def test_heavy_and_light_buckets_in_the_block_reduction(optimizer):
     field gives the few leaves it sees hundreds.  Against the oracle:
     the adjoint's gradients (its own counting pass), and the fused RMSProp /
     Adam steps replaying the training forward's records (eps = 1e-4, as in the
-    fused tests above)."""
+    fused tests above); the sphere octree of config 1 at SH degree 2, and the
+    same tree at degrees 0 and 3."""
     core = _core()
-    s = synth.sphere_scene()
+    s = synth.sphere_scene() if degree == 2 else synth.make_scene(synth.sdf_sphere(0.5), max_depth=5, degree=degree,
+                                                                   seed=0)
     cams = np.concatenate([synth.cameras([(30.0, 20.0, 4.0, 64, 64)]),
                            np.atleast_1d(synth.look_at_camera(30.0, 20.0, 4.0, 64, 64, fov_deg=4.0))])
     ci = np.repeat(np.arange(2, dtype=np.int32), 64 * 64)
