@@ -697,9 +697,9 @@ __device__ __forceinline__ void bucket_sum_wave(const float4* __restrict__ p, ui
 }
 
 // Buckets of more rows than this are left out of the thread-per-leaf sums and
-// reduced at the end of the kernel by the whole wave of the thread that owns
-// the leaf: a thread-per-leaf sum would keep the block waiting on its longest
-// bucket (a few leaves of a large batch collect thousands of rows).
+// reduced a wave per leaf by bwd_heavy_kernel: a thread-per-leaf sum would keep
+// the block waiting on its longest bucket (a few leaves of a large batch
+// collect thousands of rows).
 constexpr uint32_t kLightRows = 64;
 
 // Rows of the bucket of leaf l (0 for l >= L) and, for a light bucket, its sums
