@@ -8,8 +8,10 @@ once; beside them the counter traffic of the same launch kind and the two
 measured ceilings, streaming reads and random 192-byte row gathers), the same
 frame with the fused max-weight signal (its buffer cleared in every step), the
 FP64 CPU oracle as a baseline, and the other measured forms of the hot path
-(FP16/BF16/palette leaves, the differentiable training step, Alg. 1 epochs,
-refinement, serving latency on the persistent launch and on relaunches).
+(FP16/BF16/palette leaves, the device-wide atomic rate that bounds the
+training forward's counting, the differentiable training step, Alg. 1
+epochs, refinement, serving latency on the persistent launch and on
+relaunches).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
