@@ -840,19 +840,18 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_reduce_kernel(int64_t L, const 
     }
 }
 
-// The optimiser step on channel ch of a block's nl leaves, whose SH sums sit
-// in stage (K per leaf, padded to KP).  Item i = (leaf r, run q) covers W
-// consecutive columns (W = 4: float4 accesses, when K % 4 == 0 and the planes
-// are 16-byte aligned).  hit[r] = 0 marks a leaf with an empty bucket (g = 0):
+// The optimiser step on columns [ch K, ch K + K) of a block's nl leaves (rows
+// of NV), whose SH sums sit in stage (K per leaf, padded to KP).  Item i =
+// (leaf r, run q) covers W consecutive columns (W = 4: float4 accesses, when
+// K % 4 == 0 and the planes are 16-byte aligned).  hit[r] = 0 marks a leaf with an empty bucket (g = 0):
 // RMSProp then leaves its values exactly as they are (lr 0 / (sqrt(v) + eps)
 // = 0) and only decays the square average, so the values are neither read
 // nor written; Adam still moves such a leaf by its first moment.  hit[r] = 2
 // marks a heavy bucket, whose leaf bwd_heavy_kernel updates.
-template <int K, int W, int OPT>
+template <int K, int NV, int W, int OPT>
 __device__ __forceinline__ void fused_channel(int64_t l0, int nl, int ch, const float* stage, const int* hit,
                                               float* __restrict__ sh, int stride, const FusedOpt& o) {
     constexpr int KP = K + 1;
-    constexpr int NV = 3 * K;
     constexpr int Q = K / W;
     static_assert(K % W == 0, "runs tile the channel");
     struct alignas(4 * W) Run {
@@ -917,9 +916,11 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const u
                                                               const float* __restrict__ rows,
                                                               float* __restrict__ sigma, float* __restrict__ sh,
                                                               int stride, FusedOpt o) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr int NV = 3 * K;
-    constexpr int KP = K + 1;
+    constexpr int NV = 3 * (DEG + 1) * (DEG + 1);
+    // the sums of all 3K columns staged at once, so every row of the state is
+    // swept in one pass (per channel, the half-lines a row shares with the
+    // next channel were fetched again once the L2 had dropped them)
+    constexpr int KC = NV, KP = KC + 1;
     __shared__ float stage[RED_BLOCK * KP];
     __shared__ int hit[RED_BLOCK];
     const int64_t l0 = (int64_t)blockIdx.x * RED_BLOCK;
@@ -940,13 +941,9 @@ __global__ __launch_bounds__(RED_BLOCK) void bwd_fused_kernel(int64_t L, const u
     }
     const int64_t nl = L - l0 < RED_BLOCK ? L - l0 : RED_BLOCK;
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        if (ch) __syncthreads();
-#pragma unroll
-        for (int k = 0; k < K; ++k) stage[threadIdx.x * KP + k] = acc[ch * K + k];
-        __syncthreads();
-        fused_channel<K, W, OPT>(l0, (int)nl, ch, stage, hit, sh, stride, o);
-    }
+    for (int k = 0; k < KC; ++k) stage[threadIdx.x * KP + k] = acc[k];
+    __syncthreads();
+    fused_channel<KC, NV, W, OPT>(l0, (int)nl, 0, stage, hit, sh, stride, o);
 }
 
 // Heavy buckets on average (many rows per leaf, e.g. a small tree under a
