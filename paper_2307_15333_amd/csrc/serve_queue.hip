@@ -24,8 +24,9 @@
 // device-scope (written-through) stores, and a wave waits for its stores to
 // complete before it counts the tiles done; only the job's last tile issues a
 // release (system scope, for the host).  Runs of several tiles save claims:
-// a job is cut into about four runs per wave of an XCD (a lone job's tail, its
-// last round of runs, stays short).
+// a job is cut into about four runs per wave of an XCD, eight if it is the
+// only job in flight when admitted (a lone job's tail, its last round of runs,
+// stays short; under load the longer runs keep claims few).
 //
 // Polls are device-coherent loads, served beyond the L2; waves that find no
 // work back off (up to about 13 us between polls) so that thousands of idle
@@ -184,6 +185,7 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
             const uint64_t free_lanes = __ballot(slot < 0);
             if (free_lanes == 0) break;
             const int fl = __ffsll((unsigned long long)free_lanes) - 1;
+            const bool alone = __popcll(~free_lanes) == 0;     // no other job in flight
             const int js = (int)(copied % (uint64_t)max_jobs);
             const uint32_t* src = reinterpret_cast<const uint32_t*>(hjobs + js);
             uint32_t* dst = reinterpret_cast<uint32_t*>(dv.jobs + js);
@@ -201,9 +203,9 @@ __device__ void feeder(ServeHostCtl* ctl, const ServeJob* hjobs, const ServeDevi
                 begin = b0;
                 count = c0;
                 chunk = (c0 + kRings - 1) / kRings;
-                // about four runs per wave of the XCD for a lone job, so that
-                // its last round of runs is short
-                run = chunk / (4 * ring_waves);
+                // about four runs per wave of the XCD (eight for a job alone in
+                // the queue), so that the last round of runs is short
+                run = chunk / ((alone ? 8 : 4) * ring_waves);
                 run = run < kMinRun ? kMinRun : (run > kMaxRun ? kMaxRun : run);
                 for (int x = 0; x < kRings; ++x) cur[x] = 0;
             }
